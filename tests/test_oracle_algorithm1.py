@@ -1,0 +1,173 @@
+"""Pins for the oracle's Algorithm 1 (Section 3.2) against closed forms, invariants and
+an independent solver."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import algorithm1 as A1
+from oracle import metrics, theory
+from workloads import scaled_dense, scaled_sparse
+
+
+def _diag_fixed_point(a, gamma):
+    """Diagonal A, m = n, alpha = beta = 1: by symmetry u = v = x with a^2 e^(4x) = 1 - gamma x,
+    i.e. x = (1 - q)/gamma with q = (gamma/4) W((4 a^2/gamma) e^(4/gamma))."""
+    q = (gamma / 4.0) * theory.lambertw_exp(np.log(4.0 * a**2 / gamma) + 4.0 / gamma)
+    return (1.0 - q) / gamma
+
+
+A_DIAG = np.array([0.01, 0.3, 1.0, 2.0, 50.0, 1e3])
+
+
+def test_diagonal_matrix_reaches_closed_form_fixed_point():
+    """With one nonzero per row and column the estimate does not depend on the signs,
+    so Algorithm 1 is projected gradient descent and its iterate converges to the
+    exact regularised optimum (first-order condition of Section 3.1 solved with Lambert W)."""
+    xs = _diag_fixed_point(A_DIAG, 0.1)
+    out = A1.equilibrate(np.diag(A_DIAG), 1.0, 1.0, 0.1, 10.0, 1000, k=1, seed=1)
+    assert np.max(np.abs(out["u"] - xs)) < 1e-12
+    assert np.max(np.abs(out["v"] - xs)) < 1e-12
+    # the weighted average converges too (O(1/T^2) here)
+    assert np.max(np.abs(out["u_bar"] - xs)) < 3e-3
+    out2 = A1.equilibrate(np.diag(A_DIAG), 1.0, 1.0, 0.1, 10.0, 5000, k=1, seed=1)
+    assert np.max(np.abs(out2["u_bar"] - xs)) < 1.5e-4
+    g = theory.gradient(np.diag(A_DIAG), xs, xs, 1.0, 1.0, 0.1)
+    assert np.max(np.abs(g[0])) < 1e-12
+
+
+def test_diagonal_is_sign_independent():
+    a = A_DIAG
+    o1 = A1.equilibrate(np.diag(a), 1.0, 1.0, 0.1, 10.0, 200, k=1, seed=1)
+    o2 = A1.equilibrate(sp.csr_matrix(np.diag(a)), 1.0, 1.0, 0.1, 10.0, 200, k=4, seed=77)
+    assert np.allclose(o1["u_bar"], o2["u_bar"], rtol=0, atol=1e-13)
+
+
+def test_permuted_diagonal_matches_diagonal():
+    """A permutation of rows only relabels the problem."""
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    P = np.eye(6)[perm]
+    o1 = A1.equilibrate(np.diag(A_DIAG), 1.0, 1.0, 0.1, 10.0, 300, seed=3)
+    o2 = A1.equilibrate(P @ np.diag(A_DIAG), 1.0, 1.0, 0.1, 10.0, 300, seed=4)
+    assert np.allclose(o2["u_bar"], o1["u_bar"][perm], atol=1e-13)
+    assert np.allclose(o2["v_bar"], o1["v_bar"], atol=1e-13)
+
+
+def test_box_active_fixed_point():
+    """Tiny entries push the optimum past the box: the projection pins u = v = M... or the
+    iterate bound alpha^2/gamma, whichever is smaller."""
+    a = np.array([1e-12, 1e-9])
+    M = 3.0
+    out = A1.equilibrate(np.diag(a), 1.0, 1.0, 0.1, M, 100, seed=1)
+    assert np.allclose(out["u"], M) and np.allclose(out["v"], M)
+
+
+def test_empty_row_closed_form():
+    """A zero row has z = 0: u^1 = alpha^2/gamma exactly (eta_1 gamma = 1) and it stays there,
+    so u_bar = (1 - 2/((T+1)(T+2))) alpha^2/gamma (the closed-form average weights)."""
+    A = scaled_dense(5, 4, 1.0, 11)
+    A[2, :] = 0.0
+    al, be = A1.default_alpha_beta(5, 4)
+    T = 50
+    out = A1.equilibrate(A, al, be, 0.1, 10.0, T, seed=5)
+    assert out["u"][2] == pytest.approx(al**2 / 0.1, rel=1e-15)
+    assert out["u_bar"][2] == pytest.approx((1 - 2 / ((T + 1) * (T + 2))) * al**2 / 0.1, rel=1e-14)
+
+
+def test_running_average_equals_closed_form_weights():
+    """u_bar after T steps = sum_t 2(t+1)/((T+1)(T+2)) u^t, t = 0..T (Section 3.2)."""
+    A = scaled_sparse(40, 30, 4, 1.0, 12).to_scipy()
+    al, be = A1.default_alpha_beta(40, 30)
+    us = [np.zeros(40)]
+    T = 37
+    out = A1.equilibrate(A, al, be, 0.1, 10.0, T, k=2, seed=3,
+                         on_step=lambda t, u, v, ub, vb: us.append(u.copy()))
+    w = np.array([2.0 * (t + 1) / ((T + 1) * (T + 2)) for t in range(T + 1)])
+    assert w.sum() == pytest.approx(1.0, rel=1e-15)
+    assert np.allclose(out["u_bar"], np.tensordot(w, np.array(us), axes=1), rtol=0, atol=1e-12)
+
+
+def test_iterate_bounds_hold_every_step():
+    """u^t <= alpha^2/gamma, v^t <= beta^2/gamma (Section 3.2) and |u|, |v| <= M."""
+    A = scaled_sparse(60, 30, 5, 2.0, 13).to_scipy()
+    al, be = A1.default_alpha_beta(60, 30)
+    ga, M = 0.1, 10.0
+    bad = []
+
+    def chk(t, u, v, ub, vb):
+        if u.max() > al**2 / ga + 1e-12 or v.max() > be**2 / ga + 1e-12:
+            bad.append(t)
+        if np.abs(u).max() > M or np.abs(v).max() > M:
+            bad.append(-t)
+
+    A1.equilibrate(A, al, be, ga, M, 300, k=3, seed=9, on_step=chk)
+    assert bad == []
+
+
+def test_converges_to_newton_optimum():
+    """The relative optimality gap (Section 4) of u_bar shrinks with T towards p*
+    computed by Newton's method (box inactive at the optimum)."""
+    A = scaled_dense(30, 20, 1.0, 14)
+    al, be = A1.default_alpha_beta(30, 20)
+    ga, M = 0.1, 10.0
+    us, vs, _ = theory.newton_regularized(A, al, be, ga)
+    assert np.abs(us).max() < M and np.abs(vs).max() < M
+    p = theory.objective(A, us, vs, al, be, ga)
+    gaps = []
+    for T in (10, 100, 1000):
+        o = A1.equilibrate(A, al, be, ga, M, T, k=1, seed=21)
+        gaps.append(metrics.relative_gap(A, o["u_bar"], o["v_bar"], al, be, ga, p))
+    assert all(g >= -1e-12 for g in gaps)
+    assert gaps[2] < gaps[1] < gaps[0]
+    assert gaps[2] < 1e-3
+
+
+def test_orthogonal_matrix_optimum_is_zero():
+    """For orthogonal A with alpha = beta = 1 the gradient vanishes at (0, 0); SGD output
+    stays near 0."""
+    Q, _ = np.linalg.qr(np.random.default_rng(15).standard_normal((12, 12)))
+    g = theory.gradient(Q, np.zeros(12), np.zeros(12), 1.0, 1.0, 0.1)
+    assert np.max(np.abs(g[0])) < 1e-14 and np.max(np.abs(g[1])) < 1e-14
+    o = A1.equilibrate(Q, 1.0, 1.0, 0.1, 10.0, 2000, k=4, seed=2)
+    assert np.max(np.abs(o["u_bar"])) < 0.1
+    assert abs(o["u_bar"].mean()) < 0.02
+
+
+def test_warm_start_with_offset_keeps_fixed_point():
+    """Warm start at the exact fixed point of a diagonal problem with t0 > 0 stays there."""
+    xs = _diag_fixed_point(A_DIAG, 0.1)
+    o = A1.equilibrate(np.diag(A_DIAG), 1.0, 1.0, 0.1, 10.0, 20, seed=1, t0=50, u0=xs, v0=xs)
+    assert np.max(np.abs(o["u_bar"] - xs)) < 1e-12
+
+
+def test_first_step_erases_warm_start_without_offset():
+    """With t0 = 0, eta_1 gamma = 1, so u^1 depends on u^0 only through the estimate z."""
+    A = np.diag([0.0, 0.0, 1.0])
+    o = A1.equilibrate(A, 1.0, 1.0, 0.1, 10.0, 1, seed=1, u0=np.array([5.0, -3.0, 0.0]),
+                       v0=np.zeros(3))
+    assert o["u"][0] == pytest.approx(10.0) and o["u"][1] == pytest.approx(10.0)
+
+
+def test_nonfinite_detected():
+    A = scaled_dense(4, 3, 1.0, 16)
+    A[1, 2] = np.nan
+    with pytest.raises(A1.NonFiniteError):
+        A1.equilibrate(A, 1.0, 1.0, 0.1, 10.0, 3, seed=1)
+
+
+def test_parameter_validation():
+    A = np.eye(3)
+    for bad in [dict(alpha=0), dict(beta=-1), dict(gamma=0), dict(M=0)]:
+        kw = dict(alpha=1.0, beta=1.0, gamma=0.1, M=1.0)
+        kw.update(bad)
+        with pytest.raises(ValueError):
+            A1.equilibrate(A, kw["alpha"], kw["beta"], kw["gamma"], kw["M"], 3)
+    out = A1.equilibrate(A, 1.0, 1.0, 0.1, 1.0, 0, u0=np.ones(3))
+    assert np.array_equal(out["d"], np.exp(np.ones(3)))
+
+
+def test_default_alpha_beta_invariant():
+    """m alpha^2 = n beta^2 (Section 1) and alpha beta = 1 for the Section 4 choice."""
+    for m, n in [(200, 100), (10**6, 5 * 10**5), (7, 13)]:
+        al, be = A1.default_alpha_beta(m, n)
+        assert m * al**2 == pytest.approx(n * be**2, rel=1e-14)
+        assert al * be == pytest.approx(1.0, rel=1e-14)
