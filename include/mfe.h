@@ -1,0 +1,189 @@
+/*
+ * mfe.h -- stochastic matrix-free equilibration on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libmfe.so.  The library finds diagonal D = diag(e^u), E = diag(e^v) that
+ * approximately equilibrate A (rows of DAE with 2-norm alpha, columns with 2-norm
+ * beta) by projected stochastic gradient descent on the regularised, box-constrained
+ * convex problem of Diamond & Boyd, "Stochastic Matrix-Free Equilibration":
+ *
+ *   minimise  (1/2) sum_ij A_ij^2 e^(2u_i + 2v_j) - alpha^2 1'u - beta^2 1'v
+ *             + (gamma/2) ||(u, v)||^2      subject to ||u||_inf <= M, ||v||_inf <= M
+ *
+ * (problem (prob:reg-constr-equil), Section 2.3), solved by Algorithm 1 (Section 3.2):
+ * at step t, with Rademacher probe blocks S (n x k) and W (m x k),
+ *   z_u = e^(2u) * mean_p (A E S)_{:,p}^2,   z_v = e^(2v) * mean_p (A' D W)_{:,p}^2
+ *   u  <- clip(u - eta_t (z_u - alpha^2 + gamma u), -M, M)     (v likewise with beta)
+ *   u_bar <- 2u/(tau+2) + tau u_bar/(tau+2),  eta_t = 2/(gamma (tau+1)),  tau = t + t0,
+ * both updates from the previous iterate (Jacobi order).  Outputs d = e^u_bar, e = e^v_bar.
+ * lsqr() is the downstream consumer of Section 5.1: LSQR on (DAE) xbar = D b, x = E xbar.
+ *
+ * General conventions
+ *  - Every call returns an mfe_status; nothing aborts or throws across the ABI.  On a
+ *    non-OK status the outputs are unspecified and mfe_last_error() describes the cause.
+ *  - "device" pointers are HIP device allocations on the current device; "host"
+ *    pointers are ordinary CPU memory.  The caller owns every pointer it passes; the
+ *    library never frees caller memory.  Workspaces are library-owned and released
+ *    before the call returns, or when the owning plan is destroyed.
+ *  - Work is ordered on the HIP stream given in the parameters (NULL = default
+ *    stream).  Calls that report a status synchronise that stream once at the end.
+ *  - Probe signs are bit-exact and reproducible: probe p of index i at step t is bit
+ *    i*k + p of the Philox4x64-10 stream with key (seed, (batch << 34) | (t << 2) | side),
+ *    block c evaluated at counter (c+1, 0, 0, 0), 256 bits per block, bit q of a block
+ *    = bit (q mod 64) of output word q div 64; bit 1 means -1.  side 0 = s (indexed by
+ *    column j), side 1 = w (indexed by row i).  Section 3.1 only asks for iid fair signs.
+ *  - Results are deterministic run to run (no floating-point atomics on any path).
+ */
+#ifndef MFE_H
+#define MFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFE_OK = 0,
+  MFE_EINVAL = -1,       /* invalid parameter value or NULL where a pointer is required */
+  MFE_EDIM = -2,         /* inconsistent or unsupported dimensions (e.g. nnz >= 2^31) */
+  MFE_ENONFINITE = -3,   /* a gradient estimate or iterate became NaN/Inf (e.g. NaN in A) */
+  MFE_EDEVICE = -4,      /* a HIP runtime call failed */
+  MFE_ENOMEM = -5,       /* device allocation failed */
+  MFE_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} mfe_status;
+
+typedef enum {
+  MFE_DENSE_F64 = 0,   /* dense row-major FP64: data (device), ld >= n */
+  MFE_DENSE_BF16 = 1,  /* dense row-major bfloat16 bit patterns (uint16): data (device), ld >= n */
+  MFE_CSR_F32 = 2,     /* CSR: row_ptr int32[m+1], col_idx int32[nnz], val float[nnz] (device);
+                          column indices within a row sorted ascending and unique */
+  MFE_OPERATOR = 3     /* matrix-free: only apply() is used */
+} mfe_kind;
+
+/* Matrix-free operator (the setting of Section 3): Y = A X (trans = 0, X is n x k,
+ * Y is m x k) or Y = A' X (trans = 1, X is m x k, Y is n x k).  Row-major blocks:
+ * element (i, p) at X[i*ldx + p].  FP32, device pointers, work ordered on `stream`
+ * (a hipStream_t).  Returns 0 on success; any other value aborts the run with
+ * MFE_EDEVICE. */
+typedef int (*mfe_apply_fn)(void* ctx, int trans, int32_t k, const float* X, int64_t ldx,
+                            float* Y, int64_t ldy, void* stream);
+
+typedef struct {
+  int32_t kind;               /* mfe_kind */
+  int64_t m, n;               /* rows, columns (> 0) */
+  const void* data;           /* dense kinds */
+  int64_t ld;                 /* dense leading dimension (elements) */
+  int64_t nnz;                /* CSR */
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const float* val;
+  mfe_apply_fn apply;         /* operator kind */
+  void* ctx;
+} mfe_matrix;
+
+typedef struct {
+  double alpha, beta;   /* target row / column norms (> 0); see mfe_default_alpha_beta */
+  double gamma;         /* regularisation (> 0); the paper's experiments use 0.1 */
+  double box_M;         /* box bound M (> 0): |u_i|, |v_j| <= M */
+  int32_t steps;        /* T >= 0; T = 0 returns d = e^u0, e = e^v0 */
+  int32_t probes;       /* k probes per step, 1..256 (k = 1 is Algorithm 1 verbatim) */
+  uint64_t seed;        /* probe stream seed */
+  int32_t t0;           /* step offset >= 0 (0 = Algorithm 1); tau = t + t0 */
+  int32_t batch;        /* batch index b of the sign stream (0 for a single matrix) */
+  const double* u0;     /* device [m] warm start, or NULL for 0 */
+  const double* v0;     /* device [n] warm start, or NULL for 0 */
+  void* stream;         /* hipStream_t, NULL = default stream */
+} mfe_equil_params;
+
+typedef struct {
+  int32_t iters;           /* iterations run */
+  int32_t stop_reason;     /* 0 max_iter, 1 ||Ax-b||/||b|| <= tol, 2 normal-equation test, 3 breakdown */
+  double rel_resid;        /* ||A x - b|| / ||b|| of the original system at the last check */
+  double normal_eq;        /* ||Abar' rbar|| / (||Abar|| ||rbar||) estimate at the last check */
+} mfe_lsqr_info;
+
+typedef struct mfe_plan mfe_plan;
+
+/* alpha = (n/m)^(1/4), beta = (m/n)^(1/4): the choice of Section 4, which satisfies
+ * m alpha^2 = n beta^2 (Section 1) and alpha beta = 1.  Host pointers.
+ * EINVAL if m <= 0, n <= 0 or an output is NULL. */
+int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta);
+
+/* Algorithm 1 on one matrix (any kind).  Outputs are device FP64 arrays:
+ * d [m] = e^u_bar, e [n] = e^v_bar (required); u_bar [m], v_bar [n] (nullable).
+ * CSR and dense kinds run fused HIP kernels; the operator kind calls apply() twice per
+ * step and runs the square/step/project update in the library's kernels.
+ * EINVAL: alpha, beta, gamma or M <= 0 or not finite; steps < 0; probes outside 1..256;
+ * t0 < 0; a required pointer NULL.  EDIM: m or n <= 0, nnz >= 2^31, ld < n.
+ * EUNSUPPORTED: CSR/dense with probes > 64, or a kind not built.
+ * ENONFINITE: a non-finite estimate or iterate occurred (the clip would hide a NaN). */
+int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
+                    double* u_bar, double* v_bar);
+
+/* Plans: preprocessing (CSR -> CSC transpose, sliced-ELL layouts for both products)
+ * done once and reused.  count >= 1 CSR matrices are equilibrated together in one
+ * launch per step (the batched path).
+ * max_probes bounds p->probes of later runs (1..64).  Only MFE_CSR_F32 is accepted. */
+int mfe_plan_create(const mfe_matrix* mats, int32_t count, int32_t max_probes, void* stream,
+                    mfe_plan** out);
+
+/* Run Algorithm 1 on every matrix of the plan.  Outputs are device FP64 arrays holding
+ * all matrices back to back in plan order: d [sum m], e [sum n], u_bar/v_bar nullable.
+ * alpha_b/beta_b: host arrays [count] of per-matrix targets, or NULL to use p->alpha,
+ * p->beta for every matrix.  Matrix b uses sign-stream batch index p->batch + b.
+ * p->u0 / p->v0, when set, are device [sum m] / [sum n].
+ * use_graph != 0 captures the T step launches in one HIP graph and replays it. */
+int mfe_plan_equilibrate(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b,
+                         const double* beta_b, int32_t use_graph, double* d, double* e,
+                         double* u_bar, double* v_bar);
+
+/* Timing of the last mfe_plan_equilibrate (host pointer): milliseconds spent in the
+ * step loop (HIP events around it) and in the step kernel alone per launch average. */
+int mfe_plan_last_timing(const mfe_plan* plan, double* loop_ms, double* step_kernel_ms);
+
+int mfe_plan_destroy(mfe_plan* plan);
+
+/* LSQR (Paige & Saunders) on (D A E) xbar = D b, x = E xbar (Section 5.1), FP64
+ * vectors and recurrences, A values FP32 (CSR) or FP64 (dense).  b [m], d [m], e [n]
+ * and x [n] are device FP64; d or e NULL means the identity.  Every check_every
+ * iterations (and at max_iter) the original residual ||A x - b|| / ||b|| is evaluated;
+ * the run stops when it is <= tol (reason 1) or when LSQR's normal-equation estimate is
+ * <= tol (reason 2).  info is a host pointer (nullable).  stream: hipStream_t or NULL.
+ * Only MFE_CSR_F32 and MFE_DENSE_F64 are accepted. */
+int mfe_lsqr(const mfe_matrix* A, const double* b, const double* d, const double* e,
+             double tol, int32_t max_iter, int32_t check_every, double* x,
+             mfe_lsqr_info* info, void* stream);
+
+/* Same on a single-matrix plan (reuses its preprocessing). */
+int mfe_plan_lsqr(mfe_plan* plan, const double* b, const double* d, const double* e,
+                  double tol, int32_t max_iter, int32_t check_every, double* x,
+                  mfe_lsqr_info* info, void* stream);
+
+/* RMS equilibration error of D A E (Section 4):
+ *   (1/sqrt(m+n)) sqrt( sum_i (||row_i(DAE)|| - alpha)^2 + sum_j (||col_j(DAE)|| - beta)^2 )
+ * evaluated exactly from the entries (one pass over each layout).  d [m], e [n] device
+ * FP64 (NULL = identity).  Host outputs: rms over all rows and columns; rms_nonempty over
+ * rows/columns of A with at least one stored entry; n_empty the number left out.
+ * Only MFE_CSR_F32 and MFE_DENSE_F64 are accepted. */
+int mfe_residual(const mfe_matrix* A, const double* d, const double* e, double alpha,
+                 double beta, double* rms, double* rms_nonempty, int64_t* n_empty,
+                 void* stream);
+
+/* Sign words of the probe stream (Section 3.1 probes, contract above): writes
+ * nwords 64-bit words starting at word 0 of the stream (seed, batch, step, side) into
+ * device memory `words`.  EINVAL for out-of-range batch (>= 2^30), step (>= 2^32),
+ * side (> 3) or NULL. */
+int mfe_draw_signs(uint64_t seed, int32_t batch, int64_t step, int32_t side, int64_t nwords,
+                   uint64_t* words, void* stream);
+
+/* Thread-local description of the last non-OK status (or a warning), never NULL. */
+const char* mfe_last_error(void);
+
+/* Library version string. */
+const char* mfe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFE_H */

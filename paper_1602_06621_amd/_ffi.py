@@ -1,0 +1,355 @@
+"""ctypes marshalling for libmfe.so (see include/mfe.h for the contract of each call)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+STATUS = {0: "MFE_OK", -1: "MFE_EINVAL", -2: "MFE_EDIM", -3: "MFE_ENONFINITE", -4: "MFE_EDEVICE",
+          -5: "MFE_ENOMEM", -6: "MFE_EUNSUPPORTED"}
+KIND = {"dense_f64": 0, "dense_bf16": 1, "csr_f32": 2, "operator": 3}
+
+
+class LibraryMissing(RuntimeError):
+    """libmfe.so is not built; there is no fallback implementation."""
+
+
+class MfeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                       C.c_int64, C.c_void_p)
+
+
+class _Matrix(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("m", C.c_int64), ("n", C.c_int64), ("data", C.c_void_p),
+                ("ld", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("val", C.c_void_p), ("apply", APPLY_FN), ("ctx", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double), ("box_M", C.c_double),
+                ("steps", C.c_int32), ("probes", C.c_int32), ("seed", C.c_uint64), ("t0", C.c_int32),
+                ("batch", C.c_int32), ("u0", C.c_void_p), ("v0", C.c_void_p), ("stream", C.c_void_p)]
+
+
+class _LsqrInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("stop_reason", C.c_int32), ("rel_resid", C.c_double),
+                ("normal_eq", C.c_double)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.environ.get("MFE_LIBRARY", os.path.join(_HERE, "libmfe.so"))
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} is not built; run __graft_entry__.build() or "
+                             "python paper_1602_06621_amd/build.py")
+    lib = C.CDLL(path)
+    i32, i64, u64, dbl, vp = C.c_int32, C.c_int64, C.c_uint64, C.c_double, C.c_void_p
+    sig = {
+        "mfe_default_alpha_beta": [i64, i64, C.POINTER(dbl), C.POINTER(dbl)],
+        "mfe_equilibrate": [C.POINTER(_Matrix), C.POINTER(_Params), vp, vp, vp, vp],
+        "mfe_plan_create": [C.POINTER(_Matrix), i32, i32, vp, C.POINTER(vp)],
+        "mfe_plan_equilibrate": [vp, C.POINTER(_Params), vp, vp, i32, vp, vp, vp, vp],
+        "mfe_plan_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl)],
+        "mfe_plan_destroy": [vp],
+        "mfe_lsqr": [C.POINTER(_Matrix), vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_LsqrInfo), vp],
+        "mfe_plan_lsqr": [vp, vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_LsqrInfo), vp],
+        "mfe_residual": [C.POINTER(_Matrix), vp, vp, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl),
+                         C.POINTER(i64), vp],
+        "mfe_draw_signs": [u64, i32, i64, i32, i64, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.mfe_last_error.restype = C.c_char_p
+    lib.mfe_last_error.argtypes = []
+    lib.mfe_version.restype = C.c_char_p
+    lib.mfe_version.argtypes = []
+    _LIB = lib
+    return lib
+
+
+def last_error() -> str:
+    return _lib().mfe_last_error().decode()
+
+
+def version() -> str:
+    return _lib().mfe_version().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise MfeError(status, last_error())
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+# --------------------------------------------------------------- matrices
+
+@dataclass
+class Csr:
+    """CSR matrix in device memory: row_ptr int32 [m+1], col_idx int32 [nnz], val float32 [nnz]."""
+
+    m: int
+    n: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @staticmethod
+    def from_arrays(m, n, row_ptr, col_idx, val, device="cuda") -> "Csr":
+        t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
+        return Csr(int(m), int(n), t(row_ptr, torch.int32), t(col_idx, torch.int32), t(val, torch.float32))
+
+    def struct(self) -> _Matrix:
+        s = _Matrix()
+        s.kind = KIND["csr_f32"]
+        s.m, s.n, s.nnz = self.m, self.n, self.nnz
+        s.row_ptr = _ptr(self.row_ptr, torch.int32, "row_ptr")
+        s.col_idx = _ptr(self.col_idx, torch.int32, "col_idx") if self.nnz else None
+        s.val = _ptr(self.val, torch.float32, "val") if self.nnz else None
+        return s
+
+
+@dataclass
+class Dense:
+    """Dense row-major matrix in device memory: float64, or bfloat16 bit patterns (int16/uint16)."""
+
+    data: torch.Tensor
+    ld: Optional[int] = None
+
+    @property
+    def m(self) -> int:
+        return int(self.data.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.data.shape[1])
+
+    def struct(self) -> _Matrix:
+        s = _Matrix()
+        if self.data.dtype == torch.float64:
+            s.kind = KIND["dense_f64"]
+        elif self.data.dtype in (torch.int16, torch.bfloat16) or str(self.data.dtype) == "torch.uint16":
+            s.kind = KIND["dense_bf16"]
+        else:
+            raise TypeError("dense data must be float64 or bfloat16 bit patterns")
+        s.m, s.n = self.m, self.n
+        s.ld = self.ld if self.ld is not None else self.data.stride(0)
+        if self.data.stride(1) != 1:
+            raise ValueError("dense data must be row-major with unit column stride")
+        s.data = C.c_void_p(self.data.data_ptr())
+        return s
+
+
+class Operator:
+    """Matrix-free operator: apply(trans, k, X, Y) fills the FP32 device block Y (row-major)
+    with A X (trans = 0) or A' X (trans = 1) on the current stream."""
+
+    def __init__(self, m: int, n: int, apply):
+        self.m, self.n = int(m), int(n)
+        self._apply = apply
+
+        def cb(ctx, trans, k, X, ldx, Y, ldy, stream):
+            try:
+                rows_in = self.m if trans else self.n
+                rows_out = self.n if trans else self.m
+                self._apply(int(trans), int(k), int(X or 0), int(ldx), int(Y or 0), int(ldy), rows_in, rows_out,
+                            int(stream or 0))
+                return 0
+            except Exception:  # errors are reported through the status code
+                return 1
+
+        self._cb = APPLY_FN(cb)
+
+    def struct(self) -> _Matrix:
+        s = _Matrix()
+        s.kind = KIND["operator"]
+        s.m, s.n = self.m, self.n
+        s.apply = self._cb
+        return s
+
+
+def _params(alpha, beta, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream) -> _Params:
+    p = _Params()
+    p.alpha, p.beta, p.gamma, p.box_M = float(alpha), float(beta), float(gamma), float(M)
+    p.steps, p.probes, p.seed = int(steps), int(probes), int(seed) & ((1 << 64) - 1)
+    p.t0, p.batch = int(t0), int(batch)
+    p.u0 = _ptr(u0, torch.float64, "u0")
+    p.v0 = _ptr(v0, torch.float64, "v0")
+    p.stream = _stream(stream)
+    return p
+
+
+def default_alpha_beta(m: int, n: int):
+    a, b = C.c_double(), C.c_double()
+    _check(_lib().mfe_default_alpha_beta(int(m), int(n), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def equilibrate(A, alpha=None, beta=None, gamma=0.1, M=10.0, steps=100, probes=1, seed=0, t0=0,
+                batch=0, u0=None, v0=None, stream=None, device="cuda"):
+    """Algorithm 1 on one matrix.  Returns dict(d, e, u_bar, v_bar) of float64 device tensors."""
+    lib = _lib()
+    if alpha is None or beta is None:
+        alpha, beta = default_alpha_beta(A.m, A.n)
+    d = torch.empty(A.m, dtype=torch.float64, device=device)
+    e = torch.empty(A.n, dtype=torch.float64, device=device)
+    ub = torch.empty_like(d)
+    vb = torch.empty_like(e)
+    s = A.struct()
+    p = _params(alpha, beta, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream)
+    _check(lib.mfe_equilibrate(C.byref(s), C.byref(p), _ptr(d), _ptr(e), _ptr(ub), _ptr(vb)))
+    return dict(d=d, e=e, u_bar=ub, v_bar=vb)
+
+
+class Plan:
+    """Preprocessed CSR matrices (one or a batch) for repeated equilibration / LSQR runs."""
+
+    def __init__(self, mats: Sequence[Csr], max_probes: int = 16, stream=None):
+        lib = _lib()
+        self.mats = list(mats)
+        arr = (_Matrix * len(self.mats))(*[m.struct() for m in self.mats])
+        h = C.c_void_p()
+        _check(lib.mfe_plan_create(arr, len(self.mats), int(max_probes), _stream(stream), C.byref(h)))
+        self._h = h
+        self.M = sum(m.m for m in self.mats)
+        self.N = sum(m.n for m in self.mats)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib().mfe_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def equilibrate(self, alpha=None, beta=None, gamma=0.1, M=10.0, steps=100, probes=1, seed=0, t0=0,
+                    batch=0, u0=None, v0=None, use_graph=False, stream=None, out=None, device="cuda"):
+        """alpha/beta: scalars for every matrix, per-matrix sequences, or None for the
+        default (n_b/m_b)^(1/4), (m_b/n_b)^(1/4) of each matrix."""
+        lib = _lib()
+        cnt = len(self.mats)
+        if alpha is None or beta is None:
+            ab = [default_alpha_beta(mm.m, mm.n) for mm in self.mats]
+            alpha = [a for a, _ in ab]
+            beta = [b for _, b in ab]
+        ah = bh = None
+        if not isinstance(alpha, (int, float)) or not isinstance(beta, (int, float)):
+            al = [float(alpha)] * cnt if isinstance(alpha, (int, float)) else [float(a) for a in alpha]
+            be = [float(beta)] * cnt if isinstance(beta, (int, float)) else [float(b) for b in beta]
+            ah = (C.c_double * cnt)(*al)
+            bh = (C.c_double * cnt)(*be)
+            a0, b0 = al[0], be[0]
+        else:
+            a0, b0 = alpha, beta
+        if out is None:
+            out = dict(d=torch.empty(self.M, dtype=torch.float64, device=device),
+                       e=torch.empty(self.N, dtype=torch.float64, device=device),
+                       u_bar=torch.empty(self.M, dtype=torch.float64, device=device),
+                       v_bar=torch.empty(self.N, dtype=torch.float64, device=device))
+        p = _params(a0, b0, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream)
+        _check(lib.mfe_plan_equilibrate(self._h, C.byref(p), ah, bh, int(bool(use_graph)), _ptr(out["d"]),
+                                        _ptr(out["e"]), _ptr(out.get("u_bar")), _ptr(out.get("v_bar"))))
+        return out
+
+    def last_timing(self):
+        a, b = C.c_double(), C.c_double()
+        _check(_lib().mfe_plan_last_timing(self._h, C.byref(a), C.byref(b)))
+        return dict(loop_ms=a.value, step_ms=b.value)
+
+    def lsqr(self, b, d=None, e=None, tol=1e-6, max_iter=1000, check_every=10, stream=None, device="cuda"):
+        x = torch.empty(self.N, dtype=torch.float64, device=device)
+        info = _LsqrInfo()
+        _check(_lib().mfe_plan_lsqr(self._h, _ptr(b, torch.float64, "b"), _ptr(d, torch.float64, "d"),
+                                    _ptr(e, torch.float64, "e"), float(tol), int(max_iter), int(check_every),
+                                    _ptr(x), C.byref(info), _stream(stream)))
+        return x, _info(info)
+
+
+def _info(info: _LsqrInfo):
+    return dict(iters=info.iters, stop_reason=info.stop_reason, rel_resid=info.rel_resid,
+                normal_eq=info.normal_eq)
+
+
+def lsqr(A, b, d=None, e=None, tol=1e-6, max_iter=1000, check_every=10, stream=None, device="cuda"):
+    """LSQR on (DAE) xbar = D b, x = E xbar (Section 5.1).  Returns (x, info)."""
+    x = torch.empty(A.n, dtype=torch.float64, device=device)
+    info = _LsqrInfo()
+    s = A.struct()
+    _check(_lib().mfe_lsqr(C.byref(s), _ptr(b, torch.float64, "b"), _ptr(d, torch.float64, "d"),
+                           _ptr(e, torch.float64, "e"), float(tol), int(max_iter), int(check_every), _ptr(x),
+                           C.byref(info), _stream(stream)))
+    return x, _info(info)
+
+
+def residual(A, d=None, e=None, alpha=None, beta=None, stream=None):
+    """RMS equilibration error of DAE (Section 4).  Returns (rms, rms_nonempty, n_empty)."""
+    if alpha is None or beta is None:
+        alpha, beta = default_alpha_beta(A.m, A.n)
+    r, rn, ne = C.c_double(), C.c_double(), C.c_int64()
+    s = A.struct()
+    _check(_lib().mfe_residual(C.byref(s), _ptr(d, torch.float64, "d"), _ptr(e, torch.float64, "e"),
+                               float(alpha), float(beta), C.byref(r), C.byref(rn), C.byref(ne), _stream(stream)))
+    return r.value, rn.value, ne.value
+
+
+def draw_signs(seed: int, batch: int, step: int, side: int, nwords: int, stream=None, device="cuda"):
+    """First nwords 64-bit words of the probe sign stream, as an int64 device tensor."""
+    w = torch.empty(max(int(nwords), 1), dtype=torch.int64, device=device)
+    _check(_lib().mfe_draw_signs(int(seed) & ((1 << 64) - 1), int(batch), int(step), int(side), int(nwords),
+                                 _ptr(w), _stream(stream)))
+    return w[:nwords]

@@ -1,0 +1,229 @@
+// C ABI entry points of libmfe: validation, dispatch and error reporting.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "dense.h"
+#include "sparse.h"
+
+namespace mfe {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int set_error(int status, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+void set_warning(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = std::string("warning: ") + buf;
+}
+
+// Parameter checks shared by every equilibration entry point (the paper requires
+// alpha, beta, gamma, M > 0; Algorithm 1 and Section 2.3).
+int check_params(const mfe_equil_params* p, bool check_targets) {
+  if (!p) return set_error(MFE_EINVAL, "params is NULL");
+  auto pos = [](double x) { return x > 0 && std::isfinite(x); };
+  if (check_targets && (!pos(p->alpha) || !pos(p->beta)))
+    return set_error(MFE_EINVAL, "alpha and beta must be positive and finite");
+  if (!pos(p->gamma)) return set_error(MFE_EINVAL, "gamma must be positive and finite");
+  if (!pos(p->box_M)) return set_error(MFE_EINVAL, "box bound M must be positive and finite");
+  if (p->steps < 0) return set_error(MFE_EINVAL, "steps must be >= 0");
+  if (p->probes < 1 || p->probes > 256) return set_error(MFE_EINVAL, "probes must be in 1..256");
+  if (p->t0 < 0) return set_error(MFE_EINVAL, "t0 must be >= 0");
+  if (p->batch < 0 || p->batch >= (1 << 30)) return set_error(MFE_EINVAL, "batch must be in [0, 2^30)");
+  if ((int64_t)p->steps + (int64_t)p->t0 + 2 >= (int64_t)1 << 32)
+    return set_error(MFE_EINVAL, "steps + t0 exceed the sign stream range");
+  return MFE_OK;
+}
+
+}  // namespace mfe
+
+using namespace mfe;
+
+extern "C" {
+
+const char* mfe_last_error(void) { return g_last_error.c_str(); }
+
+const char* mfe_version(void) { return "mfe 0.1 (gfx950)"; }
+
+int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta) {
+  clear_error();
+  if (m <= 0 || n <= 0) return set_error(MFE_EINVAL, "m and n must be positive");
+  if (!alpha || !beta) return set_error(MFE_EINVAL, "NULL output");
+  *alpha = std::pow((double)n / (double)m, 0.25);
+  *beta = std::pow((double)m / (double)n, 0.25);
+  return MFE_OK;
+}
+
+int mfe_draw_signs(uint64_t seed, int32_t batch, int64_t step, int32_t side, int64_t nwords,
+                   uint64_t* words, void* stream) {
+  clear_error();
+  if (batch < 0 || batch >= (1 << 30)) return set_error(MFE_EINVAL, "batch out of range");
+  if (step < 0 || step >= ((int64_t)1 << 32)) return set_error(MFE_EINVAL, "step out of range");
+  if (side < 0 || side > 3) return set_error(MFE_EINVAL, "side out of range");
+  if (nwords < 0) return set_error(MFE_EINVAL, "nwords < 0");
+  if (nwords == 0) return MFE_OK;
+  if (!words) return set_error(MFE_EINVAL, "words is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  // Philox blocks are written whole: draw into a padded scratch area when needed.
+  const int64_t nblk = ceil_div(nwords, 4);
+  uint64_t* dst = words;
+  uint64_t* tmp = nullptr;
+  if (nwords % 4) {
+    MFE_HIP(hipMalloc((void**)&tmp, sizeof(uint64_t) * nblk * 4));
+    dst = tmp;
+  }
+  SignSeg seg;
+  seg.ctrl_lo = ((uint64_t)batch << 34) | (uint64_t)side;
+  seg.nblocks = nblk;
+  seg.word_off = 0;
+  SignSeg* dseg = nullptr;
+  int64_t* dpre = nullptr;
+  int rc = MFE_OK;
+  const int64_t pre[2] = {0, nblk};
+  if (hipMalloc((void**)&dseg, sizeof(SignSeg)) != hipSuccess ||
+      hipMalloc((void**)&dpre, sizeof(pre)) != hipSuccess) {
+    rc = set_error(MFE_ENOMEM, "hipMalloc failed");
+  } else if (hipMemcpyAsync(dseg, &seg, sizeof seg, hipMemcpyHostToDevice, st) != hipSuccess ||
+             hipMemcpyAsync(dpre, pre, sizeof pre, hipMemcpyHostToDevice, st) != hipSuccess) {
+    rc = set_error(MFE_EDEVICE, "hipMemcpyAsync failed");
+  } else {
+    SignGenDev g;
+    g.segs = dseg;
+    g.seg_prefix = dpre;
+    g.nseg = 1;
+    g.nblocks = nblk;
+    g.seed = seed;
+    g.step = (uint64_t)step;
+    g.out = dst;
+    rc = launch_signgen(g, st);
+    if (rc == MFE_OK && tmp &&
+        hipMemcpyAsync(words, tmp, sizeof(uint64_t) * nwords, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      rc = set_error(MFE_EDEVICE, "hipMemcpyAsync failed");
+    if (rc == MFE_OK && hipStreamSynchronize(st) != hipSuccess) rc = set_error(MFE_EDEVICE, "sync failed");
+  }
+  (void)hipFree(dseg);
+  (void)hipFree(dpre);
+  (void)hipFree(tmp);
+  return rc;
+}
+
+int mfe_plan_create(const mfe_matrix* mats, int32_t count, int32_t max_probes, void* stream, mfe_plan** out) {
+  clear_error();
+  return plan_build(mats, count, max_probes, (hipStream_t)stream, out);
+}
+
+int mfe_plan_equilibrate(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b,
+                         const double* beta_b, int32_t use_graph, double* d, double* e, double* u_bar,
+                         double* v_bar) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  MFE_CHECK(check_params(p, alpha_b == nullptr || beta_b == nullptr));
+  if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "sparse path supports at most 64 probes per step");
+  return plan_run(plan, p, alpha_b, beta_b, use_graph, d, e, u_bar, v_bar);
+}
+
+int mfe_plan_last_timing(const mfe_plan* plan, double* loop_ms, double* step_kernel_ms) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  if (loop_ms) *loop_ms = plan->last_loop_ms;
+  if (step_kernel_ms) *step_kernel_ms = plan->last_step_ms;
+  return MFE_OK;
+}
+
+int mfe_plan_destroy(mfe_plan* plan) {
+  clear_error();
+  plan_free(plan);
+  return MFE_OK;
+}
+
+int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e, double* u_bar,
+                    double* v_bar) {
+  clear_error();
+  if (!A) return set_error(MFE_EINVAL, "matrix is NULL");
+  MFE_CHECK(check_params(p, true));
+  if (!d || !e) return set_error(MFE_EINVAL, "outputs d and e are required");
+  if (A->m <= 0 || A->n <= 0) return set_error(MFE_EDIM, "m and n must be positive");
+  switch (A->kind) {
+    case MFE_CSR_F32: {
+      if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "sparse path supports at most 64 probes per step");
+      mfe_plan* plan = nullptr;
+      MFE_CHECK(plan_build(A, 1, p->probes, (hipStream_t)p->stream, &plan));
+      int rc = plan_run(plan, p, nullptr, nullptr, 0, d, e, u_bar, v_bar);
+      plan_free(plan);
+      return rc;
+    }
+    case MFE_DENSE_F64:
+      return dense_f64_equilibrate(A, p, d, e, u_bar, v_bar);
+    case MFE_OPERATOR:
+      return operator_equilibrate(A, p, d, e, u_bar, v_bar);
+    case MFE_DENSE_BF16:
+      return dense_bf16_equilibrate(A, p, d, e, u_bar, v_bar);
+    default:
+      return set_error(MFE_EINVAL, "unknown matrix kind %d", (int)A->kind);
+  }
+}
+
+int mfe_plan_lsqr(mfe_plan* plan, const double* b, const double* d, const double* e, double tol,
+                  int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, void* stream) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  if (plan->count != 1) return set_error(MFE_EUNSUPPORTED, "LSQR needs a single-matrix plan");
+  if (!b || !x) return set_error(MFE_EINVAL, "b and x are required");
+  if (!(tol >= 0) || max_iter < 0 || check_every < 1)
+    return set_error(MFE_EINVAL, "need tol >= 0, max_iter >= 0, check_every >= 1");
+  return plan_lsqr(plan, b, d, e, tol, max_iter, check_every, x, info, (hipStream_t)stream);
+}
+
+int mfe_lsqr(const mfe_matrix* A, const double* b, const double* d, const double* e, double tol,
+             int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, void* stream) {
+  clear_error();
+  if (!A) return set_error(MFE_EINVAL, "matrix is NULL");
+  if (!b || !x) return set_error(MFE_EINVAL, "b and x are required");
+  if (!(tol >= 0) || max_iter < 0 || check_every < 1)
+    return set_error(MFE_EINVAL, "need tol >= 0, max_iter >= 0, check_every >= 1");
+  if (A->m <= 0 || A->n <= 0) return set_error(MFE_EDIM, "m and n must be positive");
+  if (A->kind == MFE_CSR_F32) {
+    mfe_plan* plan = nullptr;
+    MFE_CHECK(plan_build(A, 1, 1, (hipStream_t)stream, &plan));
+    int rc = plan_lsqr(plan, b, d, e, tol, max_iter, check_every, x, info, (hipStream_t)stream);
+    plan_free(plan);
+    return rc;
+  }
+  if (A->kind == MFE_DENSE_F64) return dense_f64_lsqr(A, b, d, e, tol, max_iter, check_every, x, info, (hipStream_t)stream);
+  return set_error(MFE_EUNSUPPORTED, "LSQR accepts CSR FP32 and dense FP64 matrices");
+}
+
+int mfe_residual(const mfe_matrix* A, const double* d, const double* e, double alpha, double beta, double* rms,
+                 double* rms_nonempty, int64_t* n_empty, void* stream) {
+  clear_error();
+  if (!A) return set_error(MFE_EINVAL, "matrix is NULL");
+  if (!(alpha > 0) || !(beta > 0)) return set_error(MFE_EINVAL, "alpha and beta must be positive");
+  if (A->m <= 0 || A->n <= 0) return set_error(MFE_EDIM, "m and n must be positive");
+  if (A->kind == MFE_CSR_F32) {
+    mfe_plan* plan = nullptr;
+    MFE_CHECK(plan_build(A, 1, 1, (hipStream_t)stream, &plan));
+    int rc = plan_residual(plan, d, e, alpha, beta, rms, rms_nonempty, n_empty, (hipStream_t)stream);
+    plan_free(plan);
+    return rc;
+  }
+  if (A->kind == MFE_DENSE_F64) return dense_f64_residual(A, d, e, alpha, beta, rms, rms_nonempty, n_empty, (hipStream_t)stream);
+  return set_error(MFE_EUNSUPPORTED, "residual accepts CSR FP32 and dense FP64 matrices");
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Shared host/device definitions of libmfe (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mfe.h"
+
+namespace mfe {
+
+// ----------------------------------------------------------------- errors
+
+// Records a message for mfe_last_error() and returns the status.
+int set_error(int status, const char* fmt, ...);
+void clear_error();
+void set_warning(const char* fmt, ...);
+
+#define MFE_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (call);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return ::mfe::set_error(_e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EDEVICE,     \
+                              "%s failed: %s (%s:%d)", #call, hipGetErrorString(_e),    \
+                              __FILE__, __LINE__);                                      \
+  } while (0)
+
+#define MFE_CHECK(status_expr)        \
+  do {                                \
+    int _s = (status_expr);           \
+    if (_s != MFE_OK) return _s;      \
+  } while (0)
+
+// ----------------------------------------------------------------- probe signs
+//
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One block = 4 x 64 bits for a
+// counter (c+1, 0, 0, 0) and key (seed, ctrl).  The stream bit layout is documented in
+// mfe.h.
+
+struct U64x4 {
+  uint64_t x[4];
+};
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = mulhi64(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = mulhi64(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  U64x4 o;
+  o.x[0] = c0;
+  o.x[1] = c1;
+  o.x[2] = c2;
+  o.x[3] = c3;
+  return o;
+}
+
+__host__ __device__ inline uint64_t stream_ctrl(uint64_t batch, uint64_t step, uint64_t side) {
+  return (batch << 34) | (step << 2) | side;
+}
+
+// k (<= 64) bits starting at bit g of a word array.
+__device__ inline uint64_t extract_bits(const uint64_t* __restrict__ words, int64_t g, int k) {
+  const int64_t w = g >> 6;
+  const int sh = (int)(g & 63);
+  uint64_t v = words[w] >> sh;
+  if (sh + k > 64) v |= words[w + 1] << (64 - sh);
+  return k == 64 ? v : (v & ((1ull << k) - 1ull));
+}
+
+// Gathered per-index record of the sparse path: the scale e^x of the index (FP64) and
+// the sign bits of its probes for the step that consumes it.
+struct __align__(16) Desc {
+  double scale;
+  uint64_t bits;
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Per-step scalars, computed on the host exactly as the oracle writes them.
+struct StepScalars {
+  double eta;   // 2 / (gamma (tau + 1))
+  double tau;   // t + t0
+  double gamma;
+  double M;
+};
+
+}  // namespace mfe

@@ -1,0 +1,144 @@
+// Sparse (CSR) engine of libmfe: layouts, plan and kernel argument blocks.
+//
+// Both products of Algorithm 1 (Section 3.2) run from one library-built layout per
+// direction: the rows of A for Y = A E S and the rows of A' (the CSC of A) for
+// X = A' D W.  Each direction is stored as a sliced ELL structure with 64 rows per
+// slice (one wavefront, one row per lane): entry (slot q, lane l) of slice s sits at
+// ent[slice_off[s] + 64 q + l], so every load of a slot is one contiguous 512-byte
+// access.  Within windows of 4096 rows the rows are ordered by decreasing length so
+// that the lanes of a slice have similar lengths (little padding, few idle lanes).
+// Per-index state (iterates, averages, descriptors) lives in this internal order; the
+// entry indices refer to the other direction's internal order.  Several matrices are
+// handled as one block-diagonal problem; slices never span two matrices.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace mfe {
+
+constexpr int kSlice = 64;       // rows per slice = wavefront size
+constexpr int kWindow = 4096;    // rows sorted together by length
+constexpr int kBlock = 256;      // threads per workgroup of the step kernel
+
+struct SideLayout {
+  int64_t norig = 0;   // original indices (sum over matrices)
+  int64_t nint = 0;    // internal indices (each matrix padded to whole slices)
+  int64_t nslices = 0;
+  int64_t nent = 0;    // stored entries including padding
+  int64_t* slice_off = nullptr;   // [nslices + 1] first entry of each slice
+  int32_t* slice_mat = nullptr;   // [nslices] matrix of the slice
+  int32_t* len = nullptr;         // [nint] row length, 0 for padding lanes
+  int32_t* orig = nullptr;        // [nint] local original index, -1 for padding lanes
+  int32_t* orig2int = nullptr;    // [norig] global original index -> internal index
+  int2* ent = nullptr;            // [nent] (other-side internal index, FP32 value bits)
+};
+
+// Per-matrix data the kernels need (device table).
+struct MatDev {
+  double tgt_row;         // alpha_b^2
+  double tgt_col;         // beta_b^2
+  int64_t row_orig_base;  // first original row of the matrix in the concatenation
+  int64_t col_orig_base;
+  int64_t sign_word_row;  // first sign word of the matrix's side-1 segment in a slot
+  int64_t sign_word_col;  // first sign word of the matrix's side-0 segment in a slot
+};
+
+struct MatMeta {
+  int64_t m, n, nnz;
+  int64_t row_orig_base, col_orig_base, nnz_base;
+  int64_t row_int_base, col_int_base;
+};
+
+// One Philox sign segment: all indices of one side of one matrix.
+struct SignSeg {
+  uint64_t ctrl_lo;   // (batch << 34) | side; the step is or-ed in per launch
+  int64_t nblocks;    // Philox blocks of the segment
+  int64_t word_off;   // first word of the segment inside a slot
+};
+
+struct SideDev {
+  const int64_t* slice_off;
+  const int32_t* slice_mat;
+  const int32_t* len;
+  const int32_t* orig;
+  const int2* ent;
+  int64_t nint;
+  double* x;                  // iterate (u or v)
+  double* xbar;               // running average
+  const Desc* gather;         // other side's descriptors from the previous step
+  Desc* out;                  // this side's descriptors for the next step
+  const uint64_t* next_signs; // slot holding the sign words of step t + 1
+  int is_row;                 // 1: rows (targets alpha^2, side-1 signs); 0: columns
+};
+
+struct SignGenDev {
+  const SignSeg* segs;
+  const int64_t* seg_prefix;  // [nseg + 1] prefix sums of blocks
+  int32_t nseg;
+  int64_t nblocks;            // total Philox blocks
+  uint64_t seed;
+  uint64_t step;              // step whose signs are generated (0: none)
+  uint64_t* out;              // destination slot
+};
+
+struct StepArgs {
+  SideDev rows, cols;
+  SignGenDev gen;
+  const MatDev* mats;
+  int32_t k;
+  StepScalars sc;
+  int64_t row_blocks, col_blocks, gen_blocks;
+  int* flag;                  // bit 0: non-finite value seen
+};
+
+struct mfe_plan_impl;
+
+}  // namespace mfe
+
+struct mfe_plan {
+  int32_t count = 0;
+  int32_t max_probes = 0;
+  std::vector<mfe::MatMeta> meta;
+  int64_t M = 0, N = 0, NNZ = 0;
+  mfe::SideLayout rows, cols;
+  // run-time buffers (allocated on first use)
+  double *x_row = nullptr, *xbar_row = nullptr, *x_col = nullptr, *xbar_col = nullptr;
+  mfe::Desc* desc_row[2] = {nullptr, nullptr};
+  mfe::Desc* desc_col[2] = {nullptr, nullptr};
+  uint64_t* signs[2] = {nullptr, nullptr};
+  int64_t sign_words = 0;           // words per slot
+  int32_t sign_k = 0;               // k the sign layout was built for
+  int64_t sign_batch_base = -1;     // batch index of matrix 0 in that layout
+  std::vector<mfe::SignSeg> segs_host;
+  mfe::SignSeg* segs = nullptr;
+  int64_t* seg_prefix = nullptr;
+  int64_t sign_blocks = 0;
+  mfe::MatDev* mats = nullptr;
+  int* flag = nullptr;
+  double last_loop_ms = 0.0, last_step_ms = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // cached HIP graph of the step loop, valid for the run parameters in graph_key
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace mfe {
+
+int plan_build(const mfe_matrix* mats, int32_t count, int32_t max_probes, hipStream_t s,
+               mfe_plan** out);
+void plan_free(mfe_plan* p);
+int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
+             int use_graph, double* d, double* e, double* u_bar, double* v_bar);
+int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, double tol,
+              int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t s);
+int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta,
+                  double* rms, double* rms_nonempty, int64_t* n_empty, hipStream_t s);
+
+// Launches the fused sign-generation for one step into `out` (all segments).
+int launch_signgen(const SignGenDev& g, hipStream_t s);
+
+}  // namespace mfe

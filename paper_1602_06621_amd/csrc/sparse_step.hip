@@ -1,0 +1,383 @@
+// Fused step kernel of the sparse engine and its driver (Algorithm 1, Section 3.2).
+//
+// One launch per step t performs, for every index of both directions at once
+// (Jacobi order: both read the descriptors of step t-1):
+//   rows:    Y_i = sum_j A_ij e^(v_j) s_jp        (p < k)  -> z_i = e^(2u_i) mean_p Y_ip^2
+//            u_i <- clip(u_i - eta (z_i - alpha^2 + gamma u_i), -M, M),  u_bar update,
+//            descriptor_i <- (e^(u_i), probe bits w_i of step t+1)
+//   columns: X_j = sum_i A_ij e^(u_i) w_ip                -> z_j = e^(2v_j) mean_p X_jp^2
+//            v_j update with beta, v_bar update, descriptor_j <- (e^(v_j), bits s_j of t+1)
+//   extra workgroups: Philox sign words of step t+2 for all indices.
+// Arithmetic: matrix values FP32 (exact in FP64), scales, products, sums and iterates
+// FP64.  Early steps of Algorithm 1 have eta gamma close to 1 and amplify rounding, so
+// FP32 accumulation cannot track the FP64 iteration to 1e-5 (measured, see the
+// design notes); FP64 costs no more VALU issue slots than unpacked FP32 on gfx950.
+#include <cmath>
+#include <vector>
+
+#include "sparse.h"
+
+namespace mfe {
+namespace {
+
+// acc_p += (-1)^bit_p * t for p < KP.  The sign of t is folded into the probe bits so
+// each probe costs one shift, one and-or on the high word and one FP64 add.
+template <int KP>
+__device__ __forceinline__ void accumulate(double (&acc)[KP], double t, uint64_t bits) {
+  const uint64_t tb = (uint64_t)__double_as_longlong(t);
+  const uint32_t lo = (uint32_t)tb;
+  const uint32_t hi_abs = (uint32_t)(tb >> 32) & 0x7FFFFFFFu;
+  if (tb >> 63) bits = ~bits;
+  const uint32_t b0 = (uint32_t)bits;
+  const uint32_t b1 = (uint32_t)(bits >> 32);
+#pragma unroll
+  for (int p = 0; p < KP; ++p) {
+    const uint32_t sb = p < 32 ? ((b0 << (31 - (p & 31))) & 0x80000000u)
+                               : ((b1 << (31 - (p & 31))) & 0x80000000u);
+    acc[p] += __longlong_as_double((long long)(((uint64_t)(hi_abs | sb) << 32) | lo));
+  }
+}
+
+template <int KP>
+__device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
+                                            const StepScalars& sc, int64_t blk, int* flag) {
+  const int64_t r = blk * kBlock + threadIdx.x;
+  if (r >= S.nint) return;  // nint is a multiple of 64: whole wavefronts leave together
+  const int64_t s = r >> 6;
+  const int lane = (int)(threadIdx.x & 63);
+  const int len = S.len[r];
+  const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
+  double acc[KP];
+#pragma unroll
+  for (int p = 0; p < KP; ++p) acc[p] = 0.0;
+  for (int q = 0; q < len; ++q) {
+    const long long en = __builtin_nontemporal_load(e + (int64_t)q * kSlice);
+    const int32_t idx = (int32_t)(en & 0xFFFFFFFFll);
+    const float a = __int_as_float((int32_t)(en >> 32));
+    const Desc d = S.gather[idx];
+    accumulate<KP>(acc, (double)a * d.scale, d.bits);
+  }
+  const int32_t li = S.orig[r];
+  if (li < 0) return;
+  const MatDev mt = mats[S.slice_mat[s]];
+  double ss = 0.0;
+#pragma unroll
+  for (int p = 0; p < KP; ++p)
+    if (p < k) ss += acc[p] * acc[p];
+  const double x_old = S.x[r];
+  const double z = exp(2.0 * x_old) * (ss / (double)k);
+  const double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
+  const double g = (z - tgt) + sc.gamma * x_old;
+  double xn = x_old - sc.eta * g;
+  xn = fmin(fmax(xn, -sc.M), sc.M);
+  if (!isfinite(z) || !isfinite(xn)) atomicOr(flag, 1);
+  S.x[r] = xn;
+  S.xbar[r] = 2.0 * xn / (sc.tau + 2.0) + sc.tau * S.xbar[r] / (sc.tau + 2.0);
+  const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
+  Desc nd;
+  nd.scale = exp(xn);
+  nd.bits = extract_bits(S.next_signs + wbase, (int64_t)li * k, k);
+  S.out[r] = nd;
+}
+
+__device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk) {
+  const int64_t c = gblk * kBlock + threadIdx.x;
+  if (c >= g.nblocks) return;
+  int lo = 0, hi = g.nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.seg_prefix[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const SignSeg sg = g.segs[lo];
+  const int64_t cb = c - g.seg_prefix[lo];
+  const U64x4 w = philox4x64_10((uint64_t)cb + 1, 0, 0, 0, g.seed, sg.ctrl_lo | (g.step << 2));
+  uint64_t* o = g.out + sg.word_off + 4 * cb;
+  o[0] = w.x[0];
+  o[1] = w.x[1];
+  o[2] = w.x[2];
+  o[3] = w.x[3];
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
+  const int64_t b = blockIdx.x;
+  if (b < a.row_blocks) side_update<KP>(a.rows, a.mats, a.k, a.sc, b, a.flag);
+  else if (b < a.row_blocks + a.col_blocks) side_update<KP>(a.cols, a.mats, a.k, a.sc, b - a.row_blocks, a.flag);
+  else signgen_block(a.gen, b - a.row_blocks - a.col_blocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
+
+__global__ void k_init(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ x0, int k) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.nint) return;
+  const int32_t li = S.orig[r];
+  if (li < 0) return;
+  const MatDev mt = mats[S.slice_mat[r >> 6]];
+  const int64_t g = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
+  const double x = x0 ? x0[g] : 0.0;
+  S.x[r] = x;
+  S.xbar[r] = x;
+  Desc nd;
+  nd.scale = exp(x);
+  nd.bits = extract_bits(S.next_signs + (S.is_row ? mt.sign_word_row : mt.sign_word_col), (int64_t)li * k, k);
+  S.out[r] = nd;
+}
+
+__global__ void k_output(SideDev S, const MatDev* __restrict__ mats, double* __restrict__ dout,
+                         double* __restrict__ xbar_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.nint) return;
+  const int32_t li = S.orig[r];
+  if (li < 0) return;
+  const MatDev mt = mats[S.slice_mat[r >> 6]];
+  const int64_t g = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
+  const double xb = S.xbar[r];
+  dout[g] = exp(xb);
+  if (xbar_out) xbar_out[g] = xb;
+}
+
+template <class T>
+int ensure(T** ptr, int64_t count) {
+  if (*ptr) return MFE_OK;
+  hipError_t e = hipMalloc((void**)ptr, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+  if (e != hipSuccess)
+    return set_error(e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EDEVICE, "hipMalloc failed: %s",
+                     hipGetErrorString(e));
+  return MFE_OK;
+}
+
+// Sign stream layout of a plan for k probes: per matrix, one segment for side 0
+// (columns) and one for side 1 (rows), each starting on a Philox block boundary.
+int build_sign_layout(mfe_plan* p, int k, int64_t batch_base) {
+  if (p->sign_k == k && p->sign_batch_base == batch_base) return MFE_OK;
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(p->signs[i]);
+    p->signs[i] = nullptr;
+  }
+  (void)hipFree(p->segs);
+  (void)hipFree(p->seg_prefix);
+  p->segs = nullptr;
+  p->seg_prefix = nullptr;
+  p->segs_host.clear();
+  std::vector<int64_t> prefix;
+  int64_t words = 0, blocks = 0;
+  prefix.push_back(0);
+  for (int side = 0; side < 2; ++side) {
+    for (int b = 0; b < p->count; ++b) {
+      const int64_t cnt = side == 0 ? p->meta[b].n : p->meta[b].m;
+      SignSeg sg;
+      sg.ctrl_lo = ((uint64_t)(batch_base + b) << 34) | (uint64_t)side;
+      sg.nblocks = ceil_div(cnt * k, 256);
+      sg.word_off = words;
+      words += 4 * sg.nblocks + 4;  // one spare block: bit extraction may read one word past the end
+      blocks += sg.nblocks;
+      prefix.push_back(blocks);
+      p->segs_host.push_back(sg);
+    }
+  }
+  p->sign_words = words;
+  p->sign_blocks = blocks;
+  MFE_CHECK(ensure(&p->signs[0], words));
+  MFE_CHECK(ensure(&p->signs[1], words));
+  MFE_HIP(hipMemset(p->signs[0], 0, sizeof(uint64_t) * words));
+  MFE_HIP(hipMemset(p->signs[1], 0, sizeof(uint64_t) * words));
+  MFE_CHECK(ensure(&p->segs, (int64_t)p->segs_host.size()));
+  MFE_CHECK(ensure(&p->seg_prefix, (int64_t)prefix.size()));
+  MFE_HIP(hipMemcpy(p->segs, p->segs_host.data(), sizeof(SignSeg) * p->segs_host.size(), hipMemcpyHostToDevice));
+  MFE_HIP(hipMemcpy(p->seg_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice));
+  p->sign_k = k;
+  p->sign_batch_base = batch_base;
+  return MFE_OK;
+}
+
+SignGenDev make_gen(const mfe_plan* p, uint64_t seed, uint64_t step, uint64_t* out) {
+  SignGenDev g;
+  g.segs = p->segs;
+  g.seg_prefix = p->seg_prefix;
+  g.nseg = (int32_t)p->segs_host.size();
+  g.nblocks = p->sign_blocks;
+  g.seed = seed;
+  g.step = step;
+  g.out = out;
+  return g;
+}
+
+SideDev make_side(const SideLayout& L, double* x, double* xbar, const Desc* gather, Desc* out,
+                  const uint64_t* next_signs, int is_row) {
+  SideDev S;
+  S.slice_off = L.slice_off;
+  S.slice_mat = L.slice_mat;
+  S.len = L.len;
+  S.orig = L.orig;
+  S.ent = L.ent;
+  S.nint = L.nint;
+  S.x = x;
+  S.xbar = xbar;
+  S.gather = gather;
+  S.out = out;
+  S.next_signs = next_signs;
+  S.is_row = is_row;
+  return S;
+}
+
+template <int KP>
+void launch_step(const StepArgs& a, hipStream_t st) {
+  const int64_t grid = a.row_blocks + a.col_blocks + a.gen_blocks;
+  k_step<KP><<<dim3((unsigned)grid), dim3(kBlock), 0, st>>>(a);
+}
+
+void launch_step_k(const StepArgs& a, hipStream_t st) {
+  const int k = a.k;
+  if (k <= 1) launch_step<1>(a, st);
+  else if (k <= 2) launch_step<2>(a, st);
+  else if (k <= 4) launch_step<4>(a, st);
+  else if (k <= 8) launch_step<8>(a, st);
+  else if (k <= 16) launch_step<16>(a, st);
+  else if (k <= 32) launch_step<32>(a, st);
+  else launch_step<64>(a, st);
+}
+
+}  // namespace
+
+int launch_signgen(const SignGenDev& g, hipStream_t st) {
+  if (g.nblocks <= 0) return MFE_OK;
+  k_signgen<<<dim3((unsigned)ceil_div(g.nblocks, kBlock)), dim3(kBlock), 0, st>>>(g);
+  MFE_HIP(hipGetLastError());
+  return MFE_OK;
+}
+
+int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
+             int use_graph, double* d, double* e, double* u_bar, double* v_bar) {
+  hipStream_t st = (hipStream_t)prm->stream;
+  const int k = prm->probes;
+  if (k < 1 || k > p->max_probes)
+    return set_error(MFE_EINVAL, "probes = %d outside 1..%d (the plan's max_probes)", k, p->max_probes);
+  if (!d || !e) return set_error(MFE_EINVAL, "outputs d and e are required");
+  const int64_t nr = p->rows.nint, nc = p->cols.nint;
+  MFE_CHECK(ensure(&p->x_row, nr));
+  MFE_CHECK(ensure(&p->xbar_row, nr));
+  MFE_CHECK(ensure(&p->x_col, nc));
+  MFE_CHECK(ensure(&p->xbar_col, nc));
+  for (int i = 0; i < 2; ++i) {
+    MFE_CHECK(ensure(&p->desc_row[i], nr));
+    MFE_CHECK(ensure(&p->desc_col[i], nc));
+  }
+  MFE_CHECK(ensure(&p->flag, 1));
+  MFE_CHECK(ensure(&p->mats, p->count));
+  if ((int64_t)prm->batch + p->count > ((int64_t)1 << 30))
+    return set_error(MFE_EINVAL, "batch + count exceeds 2^30");
+  MFE_CHECK(build_sign_layout(p, k, prm->batch));
+
+  // per-matrix targets and sign offsets
+  std::vector<MatDev> md(p->count);
+  int64_t ro = 0, co = 0;
+  for (int b = 0; b < p->count; ++b) {
+    const double al = alpha_b ? alpha_b[b] : prm->alpha;
+    const double be = beta_b ? beta_b[b] : prm->beta;
+    if (!(al > 0) || !(be > 0) || !std::isfinite(al) || !std::isfinite(be))
+      return set_error(MFE_EINVAL, "matrix %d: alpha and beta must be positive and finite", b);
+    md[b].tgt_row = al * al;
+    md[b].tgt_col = be * be;
+    md[b].row_orig_base = ro;
+    md[b].col_orig_base = co;
+    md[b].sign_word_col = p->segs_host[b].word_off;              // side 0
+    md[b].sign_word_row = p->segs_host[p->count + b].word_off;   // side 1
+    ro += p->meta[b].m;
+    co += p->meta[b].n;
+  }
+  MFE_HIP(hipMemcpyAsync(p->mats, md.data(), sizeof(MatDev) * p->count, hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemsetAsync(p->flag, 0, sizeof(int), st));
+
+  const uint64_t seed = prm->seed;
+  const int T = prm->steps;
+  // signs of step 1 -> slot 1, of step 2 -> slot 0
+  MFE_CHECK(launch_signgen(make_gen(p, seed, 1, p->signs[1]), st));
+  MFE_CHECK(launch_signgen(make_gen(p, seed, 2, p->signs[0]), st));
+  {
+    SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[0], p->signs[1], 1);
+    SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[0], p->signs[1], 0);
+    k_init<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, st>>>(R, p->mats, prm->u0, k);
+    k_init<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(C, p->mats, prm->v0, k);
+    MFE_HIP(hipGetLastError());
+  }
+
+  auto step_args = [&](int t) {
+    StepArgs a;
+    const int par = t & 1, prev = par ^ 1;
+    a.rows = make_side(p->rows, p->x_row, p->xbar_row, p->desc_col[prev], p->desc_row[par],
+                       p->signs[(t + 1) & 1], 1);
+    a.cols = make_side(p->cols, p->x_col, p->xbar_col, p->desc_row[prev], p->desc_col[par],
+                       p->signs[(t + 1) & 1], 0);
+    const uint64_t gen_step = (uint64_t)t + 2;
+    const bool gen = (int64_t)gen_step <= (int64_t)T + 1;
+    a.gen = make_gen(p, seed, gen_step, p->signs[t & 1]);
+    a.mats = p->mats;
+    a.k = k;
+    const double tau = (double)t + (double)prm->t0;
+    a.sc.tau = tau;
+    a.sc.eta = 2.0 / (prm->gamma * (tau + 1.0));
+    a.sc.gamma = prm->gamma;
+    a.sc.M = prm->box_M;
+    a.row_blocks = ceil_div(nr, kBlock);
+    a.col_blocks = ceil_div(nc, kBlock);
+    a.gen_blocks = gen ? ceil_div(p->sign_blocks, kBlock) : 0;
+    a.flag = p->flag;
+    return a;
+  };
+
+  // The step loop runs either as T launches or as one cached HIP graph of those T
+  // launches (captured once per (k, T, t0, gamma, M, seed, batch)).
+  hipStream_t run_st = st;
+  if (use_graph && T > 0) {
+    const double key[8] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+                           (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch};
+    bool hit = p->graph_exec != nullptr;
+    for (int i = 0; i < 8 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    if (!hit) {
+      if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+      if (p->graph) (void)hipGraphDestroy(p->graph);
+      p->graph_exec = nullptr;
+      p->graph = nullptr;
+      MFE_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      for (int t = 1; t <= T; ++t) launch_step_k(step_args(t), p->cap_stream);
+      MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
+      MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+      for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
+    }
+    if (st == nullptr) {
+      // graphs are replayed on the plan's own stream, ordered after the default stream
+      MFE_HIP(hipStreamSynchronize(nullptr));
+      run_st = p->cap_stream;
+    }
+    MFE_HIP(hipEventRecord(p->ev0, run_st));
+    MFE_HIP(hipGraphLaunch(p->graph_exec, run_st));
+    MFE_HIP(hipEventRecord(p->ev1, run_st));
+  } else {
+    MFE_HIP(hipEventRecord(p->ev0, run_st));
+    for (int t = 1; t <= T; ++t) launch_step_k(step_args(t), run_st);
+    MFE_HIP(hipGetLastError());
+    MFE_HIP(hipEventRecord(p->ev1, run_st));
+  }
+  {
+    const int par = T & 1;
+    SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[par], nullptr, 1);
+    SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[par], nullptr, 0);
+    k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, d, u_bar);
+    k_output<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, run_st>>>(C, p->mats, e, v_bar);
+    MFE_HIP(hipGetLastError());
+  }
+  int flag = 0;
+  MFE_HIP(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, run_st));
+  MFE_HIP(hipStreamSynchronize(run_st));
+  float ms = 0.f;
+  MFE_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  p->last_loop_ms = ms;
+  p->last_step_ms = T > 0 ? ms / T : 0.0;
+  if (flag) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
+  return MFE_OK;
+}
+
+}  // namespace mfe

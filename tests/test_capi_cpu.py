@@ -1,0 +1,118 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol, and
+rejects invalid arguments before touching a device.  No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfe.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1602_06621_amd import _ffi
+    from paper_1602_06621_amd import build as b
+
+    if not os.path.exists(_ffi.library_path()):
+        b.build()
+    return _ffi._lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(mfe_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mfe_equilibrate", "mfe_lsqr", "mfe_default_alpha_beta", "mfe_plan_create",
+                     "mfe_plan_equilibrate", "mfe_plan_destroy", "mfe_residual", "mfe_draw_signs",
+                     "mfe_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_default_alpha_beta(lib):
+    a, b = C.c_double(), C.c_double()
+    assert lib.mfe_default_alpha_beta(200, 100, C.byref(a), C.byref(b)) == 0
+    assert a.value == pytest.approx(0.5 ** 0.25, rel=1e-15)
+    assert b.value == pytest.approx(2.0 ** 0.25, rel=1e-15)
+    assert lib.mfe_default_alpha_beta(0, 5, C.byref(a), C.byref(b)) == -1
+    assert "positive" in lib.mfe_last_error().decode()
+
+
+def _params(**kw):
+    from paper_1602_06621_amd._ffi import _Params
+
+    p = _Params()
+    p.alpha, p.beta, p.gamma, p.box_M = 1.0, 1.0, 0.1, 10.0
+    p.steps, p.probes, p.seed, p.t0, p.batch = 10, 4, 1, 0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _csr_struct(m=4, n=3):
+    from paper_1602_06621_amd._ffi import _Matrix
+
+    s = _Matrix()
+    s.kind, s.m, s.n, s.nnz = 2, m, n, 0
+    return s
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(alpha=0.0), -1), (dict(beta=-1.0), -1), (dict(gamma=0.0), -1), (dict(box_M=0.0), -1),
+    (dict(alpha=float("nan")), -1), (dict(steps=-1), -1), (dict(probes=0), -1), (dict(probes=257), -1),
+    (dict(t0=-2), -1), (dict(batch=-1), -1),
+])
+def test_invalid_parameters_rejected_on_host(lib, bad, code):
+    s = _csr_struct()
+    p = _params(**bad)
+    dummy = C.c_void_p(16)
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(p), dummy, dummy, None, None) == code
+    assert lib.mfe_last_error().decode() != ""
+
+
+def test_missing_outputs_and_dims_rejected(lib):
+    s = _csr_struct()
+    p = _params()
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(p), None, None, None, None) == -1
+    s.m = 0
+    dummy = C.c_void_p(16)
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(p), dummy, dummy, None, None) == -2
+    assert lib.mfe_equilibrate(None, C.byref(p), dummy, dummy, None, None) == -1
+
+
+def test_draw_signs_argument_checks(lib):
+    assert lib.mfe_draw_signs(1, -1, 1, 0, 4, C.c_void_p(16), None) == -1
+    assert lib.mfe_draw_signs(1, 0, 2**32, 0, 4, C.c_void_p(16), None) == -1
+    assert lib.mfe_draw_signs(1, 0, 1, 4, 4, C.c_void_p(16), None) == -1
+    assert lib.mfe_draw_signs(1, 0, 1, 0, 0, None, None) == 0
+
+
+def test_plan_rejects_bad_probe_counts(lib):
+    s = _csr_struct()
+    h = C.c_void_p()
+    assert lib.mfe_plan_create(C.byref(s), 1, 65, None, C.byref(h)) == -6
+    assert lib.mfe_plan_create(C.byref(s), 0, 4, None, C.byref(h)) == -1
+
+
+def test_version(lib):
+    assert "gfx950" in lib.mfe_version().decode()
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1602_06621_amd import _ffi
+
+    monkeypatch.setattr(_ffi, "_LIB", None)
+    monkeypatch.setenv("MFE_LIBRARY", str(tmp_path / "absent.so"))
+    with pytest.raises(_ffi.LibraryMissing):
+        _ffi.default_alpha_beta(2, 2)
