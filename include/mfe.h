@@ -90,8 +90,8 @@ typedef struct {
   uint64_t seed;        /* probe stream seed */
   int32_t t0;           /* step offset >= 0 (0 = Algorithm 1); tau = t + t0 */
   int32_t batch;        /* batch index b of the sign stream (0 for a single matrix) */
-  const double* u0;     /* device [m] warm start, or NULL for 0 */
-  const double* v0;     /* device [n] warm start, or NULL for 0 */
+  const double* u0;     /* device [m] warm start in [-M, M], or NULL for 0 (EINVAL if outside) */
+  const double* v0;     /* device [n] warm start in [-M, M], or NULL for 0 (EINVAL if outside) */
   void* stream;         /* hipStream_t, NULL = default stream */
 } mfe_equil_params;
 

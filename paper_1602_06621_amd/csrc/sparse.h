@@ -21,6 +21,10 @@ namespace mfe {
 constexpr int kSlice = 64;       // rows per slice = wavefront size
 constexpr int kWindow = 4096;    // rows sorted together by length
 constexpr int kBlock = 256;      // threads per workgroup of the step kernel
+#ifndef MFE_BATCH
+#define MFE_BATCH 8
+#endif
+constexpr int kBatch = MFE_BATCH;  // slots whose loads a lane issues together
 
 struct SideLayout {
   int64_t norig = 0;   // original indices (sum over matrices)
@@ -67,8 +71,8 @@ struct SideDev {
   int64_t nint;
   double* x;                  // iterate (u or v)
   double* xbar;               // running average
-  const Desc* gather;         // other side's descriptors from the previous step
-  Desc* out;                  // this side's descriptors for the next step
+  const void* gather;         // other side's descriptors from the previous step
+  void* out;                  // this side's descriptors for the next step
   const uint64_t* next_signs; // slot holding the sign words of step t + 1
   int is_row;                 // 1: rows (targets alpha^2, side-1 signs); 0: columns
 };
@@ -83,14 +87,15 @@ struct SignGenDev {
   uint64_t* out;              // destination slot
 };
 
-struct StepArgs {
-  SideDev rows, cols;
+// Arguments of one launch of the step kernel: one direction of one step.
+struct PhaseArgs {
+  SideDev side;
   SignGenDev gen;
   const MatDev* mats;
   int32_t k;
   StepScalars sc;
-  int64_t row_blocks, col_blocks, gen_blocks;
-  int* flag;                  // bit 0: non-finite value seen
+  int64_t side_blocks, gen_blocks;
+  int* flag;                  // bit 0: non-finite value seen; bit 1: warm start outside the box
 };
 
 struct mfe_plan_impl;

@@ -1,13 +1,13 @@
-// Fused step kernel of the sparse engine and its driver (Algorithm 1, Section 3.2).
+// Step kernels of the sparse engine and their driver (Algorithm 1, Section 3.2).
 //
-// One launch per step t performs, for every index of both directions at once
-// (Jacobi order: both read the descriptors of step t-1):
+// Step t is two launches, one per direction; both read the descriptors of step t-1
+// (Jacobi order) and write those of step t (double-buffered):
 //   rows:    Y_i = sum_j A_ij e^(v_j) s_jp        (p < k)  -> z_i = e^(2u_i) mean_p Y_ip^2
 //            u_i <- clip(u_i - eta (z_i - alpha^2 + gamma u_i), -M, M),  u_bar update,
 //            descriptor_i <- (e^(u_i), probe bits w_i of step t+1)
 //   columns: X_j = sum_i A_ij e^(u_i) w_ip                -> z_j = e^(2v_j) mean_p X_jp^2
 //            v_j update with beta, v_bar update, descriptor_j <- (e^(v_j), bits s_j of t+1)
-//   extra workgroups: Philox sign words of step t+2 for all indices.
+//   extra workgroups of the row launch: Philox sign words of step t+2 for all indices.
 // Arithmetic: matrix values FP32 (exact in FP64), scales, products, sums and iterates
 // FP64.  Early steps of Algorithm 1 have eta gamma close to 1 and amplify rounding, so
 // FP32 accumulation cannot track the FP64 iteration to 1e-5 (measured, see the
@@ -38,46 +38,140 @@ __device__ __forceinline__ void accumulate(double (&acc)[KP], double t, uint64_t
   }
 }
 
+// Descriptor codecs.  Wide: {FP64 scale, 64 sign bits} (16 B).  Packed (8 B, KP <= 16 and
+// |x| <= 11): e^x has an unbiased binary exponent in [-16, 15], stored in 5 bits; the
+// low KP bits hold the probe signs and the mantissa keeps 52 - max(0, KP - 7) bits
+// (truncated: relative error below 2^-43 for KP = 16, exact for KP <= 7).  Halving the
+// gathered table keeps more of it in each XCD's L2, which sets the gather rate.
+template <int KP, bool PACKED>
+struct Codec;
+
 template <int KP>
+struct Codec<KP, false> {
+  using T = Desc;
+  __device__ static inline void decode(const T& d, double& scale, uint64_t& bits) {
+    scale = d.scale;
+    bits = d.bits;
+  }
+  __device__ static inline T encode(double scale, uint64_t bits) {
+    T d;
+    d.scale = scale;
+    d.bits = bits;
+    return d;
+  }
+};
+
+template <int KP>
+struct Codec<KP, true> {
+  using T = uint64_t;
+  static constexpr int kDrop = KP > 7 ? KP - 7 : 0;
+  static constexpr int kMant = 52 - kDrop;
+  __device__ static inline void decode(const T& d, double& scale, uint64_t& bits) {
+    bits = d & ((1ull << KP) - 1ull);
+    const uint64_t mant = ((d >> KP) & ((1ull << kMant) - 1ull)) << kDrop;
+    const uint64_t ex = (d >> 59) + 1007ull;
+    scale = __longlong_as_double((long long)((ex << 52) | mant));
+  }
+  __device__ static inline T encode(double scale, uint64_t bits) {
+    const uint64_t u = (uint64_t)__double_as_longlong(scale);
+    const uint64_t ex = ((u >> 52) & 0x7FFull) - 1007ull;
+    const uint64_t mant = (u & ((1ull << 52) - 1ull)) >> kDrop;
+    return (ex << 59) | (mant << KP) | bits;
+  }
+};
+
+// Per-index state is touched once per step: streamed with non-temporal hints so that it
+// does not evict the gathered descriptor table from L2.
+#ifndef MFE_NT_STATE
+#define MFE_NT_STATE 1
+#endif
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+#if MFE_NT_STATE
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+#if MFE_NT_STATE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(Desc* p, Desc v) {
+  u64x2 w;
+  w.x = (unsigned long long)__double_as_longlong(v.scale);
+  w.y = v.bits;
+  st_stream(reinterpret_cast<u64x2*>(p), w);
+}
+
+template <int KP, bool PACKED>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
+  using C = Codec<KP, PACKED>;
+  using DT = typename C::T;
   const int64_t r = blk * kBlock + threadIdx.x;
   if (r >= S.nint) return;  // nint is a multiple of 64: whole wavefronts leave together
   const int64_t s = r >> 6;
   const int lane = (int)(threadIdx.x & 63);
-  const int len = S.len[r];
+  const int len = ld_stream(S.len + r);
   const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
+  const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
   double acc[KP];
 #pragma unroll
   for (int p = 0; p < KP; ++p) acc[p] = 0.0;
-  for (int q = 0; q < len; ++q) {
-    const long long en = __builtin_nontemporal_load(e + (int64_t)q * kSlice);
-    const int32_t idx = (int32_t)(en & 0xFFFFFFFFll);
-    const float a = __int_as_float((int32_t)(en >> 32));
-    const Desc d = S.gather[idx];
-    accumulate<KP>(acc, (double)a * d.scale, d.bits);
+  // Batches of kBatch slots: all entry loads of a batch are issued, then all descriptor
+  // gathers, then the accumulation, so a wavefront keeps 2 x kBatch independent memory
+  // requests in flight instead of one dependent load/gather pair per slot.
+  for (int q0 = 0; q0 < len; q0 += kBatch) {
+    long long en[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      en[u] = (q0 + u < len) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
+    DT d[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (q0 + u < len) d[u] = gather[(int32_t)(en[u] & 0xFFFFFFFFll)];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      if (q0 + u < len) {
+        double scale;
+        uint64_t bits;
+        C::decode(d[u], scale, bits);
+        const float a = __int_as_float((int32_t)(en[u] >> 32));
+        accumulate<KP>(acc, (double)a * scale, bits);
+      }
+    }
   }
-  const int32_t li = S.orig[r];
+  const int32_t li = ld_stream(S.orig + r);
   if (li < 0) return;
   const MatDev mt = mats[S.slice_mat[s]];
   double ss = 0.0;
 #pragma unroll
   for (int p = 0; p < KP; ++p)
     if (p < k) ss += acc[p] * acc[p];
-  const double x_old = S.x[r];
+  const double x_old = ld_stream(S.x + r);
+  const double xbar_old = ld_stream(S.xbar + r);
   const double z = exp(2.0 * x_old) * (ss / (double)k);
   const double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
   const double g = (z - tgt) + sc.gamma * x_old;
   double xn = x_old - sc.eta * g;
   xn = fmin(fmax(xn, -sc.M), sc.M);
-  if (!isfinite(z) || !isfinite(xn)) atomicOr(flag, 1);
-  S.x[r] = xn;
-  S.xbar[r] = 2.0 * xn / (sc.tau + 2.0) + sc.tau * S.xbar[r] / (sc.tau + 2.0);
+  const bool bad = !isfinite(z) || !isfinite(xn);
+  if (bad) {
+    atomicOr(flag, 1);
+    xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
+  }
+  st_stream(S.x + r, xn);
+  st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
   const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
-  Desc nd;
-  nd.scale = exp(xn);
-  nd.bits = extract_bits(S.next_signs + wbase, (int64_t)li * k, k);
-  S.out[r] = nd;
+  st_stream(reinterpret_cast<DT*>(S.out) + r,
+            C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
 }
 
 __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk) {
@@ -99,30 +193,36 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk)
   o[3] = w.x[3];
 }
 
-template <int KP>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a) {
+// One direction of one step; extra workgroups past side_blocks draw the sign words
+// of step t+2 (the row launch carries them).
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
   const int64_t b = blockIdx.x;
-  if (b < a.row_blocks) side_update<KP>(a.rows, a.mats, a.k, a.sc, b, a.flag);
-  else if (b < a.row_blocks + a.col_blocks) side_update<KP>(a.cols, a.mats, a.k, a.sc, b - a.row_blocks, a.flag);
-  else signgen_block(a.gen, b - a.row_blocks - a.col_blocks);
+  if (b < a.side_blocks) side_update<KP, PACKED>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else signgen_block(a.gen, b - a.side_blocks);
 }
 
 __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
 
-__global__ void k_init(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ x0, int k) {
+template <int KP, bool PACKED>
+__global__ void k_init(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ x0, int k, double M,
+                       int* flag) {
+  using C = Codec<KP, PACKED>;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= S.nint) return;
   const int32_t li = S.orig[r];
   if (li < 0) return;
   const MatDev mt = mats[S.slice_mat[r >> 6]];
   const int64_t g = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
-  const double x = x0 ? x0[g] : 0.0;
+  double x = x0 ? x0[g] : 0.0;
+  if (!(fabs(x) <= M)) {
+    atomicOr(flag, 2);  // warm start outside the box (or NaN)
+    x = 0.0;
+  }
   S.x[r] = x;
   S.xbar[r] = x;
-  Desc nd;
-  nd.scale = exp(x);
-  nd.bits = extract_bits(S.next_signs + (S.is_row ? mt.sign_word_row : mt.sign_word_col), (int64_t)li * k, k);
-  S.out[r] = nd;
+  const uint64_t bits = extract_bits(S.next_signs + (S.is_row ? mt.sign_word_row : mt.sign_word_col), (int64_t)li * k, k);
+  reinterpret_cast<typename C::T*>(S.out)[r] = C::encode(exp(x), bits);
 }
 
 __global__ void k_output(SideDev S, const MatDev* __restrict__ mats, double* __restrict__ dout,
@@ -204,7 +304,7 @@ SignGenDev make_gen(const mfe_plan* p, uint64_t seed, uint64_t step, uint64_t* o
   return g;
 }
 
-SideDev make_side(const SideLayout& L, double* x, double* xbar, const Desc* gather, Desc* out,
+SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gather, void* out,
                   const uint64_t* next_signs, int is_row) {
   SideDev S;
   S.slice_off = L.slice_off;
@@ -222,22 +322,48 @@ SideDev make_side(const SideLayout& L, double* x, double* xbar, const Desc* gath
   return S;
 }
 
-template <int KP>
-void launch_step(const StepArgs& a, hipStream_t st) {
-  const int64_t grid = a.row_blocks + a.col_blocks + a.gen_blocks;
-  k_step<KP><<<dim3((unsigned)grid), dim3(kBlock), 0, st>>>(a);
+template <int KP, bool PACKED>
+void launch_phase(const PhaseArgs& a, hipStream_t st) {
+  k_phase<KP, PACKED><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
 }
 
-void launch_step_k(const StepArgs& a, hipStream_t st) {
-  const int k = a.k;
-  if (k <= 1) launch_step<1>(a, st);
-  else if (k <= 2) launch_step<2>(a, st);
-  else if (k <= 4) launch_step<4>(a, st);
-  else if (k <= 8) launch_step<8>(a, st);
-  else if (k <= 16) launch_step<16>(a, st);
-  else if (k <= 32) launch_step<32>(a, st);
-  else launch_step<64>(a, st);
+template <int KP, bool PACKED>
+void launch_init(const SideDev& S, const MatDev* mats, const double* x0, int k, double M, int* flag, hipStream_t st) {
+  k_init<KP, PACKED><<<dim3((unsigned)ceil_div(S.nint, 256)), dim3(256), 0, st>>>(S, mats, x0, k, M, flag);
 }
+
+// Dispatch on the probe bucket KP >= k and on the descriptor format.
+template <template <int, bool> class F, class... Args>
+void dispatch(int k, bool packed, Args&&... args) {
+  if (packed) {
+    if (k <= 1) F<1, true>::run(args...);
+    else if (k <= 2) F<2, true>::run(args...);
+    else if (k <= 4) F<4, true>::run(args...);
+    else if (k <= 8) F<8, true>::run(args...);
+    else F<16, true>::run(args...);
+  } else {
+    if (k <= 1) F<1, false>::run(args...);
+    else if (k <= 2) F<2, false>::run(args...);
+    else if (k <= 4) F<4, false>::run(args...);
+    else if (k <= 8) F<8, false>::run(args...);
+    else if (k <= 16) F<16, false>::run(args...);
+    else if (k <= 32) F<32, false>::run(args...);
+    else F<64, false>::run(args...);
+  }
+}
+
+template <int KP, bool PACKED>
+struct PhaseLauncher {
+  static void run(const PhaseArgs& a, hipStream_t st) { launch_phase<KP, PACKED>(a, st); }
+};
+
+template <int KP, bool PACKED>
+struct InitLauncher {
+  static void run(const SideDev& S, const MatDev* mats, const double* x0, int k, double M, int* flag,
+                  hipStream_t st) {
+    launch_init<KP, PACKED>(S, mats, x0, k, M, flag, st);
+  }
+};
 
 }  // namespace
 
@@ -292,26 +418,33 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
 
   const uint64_t seed = prm->seed;
   const int T = prm->steps;
+  // 8-byte descriptors whenever k <= 16 and the box keeps e^x inside the packed range
+  const bool packed = k <= 16 && prm->box_M <= 11.0;
   // signs of step 1 -> slot 1, of step 2 -> slot 0
   MFE_CHECK(launch_signgen(make_gen(p, seed, 1, p->signs[1]), st));
   MFE_CHECK(launch_signgen(make_gen(p, seed, 2, p->signs[0]), st));
   {
     SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[0], p->signs[1], 1);
     SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[0], p->signs[1], 0);
-    k_init<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, st>>>(R, p->mats, prm->u0, k);
-    k_init<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(C, p->mats, prm->v0, k);
+    dispatch<InitLauncher>(k, packed, R, (const MatDev*)p->mats, prm->u0, k, prm->box_M, p->flag, st);
+    dispatch<InitLauncher>(k, packed, C, (const MatDev*)p->mats, prm->v0, k, prm->box_M, p->flag, st);
     MFE_HIP(hipGetLastError());
   }
 
-  auto step_args = [&](int t) {
-    StepArgs a;
+  // Step t = two launches (Jacobi order: both read the descriptors of step t-1):
+  // the row direction (plus the sign words of step t+2), then the column direction.
+  // Keeping the directions apart lets each launch's L2 hold only the table it gathers.
+  auto phase_args = [&](int t, bool rows) {
+    PhaseArgs a;
     const int par = t & 1, prev = par ^ 1;
-    a.rows = make_side(p->rows, p->x_row, p->xbar_row, p->desc_col[prev], p->desc_row[par],
-                       p->signs[(t + 1) & 1], 1);
-    a.cols = make_side(p->cols, p->x_col, p->xbar_col, p->desc_row[prev], p->desc_col[par],
-                       p->signs[(t + 1) & 1], 0);
+    if (rows)
+      a.side = make_side(p->rows, p->x_row, p->xbar_row, p->desc_col[prev], p->desc_row[par],
+                         p->signs[(t + 1) & 1], 1);
+    else
+      a.side = make_side(p->cols, p->x_col, p->xbar_col, p->desc_row[prev], p->desc_col[par],
+                         p->signs[(t + 1) & 1], 0);
     const uint64_t gen_step = (uint64_t)t + 2;
-    const bool gen = (int64_t)gen_step <= (int64_t)T + 1;
+    const bool gen = rows && (int64_t)gen_step <= (int64_t)T + 1;
     a.gen = make_gen(p, seed, gen_step, p->signs[t & 1]);
     a.mats = p->mats;
     a.k = k;
@@ -320,14 +453,19 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     a.sc.eta = 2.0 / (prm->gamma * (tau + 1.0));
     a.sc.gamma = prm->gamma;
     a.sc.M = prm->box_M;
-    a.row_blocks = ceil_div(nr, kBlock);
-    a.col_blocks = ceil_div(nc, kBlock);
+    a.side_blocks = ceil_div(rows ? nr : nc, kBlock);
     a.gen_blocks = gen ? ceil_div(p->sign_blocks, kBlock) : 0;
     a.flag = p->flag;
     return a;
   };
+  auto launch_steps = [&](hipStream_t s) {
+    for (int t = 1; t <= T; ++t) {
+      dispatch<PhaseLauncher>(k, packed, phase_args(t, true), s);
+      dispatch<PhaseLauncher>(k, packed, phase_args(t, false), s);
+    }
+  };
 
-  // The step loop runs either as T launches or as one cached HIP graph of those T
+  // The step loop runs either as 2T launches or as one cached HIP graph of those
   // launches (captured once per (k, T, t0, gamma, M, seed, batch)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
@@ -342,7 +480,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       p->graph_exec = nullptr;
       p->graph = nullptr;
       MFE_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-      for (int t = 1; t <= T; ++t) launch_step_k(step_args(t), p->cap_stream);
+      launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
       for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
@@ -357,7 +495,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     MFE_HIP(hipEventRecord(p->ev1, run_st));
   } else {
     MFE_HIP(hipEventRecord(p->ev0, run_st));
-    for (int t = 1; t <= T; ++t) launch_step_k(step_args(t), run_st);
+    launch_steps(run_st);
     MFE_HIP(hipGetLastError());
     MFE_HIP(hipEventRecord(p->ev1, run_st));
   }
@@ -376,7 +514,8 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   MFE_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
   p->last_loop_ms = ms;
   p->last_step_ms = T > 0 ? ms / T : 0.0;
-  if (flag) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
+  if (flag & 2) return set_error(MFE_EINVAL, "warm start u0/v0 outside the box [-M, M] (or NaN)");
+  if (flag & 1) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
   return MFE_OK;
 }
 
