@@ -62,11 +62,12 @@ typedef enum {
 
 /* Matrix-free operator (the setting of Section 3): Y = A X (trans = 0, X is n x k,
  * Y is m x k) or Y = A' X (trans = 1, X is m x k, Y is n x k).  Row-major blocks:
- * element (i, p) at X[i*ldx + p].  FP32, device pointers, work ordered on `stream`
- * (a hipStream_t).  Returns 0 on success; any other value aborts the run with
- * MFE_EDEVICE. */
-typedef int (*mfe_apply_fn)(void* ctx, int trans, int32_t k, const float* X, int64_t ldx,
-                            float* Y, int64_t ldy, void* stream);
+ * element (i, p) at X[i*ldx + p].  FP64 device pointers (the iteration amplifies
+ * rounding in its first steps, so FP32 products cannot track the FP64 method closely),
+ * work ordered on `stream` (a hipStream_t).  Returns 0 on success; any other value
+ * aborts the run with MFE_EDEVICE. */
+typedef int (*mfe_apply_fn)(void* ctx, int trans, int32_t k, const double* X, int64_t ldx,
+                            double* Y, int64_t ldy, void* stream);
 
 typedef struct {
   int32_t kind;               /* mfe_kind */
@@ -113,6 +114,9 @@ int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta);
  * d [m] = e^u_bar, e [n] = e^v_bar (required); u_bar [m], v_bar [n] (nullable).
  * CSR and dense kinds run fused HIP kernels; the operator kind calls apply() twice per
  * step and runs the square/step/project update in the library's kernels.
+ * MFE_DENSE_BF16 runs both products on the matrix cores: probe operands are exact signs
+ * times bf16(e^x), products accumulate in FP32, iterates stay FP64 (the library keeps
+ * two tiled copies of A, 2 x 2mn bytes of device memory, for the call's duration).
  * EINVAL: alpha, beta, gamma or M <= 0 or not finite; steps < 0; probes outside 1..256;
  * t0 < 0; a required pointer NULL.  EDIM: m or n <= 0, nnz >= 2^31, ld < n.
  * EUNSUPPORTED: CSR/dense with probes > 64, or a kind not built.
@@ -142,6 +146,11 @@ int mfe_plan_equilibrate(mfe_plan* plan, const mfe_equil_params* p, const double
 int mfe_plan_last_timing(const mfe_plan* plan, double* loop_ms, double* step_kernel_ms);
 
 int mfe_plan_destroy(mfe_plan* plan);
+
+/* Timing of the step loop of the last mfe_equilibrate on the calling thread (dense
+ * BF16 path): milliseconds for all T steps and per step (HIP events on the stream).
+ * Host pointers (nullable). */
+int mfe_last_timing(double* loop_ms, double* step_ms);
 
 /* LSQR (Paige & Saunders) on (D A E) xbar = D b, x = E xbar (Section 5.1), FP64
  * vectors and recurrences, A values FP32 (CSR) or FP64 (dense).  b [m], d [m], e [n]

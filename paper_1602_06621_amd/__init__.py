@@ -21,6 +21,7 @@ from ._ffi import (  # noqa: F401
     draw_signs,
     equilibrate,
     last_error,
+    last_timing,
     library_path,
     lsqr,
     residual,

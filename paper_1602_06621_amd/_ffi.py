@@ -26,6 +26,7 @@ class MfeError(RuntimeError):
         self.name = STATUS.get(status, str(status))
 
 
+# int apply(void* ctx, int trans, int32 k, const double* X, int64 ldx, double* Y, int64 ldy, void* stream)
 APPLY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                        C.c_int64, C.c_void_p)
 
@@ -70,6 +71,7 @@ def _lib():
         "mfe_plan_create": [C.POINTER(_Matrix), i32, i32, vp, C.POINTER(vp)],
         "mfe_plan_equilibrate": [vp, C.POINTER(_Params), vp, vp, i32, vp, vp, vp, vp],
         "mfe_plan_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl)],
+        "mfe_last_timing": [C.POINTER(dbl), C.POINTER(dbl)],
         "mfe_plan_destroy": [vp],
         "mfe_lsqr": [C.POINTER(_Matrix), vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_LsqrInfo), vp],
         "mfe_plan_lsqr": [vp, vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_LsqrInfo), vp],
@@ -187,8 +189,9 @@ class Dense:
 
 
 class Operator:
-    """Matrix-free operator: apply(trans, k, X, Y) fills the FP32 device block Y (row-major)
-    with A X (trans = 0) or A' X (trans = 1) on the current stream."""
+    """Matrix-free operator: apply(trans, k, X, ldx, Y, ldy, rows_in, rows_out, stream) fills
+    the FP64 device block Y (row-major, rows_out x k) with A X (trans = 0) or A' X
+    (trans = 1); X and Y are raw device addresses, work goes on `stream`."""
 
     def __init__(self, m: int, n: int, apply):
         self.m, self.n = int(m), int(n)
@@ -223,6 +226,13 @@ def _params(alpha, beta, gamma, M, steps, probes, seed, t0, batch, u0, v0, strea
     p.v0 = _ptr(v0, torch.float64, "v0")
     p.stream = _stream(stream)
     return p
+
+
+def last_timing():
+    """Step-loop timing of the last equilibrate() on this thread (dense BF16 path)."""
+    a, b = C.c_double(), C.c_double()
+    _check(_lib().mfe_last_timing(C.byref(a), C.byref(b)))
+    return dict(loop_ms=a.value, step_ms=b.value)
 
 
 def default_alpha_beta(m: int, n: int):

@@ -10,6 +10,12 @@ namespace mfe {
 
 namespace {
 thread_local std::string g_last_error;
+thread_local double g_loop_ms = 0.0, g_step_ms = 0.0;
+}
+
+void record_timing(double loop_ms, double step_ms) {
+  g_loop_ms = loop_ms;
+  g_step_ms = step_ms;
 }
 
 int set_error(int status, const char* fmt, ...) {
@@ -136,6 +142,12 @@ int mfe_plan_equilibrate(mfe_plan* plan, const mfe_equil_params* p, const double
   MFE_CHECK(check_params(p, alpha_b == nullptr || beta_b == nullptr));
   if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "sparse path supports at most 64 probes per step");
   return plan_run(plan, p, alpha_b, beta_b, use_graph, d, e, u_bar, v_bar);
+}
+
+int mfe_last_timing(double* loop_ms, double* step_ms) {
+  if (loop_ms) *loop_ms = g_loop_ms;
+  if (step_ms) *step_ms = g_step_ms;
+  return MFE_OK;
 }
 
 int mfe_plan_last_timing(const mfe_plan* plan, double* loop_ms, double* step_kernel_ms) {

@@ -17,6 +17,8 @@ namespace mfe {
 // Records a message for mfe_last_error() and returns the status.
 int set_error(int status, const char* fmt, ...);
 void clear_error();
+// Step-loop timing of the last equilibration on this thread (HIP events on its stream).
+void record_timing(double loop_ms, double step_ms);
 void set_warning(const char* fmt, ...);
 
 #define MFE_HIP(call)                                                                   \
@@ -33,6 +35,15 @@ void set_warning(const char* fmt, ...);
     int _s = (status_expr);           \
     if (_s != MFE_OK) return _s;      \
   } while (0)
+
+// Per-step scalars, computed on the host exactly as the oracle writes them.
+struct StepScalars {
+  double eta;   // 2 / (gamma (tau + 1))
+  double tau;   // t + t0
+  double gamma;
+  double M;
+};
+using StepScalarsFwd = StepScalars;
 
 // ----------------------------------------------------------------- probe signs
 //
@@ -91,6 +102,41 @@ __device__ inline uint64_t extract_bits(const uint64_t* __restrict__ words, int6
   return k == 64 ? v : (v & ((1ull << k) - 1ull));
 }
 
+// acc_p += (-1)^bit_p * t for p < KP.  The sign of t is folded into the probe bits so
+// each probe costs one shift, one and-or on the high word and one FP64 add.
+template <int KP>
+__device__ __forceinline__ void accumulate_signed(double (&acc)[KP], double t, uint64_t bits) {
+  const uint64_t tb = (uint64_t)__double_as_longlong(t);
+  const uint32_t lo = (uint32_t)tb;
+  const uint32_t hi_abs = (uint32_t)(tb >> 32) & 0x7FFFFFFFu;
+  if (tb >> 63) bits = ~bits;
+  const uint32_t b0 = (uint32_t)bits;
+  const uint32_t b1 = (uint32_t)(bits >> 32);
+#pragma unroll
+  for (int p = 0; p < KP; ++p) {
+    const uint32_t sb = p < 32 ? ((b0 << (31 - (p & 31))) & 0x80000000u)
+                               : ((b1 << (31 - (p & 31))) & 0x80000000u);
+    acc[p] += __longlong_as_double((long long)(((uint64_t)(hi_abs | sb) << 32) | lo));
+  }
+}
+
+// Projected step of Algorithm 1 for one index: z = e^(2x) * (sum of squares / k),
+// x <- clip(x - eta (z - target + gamma x), -M, M), average update with weight tau.
+// Returns false if z or the new iterate is not finite.
+__device__ __forceinline__ bool sgd_update(double ss, int k, double target, const StepScalarsFwd& sc,
+                                           double& x, double& xbar) {
+  const double x_old = x;
+  const double z = exp(2.0 * x_old) * (ss / (double)k);
+  const double g = (z - target) + sc.gamma * x_old;
+  double xn = x_old - sc.eta * g;
+  xn = fmin(fmax(xn, -sc.M), sc.M);
+  const bool ok = isfinite(z) && isfinite(xn);
+  if (!ok) xn = 0.0;
+  x = xn;
+  xbar = 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar / (sc.tau + 2.0);
+  return ok;
+}
+
 // Gathered per-index record of the sparse path: the scale e^x of the index (FP64) and
 // the sign bits of its probes for the step that consumes it.
 struct __align__(16) Desc {
@@ -100,12 +146,5 @@ struct __align__(16) Desc {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Per-step scalars, computed on the host exactly as the oracle writes them.
-struct StepScalars {
-  double eta;   // 2 / (gamma (tau + 1))
-  double tau;   // t + t0
-  double gamma;
-  double M;
-};
 
 }  // namespace mfe

@@ -1,0 +1,644 @@
+// LSQR on the equilibrated system (Section 5.1) and the RMS equilibration error
+// (Section 4), for the sparse layouts of a plan and for dense FP64 matrices.
+//
+// LSQR is the Golub-Kahan bidiagonalisation method of Paige & Saunders applied to
+// Abar = D A E, bbar = D b; x = E xbar.  Every iteration is one product with Abar and
+// one with Abar' (the cost unit of Section 5.1).  Vectors and recurrences are FP64;
+// reductions are two-stage (per-block partials, then one block in a fixed order), so
+// results are deterministic.  The scalar recurrence runs on the device; the host only
+// reads the scalars at the residual checks.
+#include <cmath>
+#include <vector>
+
+#include "dense.h"
+#include "sparse.h"
+
+namespace mfe {
+namespace {
+
+constexpr int kRed = 256;  // threads of the product / reduction kernels
+
+// Device scalars of one LSQR run.
+struct LsqrScal {
+  double alpha, beta;          // current alpha_i, beta_{i+1}
+  double rhobar, phibar;       // rotation state
+  double phi_rho, theta_rho;   // update coefficients of x and w
+  double anorm2;               // Frobenius estimate of ||Abar||^2
+  double normal_eq;            // ||Abar' r|| / (||Abar|| ||r||) estimate
+  double neg_alpha, neg_beta, inv_beta, inv_alpha;
+  double bnorm2, res2;         // ||b||^2 and ||A x - b||^2 at the last check
+  double neg_one;
+  int breakdown;               // iteration at which alpha or beta became 0 (0: none)
+  int iter;
+};
+
+// Sum of 256 doubles of a block, fixed order (tree in LDS).
+__device__ double block_sum(double v) {
+  __shared__ double sh[kRed];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kRed / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- sliced products
+//
+// y_r = sout_r * inv * sum_q a_q g[idx_q] + coef * yprev_r  over the rows r of one
+// direction of a plan (internal order); gout_r = sout_r * y_r when requested; block
+// partial of sum y_r^2.  inv and coef are read from device memory (nullable = 1, 0).
+__global__ __launch_bounds__(kRed) void k_sell_product(SideDev S, const double* __restrict__ sout,
+                                                       const double* __restrict__ g, const double* inv,
+                                                       const double* coef, const double* __restrict__ yprev,
+                                                       double* __restrict__ y, double* __restrict__ gout,
+                                                       double* __restrict__ partial) {
+  const int64_t r = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  double contrib = 0.0;
+  if (r < S.nint) {
+    const int64_t s = r >> 6;
+    const int lane = (int)(r & 63);
+    const int len = S.len[r];
+    const int2* e = S.ent + S.slice_off[s] + lane;
+    double acc = 0.0;
+    for (int q = 0; q < len; ++q) {
+      const int2 en = e[(int64_t)q * kSlice];
+      acc += (double)__int_as_float(en.y) * g[en.x];
+    }
+    if (S.orig[r] >= 0) {
+      const double so = sout ? sout[r] : 1.0;
+      double v = so * (acc * (inv ? *inv : 1.0));
+      if (coef) v += *coef * yprev[r];
+      y[r] = v;
+      if (gout) gout[r] = so * v;
+      contrib = v * v;
+    }
+  }
+  const double bs = block_sum(contrib);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+}
+
+// RMS-residual pass over one direction: s_r = sum_q a_q^2 g2[idx_q] (g2 = squared scales
+// of the other side), r_r = own2_r * s_r; partials of (sqrt(r) - target)^2 over all
+// rows, over non-empty rows, and the count of empty rows.
+__global__ __launch_bounds__(kRed) void k_sell_rownorm(SideDev S, const double* __restrict__ own2,
+                                                       const double* __restrict__ g2, double target,
+                                                       double* __restrict__ p_all, double* __restrict__ p_ne,
+                                                       double* __restrict__ p_empty) {
+  const int64_t r = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  double all = 0.0, ne = 0.0, em = 0.0;
+  if (r < S.nint && S.orig[r] >= 0) {
+    const int64_t s = r >> 6;
+    const int lane = (int)(r & 63);
+    const int len = S.len[r];
+    const int2* e = S.ent + S.slice_off[s] + lane;
+    double acc = 0.0;
+    for (int q = 0; q < len; ++q) {
+      const int2 en = e[(int64_t)q * kSlice];
+      const double a = (double)__int_as_float(en.y);
+      acc += a * a * g2[en.x];
+    }
+    const double dev = sqrt((own2 ? own2[r] : 1.0) * acc) - target;
+    all = dev * dev;
+    if (len > 0) ne = all;
+    else em = 1.0;
+  }
+  const double a = block_sum(all), b = block_sum(ne), c = block_sum(em);
+  if (threadIdx.x == 0) {
+    p_all[blockIdx.x] = a;
+    p_ne[blockIdx.x] = b;
+    p_empty[blockIdx.x] = c;
+  }
+}
+
+// Original order <-> internal order of one direction.  op: 0 copy, 1 square.
+__global__ void k_to_internal(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ src,
+                              double fill, int op, double* __restrict__ dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.nint) return;
+  const int32_t li = S.orig[r];
+  if (li < 0) {
+    dst[r] = 0.0;
+    return;
+  }
+  const MatDev mt = mats[S.slice_mat[r >> 6]];
+  const int64_t gi = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
+  const double v = src ? src[gi] : fill;
+  dst[r] = op == 1 ? v * v : v;
+}
+
+__global__ void k_from_internal(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ src,
+                                const double* __restrict__ scale, double* __restrict__ dst) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.nint) return;
+  const int32_t li = S.orig[r];
+  if (li < 0) return;
+  const MatDev mt = mats[S.slice_mat[r >> 6]];
+  const int64_t gi = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
+  dst[gi] = scale ? scale[r] * src[r] : src[r];
+}
+
+// ---------------------------------------------------------------- dense FP64 products
+//
+// Row-major A (m x n, leading dimension ld).  Forward: one wavefront per row.
+__global__ __launch_bounds__(kRed) void k_dense_fwd(const double* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                                    const double* __restrict__ sout, const double* __restrict__ g,
+                                                    const double* inv, const double* coef,
+                                                    const double* __restrict__ yprev, double* __restrict__ y,
+                                                    double* __restrict__ gout, double* __restrict__ partial) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (kRed / 64) + wave;
+  double contrib = 0.0;
+  if (i < m) {
+    double acc = 0.0;
+    for (int64_t j = lane; j < n; j += 64) acc += A[i * ld + j] * g[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      const double so = sout ? sout[i] : 1.0;
+      double v = so * (acc * (inv ? *inv : 1.0));
+      if (coef) v += *coef * yprev[i];
+      y[i] = v;
+      if (gout) gout[i] = so * v;
+      contrib = v * v;
+    }
+  }
+  const double bs = block_sum(contrib);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+}
+
+// Transposed: one thread per column, coalesced across the columns of a row.
+__global__ __launch_bounds__(kRed) void k_dense_bwd(const double* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                                    const double* __restrict__ sout, const double* __restrict__ g,
+                                                    const double* inv, const double* coef,
+                                                    const double* __restrict__ yprev, double* __restrict__ y,
+                                                    double* __restrict__ gout, double* __restrict__ partial) {
+  const int64_t j = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  double contrib = 0.0;
+  if (j < n) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < m; ++i) acc += A[i * ld + j] * g[i];
+    const double so = sout ? sout[j] : 1.0;
+    double v = so * (acc * (inv ? *inv : 1.0));
+    if (coef) v += *coef * yprev[j];
+    y[j] = v;
+    if (gout) gout[j] = so * v;
+    contrib = v * v;
+  }
+  const double bs = block_sum(contrib);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+}
+
+// Dense residual passes (squared entries).
+__global__ __launch_bounds__(kRed) void k_dense_rownorm(const double* __restrict__ A, int64_t m, int64_t n, int64_t ld,
+                                                        int trans, const double* __restrict__ own, const double* __restrict__ other,
+                                                        double target, double* p_all, double* p_ne, double* p_empty) {
+  const int64_t i = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  const int64_t cnt = trans ? n : m, len = trans ? m : n;
+  double all = 0.0, ne = 0.0, em = 0.0;
+  if (i < cnt) {
+    double acc = 0.0;
+    int64_t nz = 0;
+    for (int64_t q = 0; q < len; ++q) {
+      const double a = trans ? A[q * ld + i] : A[i * ld + q];
+      const double o = other ? other[q] : 1.0;
+      acc += a * a * o * o;
+      nz += (a != 0.0);
+    }
+    const double w = own ? own[i] : 1.0;
+    const double dev = sqrt(w * w * acc) - target;
+    all = dev * dev;
+    if (nz > 0) ne = all;
+    else em = 1.0;
+  }
+  const double a = block_sum(all), b = block_sum(ne), c = block_sum(em);
+  if (threadIdx.x == 0) {
+    p_all[blockIdx.x] = a;
+    p_ne[blockIdx.x] = b;
+    p_empty[blockIdx.x] = c;
+  }
+}
+
+// ---------------------------------------------------------------- reductions + scalars
+
+// out[0] = sum of partial[0..n) in a fixed order.
+__global__ __launch_bounds__(kRed) void k_reduce(const double* __restrict__ partial, int64_t n, double* out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) *out = t;
+}
+
+// After the forward product: beta = ||p||, coefficients for the transposed product.
+// The partial sums of the forward pass are reduced here.
+__global__ __launch_bounds__(kRed) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(t);
+    sc->beta = beta;
+    sc->anorm2 += sc->alpha * sc->alpha + beta * beta;
+    sc->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+    sc->neg_beta = -beta;
+    if (beta == 0.0 && sc->breakdown == 0) sc->breakdown = sc->iter;
+  }
+}
+
+// After the transposed product: alpha_{i+1} = ||q|| and the plane rotation.  init != 0
+// is the start of the method (alpha_1 v_1 = Abar' u_1, phibar = beta_1, rhobar = alpha_1).
+__global__ __launch_bounds__(kRed) void k_scal_alpha(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
+                                                     int init) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
+  const double t = block_sum(s);
+  if (threadIdx.x == 0) {
+    const double an = sqrt(t);
+    sc->inv_alpha = an > 0.0 ? 1.0 / an : 0.0;
+    if (init) {
+      sc->phibar = sc->beta;
+      sc->rhobar = an;
+      sc->alpha = an;
+      sc->neg_alpha = -an;
+      sc->anorm2 = 0.0;
+      if (an == 0.0 && sc->breakdown == 0) sc->breakdown = -1;
+      return;
+    }
+    if (sc->breakdown == 0 || sc->breakdown == sc->iter) {
+      const double beta = sc->beta;
+      const double rho = hypot(sc->rhobar, beta);
+      const double c = sc->rhobar / rho, sn = beta / rho;
+      const double theta = sn * an;
+      sc->rhobar = -c * an;
+      const double phi = c * sc->phibar;
+      sc->phibar = sn * sc->phibar;
+      sc->phi_rho = phi / rho;
+      sc->theta_rho = theta / rho;
+      sc->normal_eq = an * fabs(c) / sqrt(sc->anorm2);
+      if (an == 0.0) sc->breakdown = sc->iter;
+    } else {
+      sc->phi_rho = 0.0;  // after a breakdown x stays fixed
+      sc->theta_rho = 0.0;
+    }
+    sc->alpha = an;
+    sc->neg_alpha = -an;
+  }
+}
+
+// Elementwise: v = q / alpha; x += phi/rho w; w = v - theta/rho w; ev = escale v
+// (column direction), and u = p / beta (row direction).  init: w = v, x = 0.
+__global__ void k_lsqr_update(int64_t ncol, int64_t nrow, const LsqrScal* __restrict__ sc, int init,
+                              double* __restrict__ v, double* __restrict__ w, double* __restrict__ x,
+                              double* __restrict__ ev, const double* __restrict__ escale, double* __restrict__ u,
+                              const int32_t* __restrict__ col_valid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool frozen = sc->breakdown != 0 && sc->breakdown != sc->iter && !init;
+  if (i < ncol) {
+    if (frozen) return;
+    const double vi = v[i] * sc->inv_alpha;
+    if (init) {
+      w[i] = vi;
+      x[i] = 0.0;
+    } else {
+      const double wi = w[i];
+      x[i] += sc->phi_rho * wi;
+      w[i] = vi - sc->theta_rho * wi;
+    }
+    v[i] = vi;
+    ev[i] = (col_valid && col_valid[i] < 0) ? 0.0 : (escale ? escale[i] : 1.0) * vi;
+  } else if (i < ncol + nrow) {
+    if (frozen) return;
+    const int64_t r = i - ncol;
+    u[r] *= sc->inv_beta;
+  }
+}
+
+__global__ void k_scal_init(LsqrScal* sc) {
+  LsqrScal z;
+  z.alpha = z.beta = z.rhobar = z.phibar = z.phi_rho = z.theta_rho = 0.0;
+  z.anorm2 = z.normal_eq = z.neg_alpha = z.neg_beta = 0.0;
+  z.inv_beta = z.inv_alpha = 1.0;
+  z.bnorm2 = z.res2 = 0.0;
+  z.neg_one = -1.0;
+  z.breakdown = 0;
+  z.iter = 0;
+  *sc = z;
+}
+
+__global__ void k_scal_iter(LsqrScal* sc, int it) { sc->iter = it; }
+
+__global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (a ? a[i] : 1.0) * b[i];
+}
+
+// ---------------------------------------------------------------- operator abstraction
+
+struct Work {
+  std::vector<void*> bufs;
+  ~Work() {
+    for (void* p : bufs) (void)hipFree(p);
+  }
+  template <class T>
+  int alloc(T** p, int64_t n) {
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    if (e != hipSuccess)
+      return set_error(e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EDEVICE, "hipMalloc failed: %s",
+                       hipGetErrorString(e));
+    bufs.push_back(*p);
+    return MFE_OK;
+  }
+};
+
+// Products y = sout * inv * (A or A') g + coef * yprev, with partial sums of y^2.
+struct Ops {
+  virtual ~Ops() {}
+  virtual int64_t rows() const = 0;  // length of row-direction vectors
+  virtual int64_t cols() const = 0;
+  virtual int64_t fwd_blocks() const = 0;
+  virtual int64_t bwd_blocks() const = 0;
+  virtual void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev,
+                   double* y, double* gout, double* partial, hipStream_t st) const = 0;
+  virtual void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev,
+                   double* y, double* gout, double* partial, hipStream_t st) const = 0;
+  // original <-> operator order
+  virtual void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const = 0;
+  virtual void from_op(bool row, const double* src, const double* scale, double* dst, hipStream_t st) const = 0;
+  virtual const int32_t* col_valid() const { return nullptr; }
+};
+
+struct SellOps : Ops {
+  mfe_plan* p;
+  SideDev R, C;
+  explicit SellOps(mfe_plan* plan) : p(plan) {
+    R = SideDev{};
+    C = SideDev{};
+    R.slice_off = p->rows.slice_off;
+    R.slice_mat = p->rows.slice_mat;
+    R.len = p->rows.len;
+    R.orig = p->rows.orig;
+    R.ent = p->rows.ent;
+    R.nint = p->rows.nint;
+    R.is_row = 1;
+    C.slice_off = p->cols.slice_off;
+    C.slice_mat = p->cols.slice_mat;
+    C.len = p->cols.len;
+    C.orig = p->cols.orig;
+    C.ent = p->cols.ent;
+    C.nint = p->cols.nint;
+    C.is_row = 0;
+  }
+  int64_t rows() const override { return p->rows.nint; }
+  int64_t cols() const override { return p->cols.nint; }
+  int64_t fwd_blocks() const override { return ceil_div(p->rows.nint, kRed); }
+  int64_t bwd_blocks() const override { return ceil_div(p->cols.nint, kRed); }
+  void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
+           double* gout, double* partial, hipStream_t st) const override {
+    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kRed), 0, st>>>(R, sout, g, inv, coef, yprev, y, gout, partial);
+  }
+  void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
+           double* gout, double* partial, hipStream_t st) const override {
+    k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kRed), 0, st>>>(C, sout, g, inv, coef, yprev, y, gout, partial);
+  }
+  void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const override {
+    const SideDev& S = row ? R : C;
+    k_to_internal<<<dim3((unsigned)ceil_div(S.nint, 256)), dim3(256), 0, st>>>(S, p->mats, src, fill, op, dst);
+  }
+  void from_op(bool row, const double* src, const double* scale, double* dst, hipStream_t st) const override {
+    const SideDev& S = row ? R : C;
+    k_from_internal<<<dim3((unsigned)ceil_div(S.nint, 256)), dim3(256), 0, st>>>(S, p->mats, src, scale, dst);
+  }
+  const int32_t* col_valid() const override { return p->cols.orig; }
+};
+
+__global__ void k_copy_scaled(int64_t n, const double* __restrict__ src, double fill, int op, double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = src ? src[i] : fill;
+  dst[i] = op == 1 ? v * v : v;
+}
+
+__global__ void k_mul_into(int64_t n, const double* __restrict__ src, const double* __restrict__ scale,
+                           double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = scale ? scale[i] * src[i] : src[i];
+}
+
+struct DenseOps : Ops {
+  const double* A;
+  int64_t m, n, ld;
+  DenseOps(const double* a, int64_t m_, int64_t n_, int64_t ld_) : A(a), m(m_), n(n_), ld(ld_) {}
+  int64_t rows() const override { return m; }
+  int64_t cols() const override { return n; }
+  int64_t fwd_blocks() const override { return ceil_div(m, kRed / 64); }
+  int64_t bwd_blocks() const override { return ceil_div(n, kRed); }
+  void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
+           double* gout, double* partial, hipStream_t st) const override {
+    k_dense_fwd<<<dim3((unsigned)fwd_blocks()), dim3(kRed), 0, st>>>(A, m, n, ld, sout, g, inv, coef, yprev, y, gout,
+                                                                     partial);
+  }
+  void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
+           double* gout, double* partial, hipStream_t st) const override {
+    k_dense_bwd<<<dim3((unsigned)bwd_blocks()), dim3(kRed), 0, st>>>(A, m, n, ld, sout, g, inv, coef, yprev, y, gout,
+                                                                     partial);
+  }
+  void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const override {
+    const int64_t cnt = row ? m : n;
+    k_copy_scaled<<<dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st>>>(cnt, src, fill, op, dst);
+  }
+  void from_op(bool row, const double* src, const double* scale, double* dst, hipStream_t st) const override {
+    const int64_t cnt = row ? m : n;
+    k_mul_into<<<dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st>>>(cnt, src, scale, dst);
+  }
+};
+
+// LSQR driver over any Ops (see the stopping rule in mfe.h).
+int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
+             int32_t check_every, double* x_out, mfe_lsqr_info* info, hipStream_t st) {
+  const int64_t nr = ops.rows(), nc = ops.cols();
+  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks());
+  Work W;
+  double *bb, *dd, *ee, *u, *du, *v, *w, *x, *ev, *res, *part, *w_tmp;
+  LsqrScal* sc;
+  MFE_CHECK(W.alloc(&w_tmp, nc));
+  MFE_CHECK(W.alloc(&bb, nr));
+  MFE_CHECK(W.alloc(&dd, nr));
+  MFE_CHECK(W.alloc(&ee, nc));
+  MFE_CHECK(W.alloc(&u, nr));
+  MFE_CHECK(W.alloc(&du, nr));
+  MFE_CHECK(W.alloc(&v, nc));
+  MFE_CHECK(W.alloc(&w, nc));
+  MFE_CHECK(W.alloc(&x, nc));
+  MFE_CHECK(W.alloc(&ev, nc));
+  MFE_CHECK(W.alloc(&res, nr));
+  MFE_CHECK(W.alloc(&part, pb));
+  MFE_CHECK(W.alloc(&sc, 1));
+  for (double* z : {u, du, res}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nr, st));
+  for (double* z : {v, w, x, ev}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nc, st));
+  ops.to_op(true, b, 0.0, 0, bb, st);
+  ops.to_op(true, d, 1.0, 0, dd, st);
+  ops.to_op(false, e, 1.0, 0, ee, st);
+  k_scal_init<<<1, 1, 0, st>>>(sc);
+  const unsigned upd_grid = (unsigned)ceil_div(nc + nr, 256);
+  const unsigned row_grid = (unsigned)ceil_div(nr, 256);
+  // ||b||^2 for the relative residual of the original system
+  k_mul<<<row_grid, 256, 0, st>>>(nr, bb, bb, res);
+  k_reduce<<<1, kRed, 0, st>>>(res, nr, &sc->bnorm2);
+  // start: beta_1 u_1 = D b, alpha_1 v_1 = Abar' u_1
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);   // u = D b (normalised by k_lsqr_update)
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);   // du = D u, gathered by the transposed product
+  k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
+  k_reduce<<<1, kRed, 0, st>>>(res, nr, part);
+  k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
+  // v = E A' D u / beta_1 (previous v is zero)
+  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);
+  k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
+  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
+  MFE_HIP(hipGetLastError());
+
+  LsqrScal h;
+  MFE_HIP(hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(h.bnorm2);
+  mfe_lsqr_info inf;
+  inf.iters = 0;
+  inf.stop_reason = 0;
+  inf.rel_resid = bnorm > 0 ? 1.0 : 0.0;
+  inf.normal_eq = 0.0;
+  if (bnorm == 0.0 || h.beta == 0.0 || h.breakdown != 0) {
+    MFE_HIP(hipMemsetAsync(x, 0, sizeof(double) * nc, st));
+    inf.stop_reason = 3;
+    max_iter = 0;
+  }
+  for (int it = 1; it <= max_iter; ++it) {
+    k_scal_iter<<<1, 1, 0, st>>>(sc, it);
+    // p = D A E v - alpha u  (u normalised), du = D p, partial ||p||^2
+    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);
+    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc);
+    // q = E A' D p / beta - beta v, partial ||q||^2
+    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);
+    k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
+    k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+    MFE_HIP(hipGetLastError());
+    if (it % check_every == 0 || it == max_iter) {
+      // residual of the original system: A (E xbar) - b, reduced over the rows
+      k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, w_tmp);
+      ops.fwd(nullptr, w_tmp, nullptr, &sc->neg_one, bb, res, nullptr, part, st);
+      k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), &sc->res2);
+      MFE_HIP(hipGetLastError());
+      MFE_HIP(hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st));
+      MFE_HIP(hipStreamSynchronize(st));
+      const double rel = std::sqrt(h.res2) / bnorm;
+      inf.iters = h.breakdown > 0 ? h.breakdown : it;
+      inf.rel_resid = rel;
+      inf.normal_eq = h.normal_eq;
+      if (rel <= tol) {
+        inf.stop_reason = 1;
+        break;
+      }
+      if (h.normal_eq <= tol) {
+        inf.stop_reason = 2;
+        break;
+      }
+      if (h.breakdown != 0) {
+        inf.stop_reason = 3;
+        break;
+      }
+    }
+  }
+  ops.from_op(false, x, ee, x_out, st);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  if (info) *info = inf;
+  return MFE_OK;
+}
+
+int run_residual_sell(mfe_plan* p, const double* d, const double* e, double alpha, double beta, double* rms,
+                      double* rms_nonempty, int64_t* n_empty, hipStream_t st) {
+  SellOps ops(p);
+  Work W;
+  double *d2, *e2, *pa, *pn, *pe, *out;
+  const int64_t nr = p->rows.nint, nc = p->cols.nint;
+  const int64_t br = ceil_div(nr, kRed), bc = ceil_div(nc, kRed);
+  MFE_CHECK(W.alloc(&d2, nr));
+  MFE_CHECK(W.alloc(&e2, nc));
+  MFE_CHECK(W.alloc(&pa, br + bc));
+  MFE_CHECK(W.alloc(&pn, br + bc));
+  MFE_CHECK(W.alloc(&pe, br + bc));
+  MFE_CHECK(W.alloc(&out, 3));
+  ops.to_op(true, d, 1.0, 1, d2, st);
+  ops.to_op(false, e, 1.0, 1, e2, st);
+  k_sell_rownorm<<<dim3((unsigned)br), dim3(kRed), 0, st>>>(ops.R, d2, e2, alpha, pa, pn, pe);
+  k_sell_rownorm<<<dim3((unsigned)bc), dim3(kRed), 0, st>>>(ops.C, e2, d2, beta, pa + br, pn + br, pe + br);
+  k_reduce<<<1, kRed, 0, st>>>(pa, br + bc, out);
+  k_reduce<<<1, kRed, 0, st>>>(pn, br + bc, out + 1);
+  k_reduce<<<1, kRed, 0, st>>>(pe, br + bc, out + 2);
+  MFE_HIP(hipGetLastError());
+  double h[3];
+  MFE_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  const double total = (double)(p->M + p->N);
+  const int64_t ne = (int64_t)llround(h[2]);
+  if (rms) *rms = std::sqrt(h[0] / total);
+  if (rms_nonempty) *rms_nonempty = total - ne > 0 ? std::sqrt(h[1] / (total - ne)) : 0.0;
+  if (n_empty) *n_empty = ne;
+  return MFE_OK;
+}
+
+}  // namespace
+
+int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
+              int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t st) {
+  MFE_CHECK(ensure_mats(p, st));
+  SellOps ops(p);
+  return run_lsqr(ops, b, d, e, tol, max_iter, check_every, x, info, st);
+}
+
+int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta, double* rms,
+                  double* rms_nonempty, int64_t* n_empty, hipStream_t st) {
+  if (p->count != 1) return set_error(MFE_EUNSUPPORTED, "residual needs a single-matrix plan");
+  MFE_CHECK(ensure_mats(p, st));
+  return run_residual_sell(p, d, e, alpha, beta, rms, rms_nonempty, n_empty, st);
+}
+
+int dense_f64_lsqr(const mfe_matrix* A, const double* b, const double* d, const double* e, double tol,
+                   int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t st) {
+  if (!A->data) return set_error(MFE_EINVAL, "dense data is NULL");
+  if (A->ld < A->n) return set_error(MFE_EDIM, "ld < n");
+  DenseOps ops((const double*)A->data, A->m, A->n, A->ld);
+  return run_lsqr(ops, b, d, e, tol, max_iter, check_every, x, info, st);
+}
+
+int dense_f64_residual(const mfe_matrix* A, const double* d, const double* e, double alpha, double beta, double* rms,
+                       double* rms_nonempty, int64_t* n_empty, hipStream_t st) {
+  if (!A->data) return set_error(MFE_EINVAL, "dense data is NULL");
+  if (A->ld < A->n) return set_error(MFE_EDIM, "ld < n");
+  const int64_t m = A->m, n = A->n;
+  const int64_t br = ceil_div(m, kRed), bc = ceil_div(n, kRed);
+  Work W;
+  double *pa, *pn, *pe, *out;
+  MFE_CHECK(W.alloc(&pa, br + bc));
+  MFE_CHECK(W.alloc(&pn, br + bc));
+  MFE_CHECK(W.alloc(&pe, br + bc));
+  MFE_CHECK(W.alloc(&out, 3));
+  const double* Ad = (const double*)A->data;
+  k_dense_rownorm<<<dim3((unsigned)br), dim3(kRed), 0, st>>>(Ad, m, n, A->ld, 0, d, e, alpha, pa, pn, pe);
+  k_dense_rownorm<<<dim3((unsigned)bc), dim3(kRed), 0, st>>>(Ad, m, n, A->ld, 1, e, d, beta, pa + br, pn + br, pe + br);
+  k_reduce<<<1, kRed, 0, st>>>(pa, br + bc, out);
+  k_reduce<<<1, kRed, 0, st>>>(pn, br + bc, out + 1);
+  k_reduce<<<1, kRed, 0, st>>>(pe, br + bc, out + 2);
+  MFE_HIP(hipGetLastError());
+  double h[3];
+  MFE_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  const double total = (double)(m + n);
+  const int64_t ne = (int64_t)llround(h[2]);
+  if (rms) *rms = std::sqrt(h[0] / total);
+  if (rms_nonempty) *rms_nonempty = total - ne > 0 ? std::sqrt(h[1] / (total - ne)) : 0.0;
+  if (n_empty) *n_empty = ne;
+  return MFE_OK;
+}
+
+}  // namespace mfe

@@ -143,6 +143,10 @@ int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, do
 int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta,
                   double* rms, double* rms_nonempty, int64_t* n_empty, hipStream_t s);
 
+// Makes sure the per-matrix device table exists (original-index bases are all that
+// LSQR and the residual need from it).
+int ensure_mats(mfe_plan* p, hipStream_t s);
+
 // Launches the fused sign-generation for one step into `out` (all segments).
 int launch_signgen(const SignGenDev& g, hipStream_t s);
 

@@ -367,6 +367,22 @@ struct InitLauncher {
 
 }  // namespace
 
+int ensure_mats(mfe_plan* p, hipStream_t st) {
+  if (p->mats) return MFE_OK;
+  MFE_CHECK(ensure(&p->mats, p->count));
+  std::vector<MatDev> md(p->count);
+  int64_t ro = 0, co = 0;
+  for (int b = 0; b < p->count; ++b) {
+    md[b] = MatDev{};
+    md[b].row_orig_base = ro;
+    md[b].col_orig_base = co;
+    ro += p->meta[b].m;
+    co += p->meta[b].n;
+  }
+  MFE_HIP(hipMemcpyAsync(p->mats, md.data(), sizeof(MatDev) * p->count, hipMemcpyHostToDevice, st));
+  return MFE_OK;
+}
+
 int launch_signgen(const SignGenDev& g, hipStream_t st) {
   if (g.nblocks <= 0) return MFE_OK;
   k_signgen<<<dim3((unsigned)ceil_div(g.nblocks, kBlock)), dim3(kBlock), 0, st>>>(g);
