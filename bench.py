@@ -1,16 +1,22 @@
-"""Benchmark of the sparse equilibration hot path on one MI355X.
+"""Benchmark of the equilibration hot path on one MI355X.
 
-Workload: CSR FP32 A, 1,000,000 x 500,000, 10 uniform random columns per row, values
-N(0,1) e^(r_i + c_j) with r, c ~ N(0, 2^2); Algorithm 1 with k = 16 probes per step,
-T = 2000 steps, alpha = (n/m)^(1/4), beta = (m/n)^(1/4), gamma = 0.1, M = 10.
+Headline workload (the JSON line's `value`): CSR FP32 A, 1,000,000 x 500,000, 10 uniform
+random columns per row, values N(0,1) e^(r_i + c_j) with r, c ~ N(0, 2^2); Algorithm 1
+with k = 16 probes per step, T = 2000 steps, alpha = (n/m)^(1/4), beta = (m/n)^(1/4),
+gamma = 0.1, M = 10.  One benchmark "step" = one full equilibration run over the
+resident matrix (T iterations: probe draw, both products, square/step/project,
+averaging, output d and e).  The one-time preprocessing (transpose and sliced layouts)
+is timed separately.  Metric: probe-matvec pairs per second (one pair = one probe column
+through A and one through A'), T * k / seconds per run.
 
-One benchmark "step" = one full equilibration run (T SGD iterations: probe draw, both
-products, square/step/project, averaging, output d and e) over the resident matrix.
-The one-time preprocessing (transpose and sliced layouts) is timed separately.
-Metric: probe-matvec pairs per second (one pair = one probe column through A and one
-through A'), i.e. T * k / seconds per run.
+The other workloads of the build are measured under "extra" (same run, same GPU):
+  c0    dense FP64 200 x 100, k = 1, T = 300 (latency case: microseconds per step)
+  c2    512 uneven CSR matrices in one plan, k = 8, T = 1000, one HIP graph
+  c3    dense bf16 16384 x 8192, k = 64, T = 500 on the matrix cores
+  lsqr  LSQR on the headline matrix to 1e-6 with (d, e), with (1, e) and without
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,lsqr]
+                       [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -24,43 +30,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 M_ROWS, N_COLS, NNZ_ROW, SIGMA = 1_000_000, 500_000, 10, 2.0
 T_STEPS, K_PROBES, GAMMA, BOX_M = 2000, 16, 0.1, 10.0
 GEN_SEED, PROBE_SEED = 1001, 2001
 
 
-def algorithmic_bytes_per_launch(m, n, nnz, k):
-    """HBM bytes one fused step launch must move at minimum.
+def sparse_algorithmic_bytes(m, n, nnz, k):
+    """HBM bytes one step (both direction launches) must move at minimum.
 
-    Per stored entry and direction: 8 B (int32 index + FP32 value), both directions.
-    Per row or column: iterate read+write 16 B, average read+write 16 B, descriptor
-    write 16 B and its compulsory read 16 B (gathered by the other direction), row
-    length and original index 8 B, probe sign bits read k/8 B and generated k/8 B.
+    Per stored entry and direction: 8 B (int32 index + FP32 value).  Per row or column:
+    iterate read+write 16 B, average read+write 16 B, descriptor write and its
+    compulsory read (8 B each when k <= 16, else 16 B each), row length and original
+    index 8 B, probe sign bits read k/8 B and generated k/8 B.
     """
-    return 2 * nnz * 8 + (m + n) * (72 + k / 4.0)
+    desc = 8 if k <= 16 else 16
+    return 2 * nnz * 8 + (m + n) * (16 + 16 + 2 * desc + 8 + k / 4.0)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is described in DESIGN.md but not built.", file=sys.stderr)
-        sys.exit(2)
-    rank = int(os.environ.get("RANK", "0"))
+def bf16_algorithmic(m, n, k):
+    """Per step: A read once (the minimum; the kernel reads its two tiled copies once
+    each), plus probe operands and FP64 state; FLOPs of both products."""
+    return 2 * m * n + (m + n) * (2 * k + 40), 2 * 2.0 * m * n * k
 
-    import numpy as np
-    import torch
 
-    from workloads import scaled_sparse
-
+def load_lib():
     try:
         import paper_1602_06621_amd as mfe
         mfe.version()
@@ -68,7 +63,165 @@ def main():
         from paper_1602_06621_amd import build as b
         b.build()
         import paper_1602_06621_amd as mfe
+    return mfe
 
+
+def timed(fn, steps, warmup):
+    import torch
+
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / max(steps, 1), out
+
+
+def bench_c0(mfe):
+    import torch
+
+    from workloads import scaled_dense
+
+    A = scaled_dense(200, 100, 1.5, 1000)
+    D = mfe.Dense(torch.tensor(A, device="cuda:0"))
+    al, be = mfe.default_alpha_beta(200, 100)
+    s, _ = timed(lambda: mfe.equilibrate(D, al, be, GAMMA, BOX_M, 300, 1, 2000), 3, 1)
+    return {"workload": "dense f64 200x100, k=1, T=300", "ms_per_run": s * 1e3, "us_per_step": s * 1e6 / 300,
+            "pairs_per_s": 300 / s}
+
+
+def bench_c2(mfe):
+    import numpy as np
+    import torch
+
+    from workloads import batched_sparse
+
+    t0 = time.time()
+    mats = batched_sparse(512, 1002)
+    gen_s = time.time() - t0
+    G = [mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0") for c in mats]
+    M = sum(c.m for c in mats)
+    N = sum(c.n for c in mats)
+    nnz = sum(c.nnz for c in mats)
+    del mats
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plan = mfe.Plan(G, max_probes=8)
+    torch.cuda.synchronize()
+    prep_ms = (time.time() - t0) * 1e3
+    T, k = 1000, 8
+    s, out = timed(lambda: plan.equilibrate(None, None, GAMMA, BOX_M, T, k, 2002, use_graph=True), 2, 1)
+    tim = plan.last_timing()
+    plan.close()
+    by = sparse_algorithmic_bytes(M, N, nnz, k)
+    return {"workload": "512 CSR f32, m~U[1k,64k], n~U[m/4,m], nnz/row~Poisson(12), sigma=2; k=8, T=1000, one graph",
+            "sum_m": M, "sum_n": N, "nnz": nnz, "ms_per_run": s * 1e3, "step_ms": tim["step_ms"],
+            "pairs_per_s": 512 * T * k / s, "algorithmic_gbs": by / (tim["step_ms"] / 1e3) / 1e9,
+            "hbm_frac": by / (tim["step_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, "prep_ms": prep_ms, "gen_s": gen_s,
+            "finite": bool(torch.isfinite(out["u_bar"]).all().item())}
+
+
+def bench_c3(mfe):
+    import numpy as np
+    import torch
+
+    from workloads import round_to_bf16, scaled_dense
+
+    m, n, k, T = 16384, 8192, 64, 500
+    A = scaled_dense(m, n, 3.0, 1003)
+    bits, _ = round_to_bf16(A)
+    del A
+    D = mfe.Dense(torch.tensor(bits.view(np.int16), device="cuda:0"))
+    al, be = mfe.default_alpha_beta(m, n)
+    s, _ = timed(lambda: mfe.equilibrate(D, al, be, GAMMA, BOX_M, T, k, 2003), 2, 1)
+    tim = mfe.last_timing()
+    by, fl = bf16_algorithmic(m, n, k)
+    step_s = tim["step_ms"] / 1e3
+    return {"workload": "dense bf16 16384x8192, k=64 exact +-1 probes x bf16(e^v), FP32 accumulate, T=500",
+            "ms_per_run": s * 1e3, "step_ms": tim["step_ms"], "pairs_per_s": T * k / s,
+            "hbm_gbs": by / step_s / 1e9, "hbm_frac": by / step_s / 1e9 / HBM_PEAK_GBS,
+            "mfma_tflops": fl / step_s / 1e12, "mfma_frac": fl / step_s / 1e12 / BF16_PEAK_TFLOPS}
+
+
+def bench_lsqr(mfe, plan, csr, out):
+    import numpy as np
+    import torch
+
+    from workloads import rhs_noisy
+
+    b, _ = rhs_noisy(csr.to_scipy(), 1002, noise=1e-3)
+    bt = torch.tensor(b, device="cuda:0")
+    res = {}
+    ones = torch.ones(csr.m, dtype=torch.float64, device="cuda:0")
+    for name, d, e in (("d_e", out["d"], out["e"]), ("col_only", ones, out["e"]), ("plain", None, None)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = plan.lsqr(bt, d, e, tol=1e-6, max_iter=3000, check_every=25)
+        torch.cuda.synchronize()
+        res[name] = dict(info, seconds=time.perf_counter() - t0)
+    return {"workload": "LSQR on the headline matrix, b = A x* + 1e-3 N(0,1), tol 1e-6, max 3000 iterations",
+            **res}
+
+
+def profile_run():
+    """Counter run: 20 steps of the headline workload (per-launch counters are what is
+    read), then a plain device copy of 512 MiB whose FETCH_SIZE / WRITE_SIZE calibrate
+    the counters (the source is flushed from the caches by a 2 GiB fill first)."""
+    import torch
+
+    from workloads import scaled_sparse
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    csr = scaled_sparse(M_ROWS, N_COLS, NNZ_ROW, SIGMA, GEN_SEED)
+    A = mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")
+    al, be = mfe.default_alpha_beta(csr.m, csr.n)
+    plan = mfe.Plan([A], max_probes=K_PROBES)
+    plan.equilibrate(al, be, GAMMA, BOX_M, 20, K_PROBES, PROBE_SEED, use_graph=False)
+    torch.cuda.synchronize()
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    flush = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    flush.fill_(2.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    plan.close()
+    print(json.dumps({"profile": "done", "copy_bytes": src.numel() * 4}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workloads", default="c1,c0,c2,c3,lsqr")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for hardware counters: the headline workload with 20 steps, "
+                         "then a 512 MiB device copy used to calibrate FETCH_SIZE / WRITE_SIZE")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); how the path would shard "
+              "across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    work = set(args.workloads.split(","))
+    if args.profile:
+        profile_run()
+        return
+
+    import numpy as np
+    import torch
+
+    from workloads import scaled_sparse
+
+    mfe = load_lib()
     torch.cuda.set_device(0)
     dev = "cuda:0"
     t0 = time.time()
@@ -81,9 +234,9 @@ def main():
     plan = mfe.Plan([A], max_probes=K_PROBES)
     torch.cuda.synchronize()
     prep_ms = (time.time() - t0) * 1e3
-    out = None
     run = dict(alpha=al, beta=be, gamma=GAMMA, M=BOX_M, steps=T_STEPS, probes=K_PROBES, seed=PROBE_SEED,
                use_graph=not args.no_graph)
+    out = None
     for _ in range(args.warmup):
         out = plan.equilibrate(**run, out=out)
     torch.cuda.synchronize()
@@ -97,11 +250,22 @@ def main():
     pairs = T_STEPS * K_PROBES
     value = pairs / (ms_per_step / 1e3)
     kern_ms = float(np.mean(step_ms_samples)) if step_ms_samples else float("nan")
-    bytes_launch = algorithmic_bytes_per_launch(csr.m, csr.n, csr.nnz, K_PROBES)
+    bytes_launch = sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, K_PROBES)
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
+
+    extra = {"prep_ms": prep_ms, "gen_s": gen_s,
+             "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
+    for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3)):
+        if name in work:
+            print(f"# measuring {name}", file=sys.stderr, flush=True)
+            extra[name] = fn(mfe)
+    if "lsqr" in work:
+        print("# measuring lsqr", file=sys.stderr, flush=True)
+        extra["lsqr"] = bench_lsqr(mfe, plan, csr, out)
 
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         from oracle import algorithm1 as A1
 
         As = csr.to_scipy()
@@ -131,10 +295,10 @@ def main():
                    "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_step<16>", "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch},
+                     "kernel": "k_phase<16,true> (row launch + column launch of one step)",
+                     "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch},
         "cpu_baseline": cpu,
-        "extra": {"prep_ms": prep_ms, "gen_s": gen_s,
-                  "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9},
+        "extra": extra,
     }
     plan.close()
     if rank == 0:

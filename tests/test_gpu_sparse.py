@@ -272,3 +272,38 @@ def test_full_size_bench_configuration_properties(config1):
     assert np.all(np.isfinite(ub)) and np.all(np.isfinite(vb))
     assert np.abs(ub).max() <= 10.0 and np.abs(vb).max() <= 10.0
     assert ub.max() <= al**2 / 0.1 + 1e-12 and vb.max() <= be**2 / 0.1 + 1e-12
+
+
+def test_batched_512_matrices_config2():
+    """The batched workload at full size: 512 uneven CSR matrices (m ~ U[1k, 64k],
+    n ~ U[m/4, m], Poisson(12) entries per row, sigma = 2) in one plan and one graph,
+    k = 8, T = 1000 (the benchmarked run).  Four matrices are compared elementwise with
+    the oracle (matrix b uses sign batch index b); all 512 are checked for finiteness,
+    box and iterate bounds.  (At T = 100 the oracle's own spread under 1e-16 perturbations
+    reaches 3e-6 on some of these matrices; at T = 1000 it is ~1e-8.)"""
+    from paper_1602_06621_amd import Csr, Plan
+    from workloads import batched_sparse
+
+    mats = batched_sparse(512, 1002)
+    G = [Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val) for c in mats]
+    _say("config2 generated", sum(c.nnz for c in mats))
+    with Plan(G, max_probes=8) as plan:
+        out = plan.equilibrate(None, None, 0.1, 10.0, 1000, 8, 2002, use_graph=True)
+        ub, vb = out["u_bar"].cpu().numpy(), out["v_bar"].cpu().numpy()
+        _say("config2 timing", plan.last_timing())
+    r0 = np.concatenate([[0], np.cumsum([c.m for c in mats])])
+    c0 = np.concatenate([[0], np.cumsum([c.n for c in mats])])
+    worst = 0.0
+    for b in (0, 255, 509, 511):
+        c = mats[b]
+        al, be = A1.default_alpha_beta(c.m, c.n)
+        o = A1.equilibrate(c.to_scipy(), al, be, 0.1, 10.0, 1000, k=8, seed=2002, batch=b)
+        worst = max(worst, np.abs(ub[r0[b]:r0[b + 1]] - o["u_bar"]).max(), np.abs(vb[c0[b]:c0[b + 1]] - o["v_bar"]).max())
+        _say("config2 matrix", b, "err", worst)
+    assert worst <= TOL
+    assert np.all(np.isfinite(ub)) and np.all(np.isfinite(vb))
+    assert np.abs(ub).max() <= 10 and np.abs(vb).max() <= 10
+    for b in range(512):
+        al, be = A1.default_alpha_beta(mats[b].m, mats[b].n)
+        assert ub[r0[b]:r0[b + 1]].max() <= al**2 / 0.1 + 1e-12
+        assert vb[c0[b]:c0[b + 1]].max() <= be**2 / 0.1 + 1e-12

@@ -125,11 +125,15 @@ def poisson_lengths(m: int, mean: float, n: int, seed: int) -> np.ndarray:
 
 
 def batched_shapes(count: int, seed: int, m_lo=1000, m_hi=64000):
-    """Shapes of a batch of uneven problems: m ~ U[m_lo, m_hi], n ~ U[m/4, m]."""
+    """Shapes of a batch of uneven problems: m ~ U[m_lo, m_hi], n ~ U[m/4, m].
+    Drawn matrix by matrix, so the first c shapes do not depend on count."""
     g = rng(seed)
-    ms = g.integers(m_lo, m_hi + 1, size=count)
-    ns = np.array([g.integers(max(1, mm // 4), mm + 1) for mm in ms])
-    return ms.astype(np.int64), ns.astype(np.int64)
+    ms, ns = [], []
+    for _ in range(count):
+        mm = int(g.integers(m_lo, m_hi + 1))
+        ms.append(mm)
+        ns.append(int(g.integers(max(1, mm // 4), mm + 1)))
+    return np.array(ms, dtype=np.int64), np.array(ns, dtype=np.int64)
 
 
 def batched_sparse(count: int, seed: int, mean_nnz=12.0, sigma=2.0, m_lo=1000, m_hi=64000):
