@@ -13,9 +13,10 @@ The other workloads of the build are measured under "extra" (same run, same GPU)
   c0    dense FP64 200 x 100, k = 1, T = 300 (latency case: microseconds per step)
   c2    512 uneven CSR matrices in one plan, k = 8, T = 1000, one HIP graph
   c3    dense bf16 16384 x 8192, k = 64, T = 500 on the matrix cores
+  c4    learned warm start vs plain SGD: steps and seconds to equal residual (200000 x 100000)
   lsqr  LSQR on the headline matrix to 1e-6 with (d, e), with (1, e) and without
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,lsqr]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,c4,lsqr]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -146,6 +147,108 @@ def bench_c3(mfe):
             "mfma_tflops": fl / step_s / 1e12, "mfma_frac": fl / step_s / 1e12 / BF16_PEAK_TFLOPS}
 
 
+def bench_c4(mfe):
+    """Learned warm start against plain SGD: steps and seconds to equal residual on a
+    held-out 200,000 x 100,000 matrix (training matrices are smaller and fewer than
+    the paper-scale set; the sizes are in the returned record)."""
+    import numpy as np
+    import torch
+
+    from paper_1602_06621_amd import warmstart as W
+    from workloads import warmstart_matrix, warmstart_training_set
+
+    k, gamma, every, rel = 16, GAMMA, 5, 1.2
+    rec = {"workload": "learned warm start: 3-layer MLP width 64 (FP32) on 4-probe sketch features; "
+                       "eval csr_f32 200000x100000, U{8..16} nnz/row, sigma=2; k=16; target = 1.2 x the "
+                       "residual of the plain run after 3000 steps"}
+    t0 = time.time()
+    train = warmstart_training_set(32, 31, m_lo=10_000, m_hi=100_000)
+    rec["train_matrices"] = len(train)
+    rec["train_rows"] = int(sum(c.m for c in train))
+    rec["train_nnz"] = int(sum(c.nnz for c in train))
+    G = [mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0") for c in train]
+    del train
+    rec["gen_s"] = time.time() - t0
+    with mfe.Plan(G, max_probes=k) as plan:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab = plan.equilibrate(None, None, gamma, BOX_M, 3000, k, 77, use_graph=True)
+        torch.cuda.synchronize()
+        rec["label_s"] = time.perf_counter() - t0
+        X, t = W.training_set(plan, 5, lab, per_matrix=4096)
+    del G, lab
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, loss = W.train(X, t, iters=2000, batch=4096, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
+    rec["train_s"] = time.perf_counter() - t0
+    rec["train_samples"] = int(X.shape[0])
+    rec["train_loss_first_last"] = [float(loss[:20].mean()), float(loss[-20:].mean())]
+    rec["target_var"] = float(t.var())
+
+    # step offsets tuned on a training-distribution matrix, never on the evaluation one
+    tm = warmstart_matrix(100_000, 50_000, 2.0, 4242)
+    al, be = mfe.default_alpha_beta(tm.m, tm.n)
+    with mfe.Plan([mfe.Csr.from_arrays(tm.m, tm.n, tm.row_ptr, tm.col_idx, tm.val, device="cuda:0")],
+                  max_probes=k) as plan:
+        t0_mlp, sweep_mlp = W.tune_t0(plan, params, 5, al, be, learned=True, seed=12)
+        t0_sk, sweep_sk = W.tune_t0(plan, params, 5, al, be, learned=False, seed=12)
+    rec["t0"] = {"mlp": t0_mlp, "sketch": t0_sk, "sweep_mlp": sweep_mlp, "sweep_sketch": sweep_sk}
+
+    c = warmstart_matrix(200_000, 100_000, 2.0, 9001)
+    al, be = mfe.default_alpha_beta(c.m, c.n)
+    Ac = mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0")
+    with mfe.Plan([Ac], max_probes=k) as plan:
+        _, plain = plan.equilibrate_trace(al, be, gamma, BOX_M, 3000, k, 11, trace_every=every)
+        target = rel * float(plain[-1])
+        arms = {"plain": (0, None), "sketch": (t0_sk, False), "mlp": (t0_mlp, True)}
+        steps = {"plain": W.steps_to_residual(plain, target, every)}
+        for name in ("sketch", "mlp"):
+            u0, v0 = W.warm_start(plan, params, 5, learned=arms[name][1])
+            _, tr = plan.equilibrate_trace(al, be, gamma, BOX_M, 3000, k, 11, t0=arms[name][0], u0=u0, v0=v0,
+                                           trace_every=every)
+            steps[name] = W.steps_to_residual(tr, target, every)
+        rec["floor"] = float(plain[-1])
+        rec["target"] = target
+        rec["steps_to_target"] = steps
+
+        def run(name):
+            t0a, learned = arms[name]
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            if name == "plain":
+                out = plan.equilibrate(al, be, gamma, BOX_M, steps[name], k, 11, use_graph=True)
+            else:
+                u0, v0 = W.warm_start(plan, params, 5, learned=learned)
+                out = plan.equilibrate(al, be, gamma, BOX_M, steps[name], k, 11, t0=t0a, u0=u0, v0=v0,
+                                       use_graph=True)
+            torch.cuda.synchronize()
+            return time.perf_counter() - s0, out
+
+        secs, reached = {}, {}
+        for name in ("plain", "sketch", "mlp"):
+            if steps[name] is None:
+                continue
+            run(name)  # graph capture
+            ts = []
+            for _ in range(5):
+                s, out = run(name)
+                ts.append(s)
+            secs[name] = float(np.median(ts))
+            reached[name] = mfe.residual(Ac, out["d"], out["e"], al, be)[0]
+        rec["seconds_to_target"] = secs
+        rec["residual_reached"] = reached
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(10):
+            W.warm_start(plan, params, 5)
+        torch.cuda.synchronize()
+        rec["warm_start_ms"] = (time.perf_counter() - s0) * 100
+    if "plain" in secs and "mlp" in secs:
+        rec["speedup_seconds"] = secs["plain"] / secs["mlp"]
+    return rec
+
+
 def bench_lsqr(mfe, plan, csr, out):
     import numpy as np
     import torch
@@ -198,7 +301,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workloads", default="c1,c0,c2,c3,lsqr")
+    ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
@@ -255,7 +358,7 @@ def main():
 
     extra = {"prep_ms": prep_ms, "gen_s": gen_s,
              "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
-    for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3)):
+    for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3), ("c4", bench_c4)):
         if name in work:
             print(f"# measuring {name}", file=sys.stderr, flush=True)
             extra[name] = fn(mfe)

@@ -185,6 +185,60 @@ int mfe_residual(const mfe_matrix* A, const double* d, const double* e, double a
 int mfe_draw_signs(uint64_t seed, int32_t batch, int64_t step, int32_t side, int64_t nwords,
                    uint64_t* words, void* stream);
 
+/* ---------------------------------------------------------------- learned warm start
+ *
+ * A warm start (u0, v0) with a step offset t0 > 0 (see mfe_equil_params) replaces the
+ * paper's u0 = v0 = 0.  It is built from probe sketches only (matrix-free):
+ *   1. sketch: with `probes` Rademacher probes per side (stream sides 2 and 3, step 0,
+ *      batch = matrix index) the Section 3.1 estimator at (u, v) = 0 gives r_i ~ row
+ *      norm^2, c_j ~ column norm^2;
+ *   2. sketch initialisation: u_i = -1/2 log r_i + c, v_j = -1/2 log c_j + c with
+ *      e^(4c) = alpha^2 F / n, F = (sum r + sum c)/2 (exact equilibration in expectation
+ *      for A = diag(a) G diag(b)); indices without entries get min(M, target/gamma);
+ *   3. a width-64, 3-layer tanh MLP maps 8 features per index to a correction; the
+ *      warm start is clip(sketch initialisation + correction, -M, M).
+ * The feature layout is documented in csrc/warmstart.hip. */
+
+/* Sketch features of every row and column of a plan (all matrices back to back, in
+ * plan order).  feat_rows [sum m][8], feat_cols [sum n][8] FP32; u_sketch [sum m],
+ * v_sketch [sum n] FP64 sketch initialisations; all device.  alpha_b / beta_b: host
+ * [count] or NULL for (n_b/m_b)^(1/4), (m_b/n_b)^(1/4).  probes in {4, 8, 16}. */
+int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
+                             const double* beta_b, double gamma, double box_M, float* feat_rows,
+                             float* feat_cols, double* u_sketch, double* v_sketch, void* stream);
+
+/* Sizes of the warm-start network: parameter count, feature count (8), width (64). */
+int mfe_mlp_sizes(int32_t* n_params, int32_t* n_features, int32_t* width);
+
+/* y[i] = MLP(X[i]) for count rows of X [count][8] (device FP32); params device FP32 in the
+ * order W1 (8 x 64, row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1). */
+int mfe_mlp_forward(const float* params, const float* X, int64_t count, float* y, void* stream);
+
+/* Mean squared error over all count rows and its gradient grad [n_params] (device FP32);
+ * loss is a host pointer (nullable). */
+int mfe_mlp_loss_grad(const float* params, const float* X, const float* t, int64_t count, float* grad,
+                      double* loss, void* stream);
+
+/* iters Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on mini-batches of `batch` rows
+ * drawn with replacement from X [count][8] / t [count]: row b of step s is
+ * Philox(counter (b+1,0,0,0), key (seed, (s << 2) | 3)) word 0 mod count.  params, adam_m,
+ * adam_v device FP32 [n_params], updated in place; step0 = steps already taken (for the
+ * bias correction and the batch stream).  loss_trace: host [iters] (nullable). */
+int mfe_mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
+                  int64_t count, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,
+                  void* stream);
+
+/* out[i] = clip(sketch[i] + delta[i], -M, M) (delta FP32, nullable = 0); device arrays. */
+int mfe_warmstart_apply(int64_t n, const double* sketch, const float* delta, double box_M, double* out,
+                        void* stream);
+
+/* Algorithm 1 on a single-matrix plan with the RMS equilibration error (Section 4) of the
+ * current average recorded after every trace_every steps: rms_trace is a host array of
+ * ceil(steps / trace_every) doubles.  Step time is measured without the evaluations
+ * (mfe_plan_last_timing). */
+int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_t trace_every,
+                               double* rms_trace, double* d, double* e, double* u_bar, double* v_bar);
+
 /* Thread-local description of the last non-OK status (or a warning), never NULL. */
 const char* mfe_last_error(void);
 

@@ -24,6 +24,11 @@ from ._ffi import (  # noqa: F401
     last_timing,
     library_path,
     lsqr,
+    mlp_forward,
+    mlp_loss_grad,
+    mlp_sizes,
+    mlp_train,
     residual,
     version,
+    warmstart_apply,
 )

@@ -78,6 +78,13 @@ def _lib():
         "mfe_residual": [C.POINTER(_Matrix), vp, vp, dbl, dbl, C.POINTER(dbl), C.POINTER(dbl),
                          C.POINTER(i64), vp],
         "mfe_draw_signs": [u64, i32, i64, i32, i64, vp, vp],
+        "mfe_plan_equilibrate_trace": [vp, C.POINTER(_Params), i32, C.POINTER(dbl), vp, vp, vp, vp],
+        "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
+        "mfe_mlp_sizes": [C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "mfe_mlp_forward": [vp, vp, i64, vp, vp],
+        "mfe_mlp_loss_grad": [vp, vp, vp, i64, vp, C.POINTER(dbl), vp],
+        "mfe_mlp_train": [vp, vp, vp, i32, vp, vp, i64, i64, i32, C.c_float, u64, vp, vp],
+        "mfe_warmstart_apply": [i64, vp, vp, dbl, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -321,6 +328,40 @@ class Plan:
         _check(_lib().mfe_plan_last_timing(self._h, C.byref(a), C.byref(b)))
         return dict(loop_ms=a.value, step_ms=b.value)
 
+    def equilibrate_trace(self, alpha, beta, gamma=0.1, M=10.0, steps=100, probes=1, seed=0, t0=0, u0=None,
+                          v0=None, trace_every=25, stream=None, device="cuda"):
+        """Single-matrix run recording the RMS equilibration error of the running average
+        every trace_every steps.  Returns (outputs, numpy trace)."""
+        import numpy as np
+
+        out = dict(d=torch.empty(self.M, dtype=torch.float64, device=device),
+                   e=torch.empty(self.N, dtype=torch.float64, device=device),
+                   u_bar=torch.empty(self.M, dtype=torch.float64, device=device),
+                   v_bar=torch.empty(self.N, dtype=torch.float64, device=device))
+        n_tr = -(-int(steps) // int(trace_every)) if steps > 0 else 0
+        tr = (C.c_double * max(n_tr, 1))()
+        p = _params(alpha, beta, gamma, M, steps, probes, seed, t0, 0, u0, v0, stream)
+        _check(_lib().mfe_plan_equilibrate_trace(self._h, C.byref(p), int(trace_every), tr, _ptr(out["d"]),
+                                                  _ptr(out["e"]), _ptr(out["u_bar"]), _ptr(out["v_bar"])))
+        return out, np.array(tr[:n_tr])
+
+    def sketch_features(self, seed, probes=4, gamma=0.1, M=10.0, alpha=None, beta=None, stream=None, device="cuda"):
+        """Sketch features [*, 8] (FP32) and sketch initialisations (FP64) of every row and
+        column of the plan's matrices (see mfe.h)."""
+        cnt = len(self.mats)
+        ah = bh = None
+        if alpha is not None:
+            ah = (C.c_double * cnt)(*([float(alpha)] * cnt if isinstance(alpha, (int, float)) else alpha))
+            bh = (C.c_double * cnt)(*([float(beta)] * cnt if isinstance(beta, (int, float)) else beta))
+        fr = torch.empty(self.M, 8, dtype=torch.float32, device=device)
+        fc = torch.empty(self.N, 8, dtype=torch.float32, device=device)
+        us = torch.empty(self.M, dtype=torch.float64, device=device)
+        vs = torch.empty(self.N, dtype=torch.float64, device=device)
+        _check(_lib().mfe_plan_sketch_features(self._h, int(seed) & ((1 << 64) - 1), int(probes), ah, bh,
+                                               float(gamma), float(M), _ptr(fr), _ptr(fc), _ptr(us), _ptr(vs),
+                                               _stream(stream)))
+        return dict(feat_rows=fr, feat_cols=fc, u_sketch=us, v_sketch=vs)
+
     def lsqr(self, b, d=None, e=None, tol=1e-6, max_iter=1000, check_every=10, stream=None, device="cuda"):
         x = torch.empty(self.N, dtype=torch.float64, device=device)
         info = _LsqrInfo()
@@ -355,6 +396,47 @@ def residual(A, d=None, e=None, alpha=None, beta=None, stream=None):
     _check(_lib().mfe_residual(C.byref(s), _ptr(d, torch.float64, "d"), _ptr(e, torch.float64, "e"),
                                float(alpha), float(beta), C.byref(r), C.byref(rn), C.byref(ne), _stream(stream)))
     return r.value, rn.value, ne.value
+
+
+def mlp_sizes():
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib().mfe_mlp_sizes(C.byref(a), C.byref(b), C.byref(c)))
+    return dict(params=a.value, features=b.value, width=c.value)
+
+
+def mlp_forward(params, X, stream=None):
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(_lib().mfe_mlp_forward(_ptr(params, torch.float32, "params"), _ptr(X, torch.float32, "X"),
+                                  int(X.shape[0]), _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_loss_grad(params, X, t, stream=None):
+    g = torch.empty_like(params)
+    loss = C.c_double()
+    _check(_lib().mfe_mlp_loss_grad(_ptr(params, torch.float32, "params"), _ptr(X, torch.float32, "X"),
+                                    _ptr(t, torch.float32, "t"), int(X.shape[0]), _ptr(g), C.byref(loss),
+                                    _stream(stream)))
+    return loss.value, g
+
+
+def mlp_train(params, adam_m, adam_v, step0, X, t, batch, iters, lr, seed, stream=None):
+    """Adam on mini-batches (in place).  Returns the per-step loss trace (numpy)."""
+    import numpy as np
+
+    tr = (C.c_double * max(int(iters), 1))()
+    _check(_lib().mfe_mlp_train(_ptr(params, torch.float32, "params"), _ptr(adam_m, torch.float32, "adam_m"),
+                                _ptr(adam_v, torch.float32, "adam_v"), int(step0), _ptr(X, torch.float32, "X"),
+                                _ptr(t, torch.float32, "t"), int(X.shape[0]), int(batch), int(iters),
+                                float(lr), int(seed) & ((1 << 64) - 1), tr, _stream(stream)))
+    return np.array(tr[:int(iters)])
+
+
+def warmstart_apply(sketch, delta, M, stream=None):
+    out = torch.empty_like(sketch)
+    _check(_lib().mfe_warmstart_apply(int(sketch.numel()), _ptr(sketch, torch.float64, "sketch"),
+                                      _ptr(delta, torch.float32, "delta"), float(M), _ptr(out), _stream(stream)))
+    return out
 
 
 def draw_signs(seed: int, batch: int, step: int, side: int, nwords: int, stream=None, device="cuda"):

@@ -238,4 +238,64 @@ int mfe_residual(const mfe_matrix* A, const double* d, const double* e, double a
   return set_error(MFE_EUNSUPPORTED, "residual accepts CSR FP32 and dense FP64 matrices");
 }
 
+int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_t trace_every,
+                                double* rms_trace, double* d, double* e, double* u_bar, double* v_bar) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  MFE_CHECK(check_params(p, true));
+  if (p->probes > plan->max_probes) return set_error(MFE_EINVAL, "probes exceed the plan's max_probes");
+  return plan_equilibrate_trace(plan, p, trace_every, rms_trace, d, e, u_bar, v_bar);
+}
+
+int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
+                             const double* beta_b, double gamma, double box_M, float* feat_rows, float* feat_cols,
+                             double* u_sketch, double* v_sketch, void* stream) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  if (!(gamma > 0) || !(box_M > 0)) return set_error(MFE_EINVAL, "gamma and M must be positive");
+  if (!feat_rows || !feat_cols || !u_sketch || !v_sketch) return set_error(MFE_EINVAL, "NULL output");
+  return plan_sketch_features(plan, seed, probes, alpha_b, beta_b, gamma, box_M, feat_rows, feat_cols, u_sketch,
+                              v_sketch, (hipStream_t)stream);
+}
+
+int mfe_mlp_sizes(int32_t* n_params, int32_t* n_features, int32_t* width) {
+  clear_error();
+  if (n_params) *n_params = mlp_param_count();
+  if (n_features) *n_features = mlp_feature_count();
+  if (width) *width = 64;
+  return MFE_OK;
+}
+
+int mfe_mlp_forward(const float* params, const float* X, int64_t count, float* y, void* stream) {
+  clear_error();
+  if (count < 0) return set_error(MFE_EINVAL, "count < 0");
+  if (count > 0 && (!params || !X || !y)) return set_error(MFE_EINVAL, "NULL pointer");
+  return mlp_forward(params, X, count, y, (hipStream_t)stream);
+}
+
+int mfe_mlp_loss_grad(const float* params, const float* X, const float* t, int64_t count, float* grad,
+                      double* loss, void* stream) {
+  clear_error();
+  if (count < 1 || !params || !X || !t || !grad) return set_error(MFE_EINVAL, "invalid arguments");
+  return mlp_grad(params, X, t, count, grad, loss, (hipStream_t)stream);
+}
+
+int mfe_mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
+                  int64_t count, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,
+                  void* stream) {
+  clear_error();
+  if (!params || !adam_m || !adam_v || !X || !t) return set_error(MFE_EINVAL, "NULL pointer");
+  if (count < 1 || batch < 1 || iters < 0 || step0 < 0 || !(lr > 0)) return set_error(MFE_EINVAL, "invalid sizes");
+  return mlp_train(params, adam_m, adam_v, step0, X, t, count, batch, iters, lr, seed, loss_trace,
+                   (hipStream_t)stream);
+}
+
+int mfe_warmstart_apply(int64_t n, const double* sketch, const float* delta, double box_M, double* out,
+                        void* stream) {
+  clear_error();
+  if (n < 0 || !(box_M > 0)) return set_error(MFE_EINVAL, "invalid arguments");
+  if (n > 0 && (!sketch || !out)) return set_error(MFE_EINVAL, "NULL pointer");
+  return warmstart_apply(n, sketch, delta, box_M, out, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -587,7 +587,68 @@ int run_residual_sell(mfe_plan* p, const double* d, const double* e, double alph
   return MFE_OK;
 }
 
+__global__ void k_exp2(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = exp(2.0 * x[i]);
+}
+
+struct TraceCtx {
+  mfe_plan* p;
+  SideDev R, C;
+  double alpha, beta;
+  double *d2, *e2, *pa, *pn, *pe, *out;
+  int64_t br, bc;
+  double* trace;
+  int idx;
+  hipStream_t st;
+};
+
+// RMS equilibration error (Section 4) of the current averages, appended to the trace.
+int trace_chunk(void* c, int /*t*/) {
+  TraceCtx* x = (TraceCtx*)c;
+  mfe_plan* p = x->p;
+  k_exp2<<<dim3((unsigned)ceil_div(p->rows.nint, 256)), dim3(256), 0, x->st>>>(p->rows.nint, p->xbar_row, x->d2);
+  k_exp2<<<dim3((unsigned)ceil_div(p->cols.nint, 256)), dim3(256), 0, x->st>>>(p->cols.nint, p->xbar_col, x->e2);
+  k_sell_rownorm<<<dim3((unsigned)x->br), dim3(kRed), 0, x->st>>>(x->R, x->d2, x->e2, x->alpha, x->pa, x->pn, x->pe);
+  k_sell_rownorm<<<dim3((unsigned)x->bc), dim3(kRed), 0, x->st>>>(x->C, x->e2, x->d2, x->beta, x->pa + x->br,
+                                                                 x->pn + x->br, x->pe + x->br);
+  k_reduce<<<1, kRed, 0, x->st>>>(x->pa, x->br + x->bc, x->out);
+  MFE_HIP(hipGetLastError());
+  double h = 0.0;
+  MFE_HIP(hipMemcpyAsync(&h, x->out, sizeof(double), hipMemcpyDeviceToHost, x->st));
+  MFE_HIP(hipStreamSynchronize(x->st));
+  x->trace[x->idx++] = std::sqrt(h / (double)(p->M + p->N));
+  return MFE_OK;
+}
+
 }  // namespace
+
+int plan_equilibrate_trace(mfe_plan* p, const mfe_equil_params* prm, int32_t trace_every, double* rms_trace,
+                           double* d, double* e, double* u_bar, double* v_bar) {
+  if (p->count != 1) return set_error(MFE_EUNSUPPORTED, "the residual trace needs a single-matrix plan");
+  if (trace_every < 1 || !rms_trace) return set_error(MFE_EINVAL, "trace_every >= 1 and a trace buffer are required");
+  MFE_CHECK(ensure_mats(p, (hipStream_t)prm->stream));
+  SellOps ops(p);
+  Work W;
+  TraceCtx c;
+  c.p = p;
+  c.R = ops.R;
+  c.C = ops.C;
+  c.alpha = prm->alpha;
+  c.beta = prm->beta;
+  c.br = ceil_div(p->rows.nint, kRed);
+  c.bc = ceil_div(p->cols.nint, kRed);
+  MFE_CHECK(W.alloc(&c.d2, p->rows.nint));
+  MFE_CHECK(W.alloc(&c.e2, p->cols.nint));
+  MFE_CHECK(W.alloc(&c.pa, c.br + c.bc));
+  MFE_CHECK(W.alloc(&c.pn, c.br + c.bc));
+  MFE_CHECK(W.alloc(&c.pe, c.br + c.bc));
+  MFE_CHECK(W.alloc(&c.out, 1));
+  c.trace = rms_trace;
+  c.idx = 0;
+  c.st = (hipStream_t)prm->stream;
+  return plan_run(p, prm, nullptr, nullptr, 0, d, e, u_bar, v_bar, trace_every, trace_chunk, &c);
+}
 
 int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
               int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t st) {

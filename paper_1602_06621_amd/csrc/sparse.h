@@ -136,8 +136,25 @@ namespace mfe {
 int plan_build(const mfe_matrix* mats, int32_t count, int32_t max_probes, hipStream_t s,
                mfe_plan** out);
 void plan_free(mfe_plan* p);
+// trace_every > 0 runs the step loop eagerly in chunks of trace_every steps and calls
+// on_chunk(t) after each chunk (the residual trace); chunk times are summed.
 int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
-             int use_graph, double* d, double* e, double* u_bar, double* v_bar);
+             int use_graph, double* d, double* e, double* u_bar, double* v_bar, int trace_every = 0,
+             int (*on_chunk)(void* ctx, int t) = nullptr, void* ctx = nullptr);
+int plan_equilibrate_trace(mfe_plan* p, const mfe_equil_params* prm, int32_t trace_every, double* rms_trace,
+                           double* d, double* e, double* u_bar, double* v_bar);
+int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
+                         double gamma, double M, float* feat_rows, float* feat_cols, double* u_sketch,
+                         double* v_sketch, hipStream_t st);
+int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st);
+int mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
+              int64_t total, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,
+              hipStream_t st);
+int mlp_grad(const float* params, const float* X, const float* t, int64_t count, float* grad, double* loss,
+             hipStream_t st);
+int warmstart_apply(int64_t n, const double* sketch, const float* delta, double M, double* out, hipStream_t st);
+int mlp_param_count();
+int mlp_feature_count();
 int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, double tol,
               int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t s);
 int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta,

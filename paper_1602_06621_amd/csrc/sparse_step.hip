@@ -391,7 +391,8 @@ int launch_signgen(const SignGenDev& g, hipStream_t st) {
 }
 
 int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
-             int use_graph, double* d, double* e, double* u_bar, double* v_bar) {
+             int use_graph, double* d, double* e, double* u_bar, double* v_bar, int trace_every,
+             int (*on_chunk)(void* ctx, int t), void* ctx) {
   hipStream_t st = (hipStream_t)prm->stream;
   const int k = prm->probes;
   if (k < 1 || k > p->max_probes)
@@ -509,6 +510,26 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     MFE_HIP(hipEventRecord(p->ev0, run_st));
     MFE_HIP(hipGraphLaunch(p->graph_exec, run_st));
     MFE_HIP(hipEventRecord(p->ev1, run_st));
+  } else if (trace_every > 0) {
+    // chunks of steps with the caller's evaluation in between; only step time is summed
+    double total_ms = 0.0;
+    for (int t0 = 1; t0 <= T; t0 += trace_every) {
+      const int t1 = std::min(T, t0 + trace_every - 1);
+      MFE_HIP(hipEventRecord(p->ev0, run_st));
+      for (int t = t0; t <= t1; ++t) {
+        dispatch<PhaseLauncher>(k, packed, phase_args(t, true), run_st);
+        dispatch<PhaseLauncher>(k, packed, phase_args(t, false), run_st);
+      }
+      MFE_HIP(hipGetLastError());
+      MFE_HIP(hipEventRecord(p->ev1, run_st));
+      MFE_HIP(hipEventSynchronize(p->ev1));
+      float ms = 0.f;
+      MFE_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+      total_ms += ms;
+      if (on_chunk) MFE_CHECK(on_chunk(ctx, t1));
+    }
+    p->last_loop_ms = total_ms;
+    p->last_step_ms = T > 0 ? total_ms / T : 0.0;
   } else {
     MFE_HIP(hipEventRecord(p->ev0, run_st));
     launch_steps(run_st);
@@ -526,10 +547,12 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   int flag = 0;
   MFE_HIP(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, run_st));
   MFE_HIP(hipStreamSynchronize(run_st));
-  float ms = 0.f;
-  MFE_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-  p->last_loop_ms = ms;
-  p->last_step_ms = T > 0 ? ms / T : 0.0;
+  if (trace_every <= 0 || use_graph) {
+    float ms = 0.f;
+    MFE_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    p->last_loop_ms = ms;
+    p->last_step_ms = T > 0 ? ms / T : 0.0;
+  }
   if (flag & 2) return set_error(MFE_EINVAL, "warm start u0/v0 outside the box [-M, M] (or NaN)");
   if (flag & 1) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
   return MFE_OK;

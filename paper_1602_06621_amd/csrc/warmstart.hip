@@ -1,0 +1,554 @@
+// Learned warm start for Algorithm 1: probe sketches -> per-index features -> a small
+// MLP -> initial (u0, v0), used with a step offset t0 (tau = t + t0).
+//
+// Sketch.  At (u, v) = 0 the estimator of Section 3.1 with ks probes per side gives
+// r_i ~ ||row_i(A)||^2 and c_j ~ ||col_j(A)||^2 (probe signs: sides 2 and 3 of the
+// stream, step 0).  For A = diag(a) G diag(b) with iid unit-variance G, the scalings
+// u_i = -1/2 log r_i + c, v_j = -1/2 log c_j + c with e^(4c) = alpha^2 F / n (F the
+// squared Frobenius norm) equilibrate A in expectation; that closed form is the
+// "sketch initialisation".  The network learns the correction from it to the
+// regularised optimum (labels: plain projected SGD run to convergence).
+//
+// Features of an index (row or column of matrix b), FP32:
+//   f0 = (l - mean l)/4   l = log of its sketch norm estimate, mean over its side of b
+//   f1 = s/4              the sketch initialisation (clipped to the box)
+//   f2 = log(target)      log alpha^2 (rows) or log beta^2 (columns)
+//   f3 = std(l)/4         spread of the log norms over its side of b
+//   f4 = 1 for rows, 0 for columns
+//   f5 = log(m_b / n_b)
+//   f6 = c                the constant of the sketch initialisation
+//   f7 = log(max_p y_p^2 / mean_p y_p^2) (sketch noise of this index; 0 if empty)
+//
+// Network: h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 w3 + b3, width 64, FP32.
+// Parameters in one flat FP32 vector: W1 (F x 64, row-major), b1, W2 (64 x 64), b2, w3, b3.
+// Training: mean squared error, Adam (Kingma & Ba), mini-batches drawn with replacement
+// by a counter-based Philox stream; every reduction is fixed-order (deterministic).
+#include <cmath>
+#include <vector>
+
+#include "sparse.h"
+
+namespace mfe {
+namespace {
+
+constexpr int kH = 64;
+constexpr int kF = 8;
+constexpr int kP = kF * kH + kH + kH * kH + kH + kH + 1;  // 4801 parameters
+
+struct Work {
+  std::vector<void*> bufs;
+  ~Work() {
+    for (void* p : bufs) (void)hipFree(p);
+  }
+  template <class T>
+  int alloc(T** p, int64_t n) {
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    if (e != hipSuccess)
+      return set_error(e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EDEVICE, "hipMalloc failed: %s",
+                       hipGetErrorString(e));
+    bufs.push_back(*p);
+    return MFE_OK;
+  }
+};
+
+// ---------------------------------------------------------------- sketch
+
+// Per index (internal order, one direction): y_p = sum_q a_q (-1)^bit(other index, p)
+// for p < ks, at u = v = 0.  Writes, in original order, the estimate mean_p y_p^2 and
+// the ratio max_p y_p^2 / mean.
+template <int KS>
+__global__ __launch_bounds__(256) void k_sketch(SideDev S, const MatDev* __restrict__ mats,
+                                                const uint64_t* __restrict__ sw_other,
+                                                const int64_t* __restrict__ word_base_other,
+                                                const int32_t* __restrict__ other_mat_of_int,
+                                                const int32_t* __restrict__ other_orig,
+                                                double* __restrict__ est, double* __restrict__ ratio) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.nint) return;
+  const int32_t li = S.orig[r];
+  if (li < 0) return;
+  const int64_t s = r >> 6;
+  const int lane = (int)(r & 63);
+  const int len = S.len[r];
+  const int2* e = S.ent + S.slice_off[s] + lane;
+  double acc[KS];
+#pragma unroll
+  for (int p = 0; p < KS; ++p) acc[p] = 0.0;
+  for (int q = 0; q < len; ++q) {
+    const int2 en = e[(int64_t)q * kSlice];
+    const int32_t o = en.x;  // other direction, internal index
+    const int32_t b = other_mat_of_int[o >> 6];
+    const int64_t g = (int64_t)other_orig[o] * KS;
+    const uint64_t bits = extract_bits(sw_other + word_base_other[b], g, KS);
+    accumulate_signed<KS>(acc, (double)__int_as_float(en.y), bits);
+  }
+  double mean = 0.0, mx = 0.0;
+#pragma unroll
+  for (int p = 0; p < KS; ++p) {
+    const double y2 = acc[p] * acc[p];
+    mean += y2;
+    mx = fmax(mx, y2);
+  }
+  mean /= KS;
+  const MatDev mt = mats[S.slice_mat[s]];
+  const int64_t gi = (S.is_row ? mt.row_orig_base : mt.col_orig_base) + li;
+  est[gi] = mean;
+  ratio[gi] = mean > 0.0 ? mx / mean : 0.0;
+}
+
+// Per matrix and side (one workgroup each): mean and std of log(est) over the non-empty
+// indices, sum of est.  stats[b] = {mean, std, sum}.
+__global__ __launch_bounds__(256) void k_side_stats(const double* __restrict__ est, const int64_t* __restrict__ base,
+                                                    double* __restrict__ stats) {
+  __shared__ double sh[3][256];
+  const int b = blockIdx.x;
+  const int64_t lo = base[b], hi = base[b + 1];
+  double s1 = 0, s2 = 0, cnt = 0, sum = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double x = est[i];
+    sum += x;
+    if (x > 0) {
+      const double l = log(x);
+      s1 += l;
+      s2 += l * l;
+      cnt += 1;
+    }
+  }
+  sh[0][threadIdx.x] = s1;
+  sh[1][threadIdx.x] = s2;
+  sh[2][threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  const double S1 = sh[0][0], S2 = sh[1][0], C = sh[2][0];
+  __syncthreads();
+  sh[0][threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = C > 0 ? S1 / C : 0.0;
+    const double var = C > 0 ? fmax(S2 / C - mean * mean, 0.0) : 0.0;
+    stats[3 * b + 0] = mean;
+    stats[3 * b + 1] = sqrt(var);
+    stats[3 * b + 2] = sh[0][0];
+  }
+}
+
+struct FeatMat {
+  double tgt_row, tgt_col;  // alpha^2, beta^2
+  double log_mn;            // log(m / n)
+  double c;                 // 1/4 log(alpha^2 F / n)
+  int64_t row_base, col_base;
+  int64_t m, n;
+};
+
+// Features and sketch initialisation of one side (original order), matrix per index
+// found by binary search over the bases.
+__global__ void k_features(const double* __restrict__ est, const double* __restrict__ ratio,
+                           const double* __restrict__ stats, const FeatMat* __restrict__ fm, int count, int is_row,
+                           int64_t total, double gamma, double M, float* __restrict__ feat,
+                           double* __restrict__ sketch_init) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((is_row ? fm[mid].row_base : fm[mid].col_base) <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const FeatMat f = fm[lo];
+  const double tgt = is_row ? f.tgt_row : f.tgt_col;
+  const double x = est[i];
+  const double mean = stats[3 * lo], sd = stats[3 * lo + 1];
+  double s, l;
+  if (x > 0) {
+    l = log(x);
+    s = -0.5 * l + f.c;
+  } else {
+    l = mean;                         // no entries: no information about the norm
+    s = fmin(tgt / gamma, M);         // where an index without entries settles (Section 2.3)
+  }
+  s = fmin(fmax(s, -M), M);
+  sketch_init[i] = s;
+  float* o = feat + i * kF;
+  o[0] = (float)((l - mean) / 4.0);
+  o[1] = (float)(s / 4.0);
+  o[2] = (float)log(tgt);
+  o[3] = (float)(sd / 4.0);
+  o[4] = is_row ? 1.f : 0.f;
+  o[5] = (float)f.log_mn;
+  o[6] = (float)f.c;
+  o[7] = (float)(ratio[i] > 0 ? log(ratio[i]) : 0.0);
+}
+
+// ---------------------------------------------------------------- network
+
+__device__ inline void philox_index(uint64_t seed, uint64_t it, uint64_t b, int64_t count, int64_t& out) {
+  const U64x4 w = philox4x64_10(b + 1, 0, 0, 0, seed, (it << 2) | 3ull);
+  out = (int64_t)(w.x[0] % (uint64_t)count);
+}
+
+// Forward for `count` samples (rows of X, or X[idx[b]] when idx is given); optionally
+// keeps h1, h2 for the backward pass.  Parameters are staged in LDS.
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ params, const float* __restrict__ X,
+                                                 const int64_t* __restrict__ idx, int64_t count, float* __restrict__ y,
+                                                 float* __restrict__ h1s, float* __restrict__ h2s) {
+  __shared__ float P[kP];
+  for (int i = threadIdx.x; i < kP; i += 256) P[i] = params[i];
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  const float* W1 = P;
+  const float* b1 = W1 + kF * kH;
+  const float* W2 = b1 + kH;
+  const float* b2 = W2 + kH * kH;
+  const float* w3 = b2 + kH;
+  const float b3 = w3[kH];
+  const int64_t row = idx ? idx[b] : b;
+  float x[kF];
+#pragma unroll
+  for (int f = 0; f < kF; ++f) x[f] = X[row * kF + f];
+  float h1[kH];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) {
+    float a = b1[j];
+#pragma unroll
+    for (int f = 0; f < kF; ++f) a = fmaf(x[f], W1[f * kH + j], a);
+    h1[j] = tanhf(a);
+  }
+  float out = b3;
+  for (int j = 0; j < kH; ++j) {
+    float a = b2[j];
+#pragma unroll
+    for (int i = 0; i < kH; ++i) a = fmaf(h1[i], W2[i * kH + j], a);
+    const float h = tanhf(a);
+    if (h2s) h2s[b * kH + j] = h;
+    out = fmaf(h, w3[j], out);
+  }
+  if (h1s)
+    for (int j = 0; j < kH; ++j) h1s[b * kH + j] = h1[j];
+  y[b] = out;
+}
+
+// Per-sample backward: gy = 2 (y - t)/B, gh2 = gy w3 (1 - h2^2), gh1 = (gh2 W2') (1 - h1^2).
+// Also the per-sample squared error for the loss.
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float* __restrict__ params, const float* __restrict__ y,
+                                                 const float* __restrict__ t, const int64_t* __restrict__ idx,
+                                                 int64_t count, const float* __restrict__ h1s,
+                                                 const float* __restrict__ h2s, float* __restrict__ gy,
+                                                 float* __restrict__ gh1, float* __restrict__ gh2,
+                                                 double* __restrict__ se) {
+  __shared__ float P[kH * kH + 2 * kH];
+  const float* W2g = params + kF * kH + kH;
+  for (int i = threadIdx.x; i < kH * kH; i += 256) P[i] = W2g[i];
+  const float* w3g = W2g + kH * kH + kH;
+  for (int i = threadIdx.x; i < kH; i += 256) P[kH * kH + i] = w3g[i];
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  const float* W2 = P;
+  const float* w3 = P + kH * kH;
+  const int64_t row = idx ? idx[b] : b;
+  const float r = y[b] - t[row];
+  se[b] = (double)r * (double)r;
+  const float g = 2.0f * r / (float)count;
+  gy[b] = g;
+  float g2[kH];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) {
+    const float h = h2s[b * kH + j];
+    g2[j] = g * w3[j] * (1.0f - h * h);
+    gh2[b * kH + j] = g2[j];
+  }
+  for (int i = 0; i < kH; ++i) {
+    float a = 0.f;
+#pragma unroll
+    for (int j = 0; j < kH; ++j) a = fmaf(g2[j], W2[i * kH + j], a);
+    const float h = h1s[b * kH + i];
+    gh1[b * kH + i] = a * (1.0f - h * h);
+  }
+}
+
+// Weight gradients: one thread per parameter, fixed-order sum over the batch.
+__global__ __launch_bounds__(256) void k_mlp_wgrad(const float* __restrict__ X, const int64_t* __restrict__ idx,
+                                                   int64_t count, const float* __restrict__ gy,
+                                                   const float* __restrict__ h1s, const float* __restrict__ h2s,
+                                                   const float* __restrict__ gh1, const float* __restrict__ gh2,
+                                                   float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kP) return;
+  double acc = 0.0;
+  if (p < kF * kH) {  // W1[f][j]
+    const int f = p / kH, j = p % kH;
+    for (int64_t b = 0; b < count; ++b) acc += (double)X[(idx ? idx[b] : b) * kF + f] * gh1[b * kH + j];
+  } else if (p < kF * kH + kH) {  // b1[j]
+    const int j = p - kF * kH;
+    for (int64_t b = 0; b < count; ++b) acc += gh1[b * kH + j];
+  } else if (p < kF * kH + kH + kH * kH) {  // W2[i][j]
+    const int q = p - (kF * kH + kH), i = q / kH, j = q % kH;
+    for (int64_t b = 0; b < count; ++b) acc += (double)h1s[b * kH + i] * gh2[b * kH + j];
+  } else if (p < kF * kH + 2 * kH + kH * kH) {  // b2[j]
+    const int j = p - (kF * kH + kH + kH * kH);
+    for (int64_t b = 0; b < count; ++b) acc += gh2[b * kH + j];
+  } else if (p < kF * kH + 3 * kH + kH * kH) {  // w3[j]
+    const int j = p - (kF * kH + 2 * kH + kH * kH);
+    for (int64_t b = 0; b < count; ++b) acc += (double)gy[b] * h2s[b * kH + j];
+  } else {  // b3
+    for (int64_t b = 0; b < count; ++b) acc += gy[b];
+  }
+  grad[p] = (float)acc;
+}
+
+__global__ void k_sum(const double* __restrict__ v, int64_t n, double scale, double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
+}
+
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int step, float lr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float gi = g[p];
+  const float mi = b1 * m[p] + (1.f - b1) * gi;
+  const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
+  m[p] = mi;
+  v[p] = vi;
+  const float mh = mi / (1.f - powf(b1, (float)step));
+  const float vh = vi / (1.f - powf(b2, (float)step));
+  th[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_batch_indices(uint64_t seed, uint64_t it, int64_t count, int64_t total, int64_t* __restrict__ idx) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < count) philox_index(seed, it, (uint64_t)b, total, idx[b]);
+}
+
+__global__ void k_apply_delta(int64_t n, const double* __restrict__ s, const float* __restrict__ d, double M,
+                              double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = fmin(fmax(s[i] + (double)(d ? d[i] : 0.f), -M), M);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- drivers
+
+int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
+                         double gamma, double M, float* feat_rows, float* feat_cols, double* u_sketch,
+                         double* v_sketch, hipStream_t st) {
+  if (ks != 4 && ks != 8 && ks != 16) return set_error(MFE_EINVAL, "sketch probes must be 4, 8 or 16");
+  MFE_CHECK(ensure_mats(p, st));
+  const int count = p->count;
+  // sketch sign words: side 2 (indexed by column) and side 3 (by row), step 0, batch b
+  std::vector<SignSeg> segs;
+  std::vector<int64_t> prefix{0}, wb_col(count), wb_row(count);
+  int64_t words = 0, blocks = 0;
+  for (int side = 2; side < 4; ++side)
+    for (int b = 0; b < count; ++b) {
+      const int64_t cnt = side == 2 ? p->meta[b].n : p->meta[b].m;
+      SignSeg sg;
+      sg.ctrl_lo = ((uint64_t)b << 34) | (uint64_t)side;
+      sg.nblocks = ceil_div(cnt * ks, 256);
+      sg.word_off = words;
+      (side == 2 ? wb_col : wb_row)[b] = words;
+      words += 4 * sg.nblocks + 4;
+      blocks += sg.nblocks;
+      prefix.push_back(blocks);
+      segs.push_back(sg);
+    }
+  Work W;
+  SignSeg* d_segs;
+  int64_t *d_prefix, *d_wb_col, *d_wb_row, *d_rbase, *d_cbase;
+  uint64_t* sw;
+  int32_t *mat_of_row_slice, *mat_of_col_slice;
+  double *est_r, *est_c, *rat_r, *rat_c, *st_r, *st_c;
+  FeatMat* d_fm;
+  MFE_CHECK(W.alloc(&d_segs, (int64_t)segs.size()));
+  MFE_CHECK(W.alloc(&d_prefix, (int64_t)prefix.size()));
+  MFE_CHECK(W.alloc(&d_wb_col, count));
+  MFE_CHECK(W.alloc(&d_wb_row, count));
+  MFE_CHECK(W.alloc(&sw, words));
+  MFE_CHECK(W.alloc(&est_r, p->M));
+  MFE_CHECK(W.alloc(&est_c, p->N));
+  MFE_CHECK(W.alloc(&rat_r, p->M));
+  MFE_CHECK(W.alloc(&rat_c, p->N));
+  MFE_CHECK(W.alloc(&st_r, 3 * count));
+  MFE_CHECK(W.alloc(&st_c, 3 * count));
+  MFE_CHECK(W.alloc(&d_rbase, count + 1));
+  MFE_CHECK(W.alloc(&d_cbase, count + 1));
+  MFE_CHECK(W.alloc(&d_fm, count));
+  mat_of_row_slice = p->rows.slice_mat;
+  mat_of_col_slice = p->cols.slice_mat;
+  MFE_HIP(hipMemcpyAsync(d_segs, segs.data(), sizeof(SignSeg) * segs.size(), hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemcpyAsync(d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemcpyAsync(d_wb_col, wb_col.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemcpyAsync(d_wb_row, wb_row.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemsetAsync(sw, 0, sizeof(uint64_t) * words, st));
+  SignGenDev g;
+  g.segs = d_segs;
+  g.seg_prefix = d_prefix;
+  g.nseg = (int32_t)segs.size();
+  g.nblocks = blocks;
+  g.seed = seed;
+  g.step = 0;
+  g.out = sw;
+  MFE_CHECK(launch_signgen(g, st));
+  SideDev R{}, C{};
+  R.slice_off = p->rows.slice_off;
+  R.slice_mat = p->rows.slice_mat;
+  R.len = p->rows.len;
+  R.orig = p->rows.orig;
+  R.ent = p->rows.ent;
+  R.nint = p->rows.nint;
+  R.is_row = 1;
+  C.slice_off = p->cols.slice_off;
+  C.slice_mat = p->cols.slice_mat;
+  C.len = p->cols.len;
+  C.orig = p->cols.orig;
+  C.ent = p->cols.ent;
+  C.nint = p->cols.nint;
+  C.is_row = 0;
+  const unsigned gr = (unsigned)ceil_div(p->rows.nint, 256), gc = (unsigned)ceil_div(p->cols.nint, 256);
+  // rows gather column-indexed sketch signs (side 2); columns gather row-indexed (side 3)
+  if (ks == 4) {
+    k_sketch<4><<<gr, 256, 0, st>>>(R, p->mats, sw, d_wb_col, mat_of_col_slice, p->cols.orig, est_r, rat_r);
+    k_sketch<4><<<gc, 256, 0, st>>>(C, p->mats, sw, d_wb_row, mat_of_row_slice, p->rows.orig, est_c, rat_c);
+  } else if (ks == 8) {
+    k_sketch<8><<<gr, 256, 0, st>>>(R, p->mats, sw, d_wb_col, mat_of_col_slice, p->cols.orig, est_r, rat_r);
+    k_sketch<8><<<gc, 256, 0, st>>>(C, p->mats, sw, d_wb_row, mat_of_row_slice, p->rows.orig, est_c, rat_c);
+  } else {
+    k_sketch<16><<<gr, 256, 0, st>>>(R, p->mats, sw, d_wb_col, mat_of_col_slice, p->cols.orig, est_r, rat_r);
+    k_sketch<16><<<gc, 256, 0, st>>>(C, p->mats, sw, d_wb_row, mat_of_row_slice, p->rows.orig, est_c, rat_c);
+  }
+  std::vector<int64_t> rb(count + 1), cb(count + 1);
+  rb[0] = cb[0] = 0;
+  for (int b = 0; b < count; ++b) {
+    rb[b + 1] = rb[b] + p->meta[b].m;
+    cb[b + 1] = cb[b] + p->meta[b].n;
+  }
+  MFE_HIP(hipMemcpyAsync(d_rbase, rb.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, st));
+  MFE_HIP(hipMemcpyAsync(d_cbase, cb.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, st));
+  k_side_stats<<<count, 256, 0, st>>>(est_r, d_rbase, st_r);
+  k_side_stats<<<count, 256, 0, st>>>(est_c, d_cbase, st_c);
+  MFE_HIP(hipGetLastError());
+  std::vector<double> hr(3 * count), hc(3 * count);
+  MFE_HIP(hipMemcpyAsync(hr.data(), st_r, sizeof(double) * 3 * count, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipMemcpyAsync(hc.data(), st_c, sizeof(double) * 3 * count, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  std::vector<FeatMat> fm(count);
+  for (int b = 0; b < count; ++b) {
+    const double al = alpha_b ? alpha_b[b] : std::pow((double)p->meta[b].n / p->meta[b].m, 0.25);
+    const double be = beta_b ? beta_b[b] : std::pow((double)p->meta[b].m / p->meta[b].n, 0.25);
+    const double F = 0.5 * (hr[3 * b + 2] + hc[3 * b + 2]);
+    fm[b].tgt_row = al * al;
+    fm[b].tgt_col = be * be;
+    fm[b].log_mn = std::log((double)p->meta[b].m / p->meta[b].n);
+    fm[b].c = F > 0 ? 0.25 * std::log(al * al * F / (double)p->meta[b].n) : 0.0;
+    fm[b].row_base = rb[b];
+    fm[b].col_base = cb[b];
+    fm[b].m = p->meta[b].m;
+    fm[b].n = p->meta[b].n;
+  }
+  MFE_HIP(hipMemcpyAsync(d_fm, fm.data(), sizeof(FeatMat) * count, hipMemcpyHostToDevice, st));
+  k_features<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(est_r, rat_r, st_r, d_fm, count, 1, p->M, gamma, M, feat_rows,
+                                                             u_sketch);
+  k_features<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(est_c, rat_c, st_c, d_fm, count, 0, p->N, gamma, M, feat_cols,
+                                                             v_sketch);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
+int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st) {
+  if (count <= 0) return MFE_OK;
+  k_mlp_fwd<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(params, X, nullptr, count, y, nullptr, nullptr);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
+int mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
+              int64_t total, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,
+              hipStream_t st) {
+  Work W;
+  int64_t* idx;
+  float *y, *gy, *h1, *h2, *g1, *g2, *grad;
+  double *se, *loss;
+  MFE_CHECK(W.alloc(&idx, batch));
+  MFE_CHECK(W.alloc(&y, batch));
+  MFE_CHECK(W.alloc(&gy, batch));
+  MFE_CHECK(W.alloc(&h1, batch * kH));
+  MFE_CHECK(W.alloc(&h2, batch * kH));
+  MFE_CHECK(W.alloc(&g1, batch * kH));
+  MFE_CHECK(W.alloc(&g2, batch * kH));
+  MFE_CHECK(W.alloc(&grad, kP));
+  MFE_CHECK(W.alloc(&se, batch));
+  MFE_CHECK(W.alloc(&loss, std::max(iters, 1)));
+  const unsigned gb = (unsigned)ceil_div(batch, 256), gp = (unsigned)ceil_div(kP, 256);
+  for (int it = 0; it < iters; ++it) {
+    const uint64_t step = (uint64_t)step0 + it + 1;
+    k_batch_indices<<<gb, 256, 0, st>>>(seed, step, batch, total, idx);
+    k_mlp_fwd<<<gb, 256, 0, st>>>(params, X, idx, batch, y, h1, h2);
+    k_mlp_bwd<<<gb, 256, 0, st>>>(params, y, t, idx, batch, h1, h2, gy, g1, g2, se);
+    k_mlp_wgrad<<<gp, 256, 0, st>>>(X, idx, batch, gy, h1, h2, g1, g2, grad);
+    k_sum<<<1, 256, 0, st>>>(se, batch, 1.0 / (double)batch, loss + it);
+    k_adam<<<gp, 256, 0, st>>>(params, grad, adam_m, adam_v, (int)step, lr);
+  }
+  MFE_HIP(hipGetLastError());
+  if (loss_trace && iters > 0)
+    MFE_HIP(hipMemcpyAsync(loss_trace, loss, sizeof(double) * iters, hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
+int mlp_grad(const float* params, const float* X, const float* t, int64_t count, float* grad, double* loss,
+             hipStream_t st) {
+  Work W;
+  float *y, *gy, *h1, *h2, *g1, *g2;
+  double *se, *l;
+  MFE_CHECK(W.alloc(&y, count));
+  MFE_CHECK(W.alloc(&gy, count));
+  MFE_CHECK(W.alloc(&h1, count * kH));
+  MFE_CHECK(W.alloc(&h2, count * kH));
+  MFE_CHECK(W.alloc(&g1, count * kH));
+  MFE_CHECK(W.alloc(&g2, count * kH));
+  MFE_CHECK(W.alloc(&se, count));
+  MFE_CHECK(W.alloc(&l, 1));
+  const unsigned gb = (unsigned)ceil_div(count, 256), gp = (unsigned)ceil_div(kP, 256);
+  k_mlp_fwd<<<gb, 256, 0, st>>>(params, X, nullptr, count, y, h1, h2);
+  k_mlp_bwd<<<gb, 256, 0, st>>>(params, y, t, nullptr, count, h1, h2, gy, g1, g2, se);
+  k_mlp_wgrad<<<gp, 256, 0, st>>>(X, nullptr, count, gy, h1, h2, g1, g2, grad);
+  k_sum<<<1, 256, 0, st>>>(se, count, 1.0 / (double)count, l);
+  MFE_HIP(hipGetLastError());
+  if (loss) MFE_HIP(hipMemcpyAsync(loss, l, sizeof(double), hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
+int warmstart_apply(int64_t n, const double* sketch, const float* delta, double M, double* out, hipStream_t st) {
+  if (n <= 0) return MFE_OK;
+  k_apply_delta<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, sketch, delta, M, out);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
+int mlp_param_count() { return kP; }
+int mlp_feature_count() { return kF; }
+
+}  // namespace mfe

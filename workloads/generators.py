@@ -182,3 +182,22 @@ def csr_from_dense(A: np.ndarray) -> CSR:
     S.sort_indices()
     return CSR(A.shape[0], A.shape[1], S.indptr.astype(np.int32), S.indices.astype(np.int32),
                S.data.astype(np.float32))
+
+
+def warmstart_matrix(m: int, n: int, sigma: float, seed: int, lo: int = 8, hi: int = 16) -> CSR:
+    """Sparse CSR with U{lo..hi} entries per row and log-normal scales sigma (the
+    learned-warm-start workloads)."""
+    g = rng(seed)
+    lengths = g.integers(lo, hi + 1, size=m)
+    return scaled_sparse(m, n, lengths, sigma, seed + 1)
+
+
+def warmstart_training_set(count: int, seed: int, m_lo=10_000, m_hi=50_000, s_lo=0.5, s_hi=3.0):
+    """Training matrices for the warm start: m ~ U[m_lo, m_hi], n = m/2, sigma ~ U[s_lo, s_hi]."""
+    g = rng(seed)
+    out = []
+    for b in range(count):
+        m = int(g.integers(m_lo, m_hi + 1))
+        s = float(g.uniform(s_lo, s_hi))
+        out.append(warmstart_matrix(m, max(1, m // 2), s, seed * 1009 + 3 * b))
+    return out
