@@ -114,6 +114,10 @@ def bench_c2(mfe):
     torch.cuda.synchronize()
     prep_ms = (time.time() - t0) * 1e3
     T, k = 1000, 8
+    torch.cuda.synchronize()
+    t0 = time.time()
+    tune = plan.autotune(None, None, GAMMA, BOX_M, k, 2002, trial_steps=20)
+    tune_s = time.time() - t0
     s, out = timed(lambda: plan.equilibrate(None, None, GAMMA, BOX_M, T, k, 2002, use_graph=True), 2, 1)
     tim = plan.last_timing()
     plan.close()
@@ -122,6 +126,7 @@ def bench_c2(mfe):
             "sum_m": M, "sum_n": N, "nnz": nnz, "ms_per_run": s * 1e3, "step_ms": tim["step_ms"],
             "pairs_per_s": 512 * T * k / s, "algorithmic_gbs": by / (tim["step_ms"] / 1e3) / 1e9,
             "hbm_frac": by / (tim["step_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, "prep_ms": prep_ms, "gen_s": gen_s,
+            "autotune": tune, "autotune_s": tune_s,
             "finite": bool(torch.isfinite(out["u_bar"]).all().item())}
 
 
@@ -270,7 +275,7 @@ def bench_lsqr(mfe, plan, csr, out):
 
 
 def profile_run():
-    """Counter run: 20 steps of the headline workload (per-launch counters are what is
+    """Counter run: autotuning, then 20 steps of the headline workload (per-launch counters are what is
     read), then a plain device copy of 512 MiB whose FETCH_SIZE / WRITE_SIZE calibrate
     the counters (the source is flushed from the caches by a 2 GiB fill first)."""
     import torch
@@ -283,6 +288,8 @@ def profile_run():
     A = mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")
     al, be = mfe.default_alpha_beta(csr.m, csr.n)
     plan = mfe.Plan([A], max_probes=K_PROBES)
+    plan.autotune(al, be, GAMMA, BOX_M, K_PROBES, PROBE_SEED, trial_steps=20)
+    # the measured run: the last 20 steps of each launch in the trace
     plan.equilibrate(al, be, GAMMA, BOX_M, 20, K_PROBES, PROBE_SEED, use_graph=False)
     torch.cuda.synchronize()
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
@@ -310,8 +317,8 @@ def main():
                          "then a 512 MiB device copy used to calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); how the path would shard "
-              "across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
+              "of the path is designed but not built.", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     work = set(args.workloads.split(","))
@@ -337,6 +344,9 @@ def main():
     plan = mfe.Plan([A], max_probes=K_PROBES)
     torch.cuda.synchronize()
     prep_ms = (time.time() - t0) * 1e3
+    t0 = time.time()
+    tune = plan.autotune(al, be, GAMMA, BOX_M, K_PROBES, PROBE_SEED, trial_steps=20)
+    tune_s = time.time() - t0
     run = dict(alpha=al, beta=be, gamma=GAMMA, M=BOX_M, steps=T_STEPS, probes=K_PROBES, seed=PROBE_SEED,
                use_graph=not args.no_graph)
     out = None
@@ -356,7 +366,7 @@ def main():
     bytes_launch = sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, K_PROBES)
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
 
-    extra = {"prep_ms": prep_ms, "gen_s": gen_s,
+    extra = {"prep_ms": prep_ms, "gen_s": gen_s, "autotune": tune, "autotune_s": tune_s,
              "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
     for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3), ("c4", bench_c4)):
         if name in work:

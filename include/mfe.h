@@ -239,6 +239,20 @@ int mfe_warmstart_apply(int64_t n, const double* sketch, const float* delta, dou
 int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_t trace_every,
                                double* rms_trace, double* d, double* e, double* u_bar, double* v_bar);
 
+/* Autotuner of a plan's step kernels (the products of Algorithm 1, Section 3.2, in the
+ * batched layouts).  Runs trial_steps steps (1..100000, eagerly, results discarded) of
+ * every launch configuration with the run parameters p (probes, targets, seed) and keeps
+ * the fastest in the plan for its later runs.  Configurations: 4, 8 or 16 entry loads in
+ * flight per lane (16 only for p->probes <= 16), and, for a single-matrix plan whose
+ * gathered table exceeds 6 MB, each direction as one launch or as two launches over
+ * halves of the table with FP64 partial sums in between.  Every configuration sums the
+ * same terms in the same order, so tuning never changes a result bit.
+ * chosen (host int32[3], nullable): loads in flight, two-part rows, two-part columns;
+ * best_step_ms, n_candidates: nullable.  Allocates two temporary device arrays.
+ * EINVAL: plan NULL, invalid p (as mfe_plan_equilibrate), trial_steps out of range. */
+int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
+                      int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates);
+
 /* Thread-local description of the last non-OK status (or a warning), never NULL. */
 const char* mfe_last_error(void);
 

@@ -79,6 +79,7 @@ def _lib():
                          C.POINTER(i64), vp],
         "mfe_draw_signs": [u64, i32, i64, i32, i64, vp, vp],
         "mfe_plan_equilibrate_trace": [vp, C.POINTER(_Params), i32, C.POINTER(dbl), vp, vp, vp, vp],
+        "mfe_plan_autotune": [vp, C.POINTER(_Params), vp, vp, i32, vp, C.POINTER(dbl), C.POINTER(i32)],
         "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
         "mfe_mlp_sizes": [C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "mfe_mlp_forward": [vp, vp, i64, vp, vp],
@@ -322,6 +323,28 @@ class Plan:
         _check(lib.mfe_plan_equilibrate(self._h, C.byref(p), ah, bh, int(bool(use_graph)), _ptr(out["d"]),
                                         _ptr(out["e"]), _ptr(out.get("u_bar")), _ptr(out.get("v_bar"))))
         return out
+
+    def _targets(self, alpha, beta):
+        cnt = len(self.mats)
+        if alpha is None or beta is None:
+            ab = [default_alpha_beta(mm.m, mm.n) for mm in self.mats]
+            alpha = [a for a, _ in ab]
+            beta = [b for _, b in ab]
+        al = [float(alpha)] * cnt if isinstance(alpha, (int, float)) else [float(a) for a in alpha]
+        be = [float(beta)] * cnt if isinstance(beta, (int, float)) else [float(b) for b in beta]
+        return (C.c_double * cnt)(*al), (C.c_double * cnt)(*be), al[0], be[0]
+
+    def autotune(self, alpha=None, beta=None, gamma=0.1, M=10.0, probes=1, seed=0, trial_steps=20, stream=None):
+        """Times every launch configuration of the step kernels (results are identical under
+        all of them) and keeps the fastest for this plan.  Returns the choice."""
+        ah, bh, a0, b0 = self._targets(alpha, beta)
+        p = _params(a0, b0, gamma, M, trial_steps, probes, seed, 0, 0, None, None, stream)
+        chosen = (C.c_int32 * 3)()
+        best, n = C.c_double(), C.c_int32()
+        _check(_lib().mfe_plan_autotune(self._h, C.byref(p), ah, bh, int(trial_steps), chosen, C.byref(best),
+                                        C.byref(n)))
+        return dict(loads_in_flight=chosen[0], two_part_rows=bool(chosen[1]), two_part_cols=bool(chosen[2]),
+                    step_ms=best.value, candidates=n.value)
 
     def last_timing(self):
         a, b = C.c_double(), C.c_double()

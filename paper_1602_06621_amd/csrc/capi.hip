@@ -247,6 +247,15 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
   return plan_equilibrate_trace(plan, p, trace_every, rms_trace, d, e, u_bar, v_bar);
 }
 
+int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
+                      int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  MFE_CHECK(check_params(p, true));
+  if (p->probes > plan->max_probes) return set_error(MFE_EINVAL, "probes exceed the plan's max_probes");
+  return plan_autotune(plan, p, alpha_b, beta_b, trial_steps, chosen, best_step_ms, n_candidates);
+}
+
 int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
                              const double* beta_b, double gamma, double box_M, float* feat_rows, float* feat_cols,
                              double* u_sketch, double* v_sketch, void* stream) {

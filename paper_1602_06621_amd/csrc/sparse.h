@@ -37,7 +37,18 @@ struct SideLayout {
   int32_t* orig = nullptr;        // [nint] local original index, -1 for padding lanes
   int32_t* orig2int = nullptr;    // [norig] global original index -> internal index
   int2* ent = nullptr;            // [nent] (other-side internal index, FP32 value bits)
+  // Two-part mode (single-matrix plans whose gathered table is larger than one XCD's L2):
+  // entries of every row are ordered so that those gathering other-side indices below
+  // split_at come first; len_lo[r] counts them.  A step then gathers from one half of
+  // the table per launch.
+  int64_t split_at = -1;          // -1: no two-part layout
+  int32_t* len_lo = nullptr;      // [nint]
 };
+
+// Gathered-table size (at 8 bytes per index) above which a plan builds the two-part
+// layout of a direction, so that the autotuner can try it: per launch, half the table
+// is gathered, which fits one XCD's 4 MB L2 better than the whole.
+constexpr int64_t kSplitBytes = 6ll << 20;
 
 // Per-matrix data the kernels need (device table).
 struct MatDev {
@@ -75,6 +86,11 @@ struct SideDev {
   void* out;                  // this side's descriptors for the next step
   const uint64_t* next_signs; // slot holding the sign words of step t + 1
   int is_row;                 // 1: rows (targets alpha^2, side-1 signs); 0: columns
+  // 0: whole rows; 1: entries [0, len_lo), k partial sums stored to part; 2: partial sums
+  // loaded from part, entries [len_lo, len), then the update
+  int part_mode;
+  const int32_t* len_lo;
+  double* part;               // [k][nint] FP64 partial sums
 };
 
 struct SignGenDev {
@@ -113,6 +129,12 @@ struct mfe_plan {
   mfe::Desc* desc_row[2] = {nullptr, nullptr};
   mfe::Desc* desc_col[2] = {nullptr, nullptr};
   uint64_t* signs[2] = {nullptr, nullptr};
+  double* part[2] = {nullptr, nullptr};  // partial sums of the two-part mode (rows, columns)
+  // Launch configuration of the step kernels, chosen by plan_autotune (results are the
+  // same bit for bit under every configuration): loads in flight per lane, and whether
+  // each direction (rows, columns) with a two-part layout runs as two launches.
+  int32_t tune_batch = mfe::kBatch;
+  int32_t tune_split[2] = {0, 0};
   int64_t sign_words = 0;           // words per slot
   int32_t sign_k = 0;               // k the sign layout was built for
   int64_t sign_batch_base = -1;     // batch index of matrix 0 in that layout
@@ -128,7 +150,7 @@ struct mfe_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  double graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double graph_key[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace mfe {
@@ -141,6 +163,11 @@ void plan_free(mfe_plan* p);
 int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
              int use_graph, double* d, double* e, double* u_bar, double* v_bar, int trace_every = 0,
              int (*on_chunk)(void* ctx, int t) = nullptr, void* ctx = nullptr);
+// Times trial_steps steps of every launch configuration (loads in flight per lane;
+// two-part directions where the plan has them) with the run parameters prm and keeps
+// the fastest in the plan.  chosen[0..2] = batch, two-part rows, two-part columns.
+int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
+                  int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates);
 int plan_equilibrate_trace(mfe_plan* p, const mfe_equil_params* prm, int32_t trace_every, double* rms_trace,
                            double* d, double* e, double* u_bar, double* v_bar);
 int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,

@@ -193,6 +193,27 @@ __global__ void k_fill_entries(const int64_t* __restrict__ slice_off, const int3
   }
 }
 
+// Two-part layout: per internal index, the number of entries gathering other-side
+// indices below h; flags rows whose entries are not in that order (they always are for
+// a single matrix split at a window boundary, since windows keep original order).
+__global__ void k_split_len(const int64_t* __restrict__ slice_off, const int32_t* __restrict__ int_len,
+                            const int2* __restrict__ ent, int64_t nint, int64_t h, int32_t* __restrict__ len_lo,
+                            int* __restrict__ bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nint) return;
+  const int64_t base = slice_off[r / kSlice] + r % kSlice;
+  const int32_t len = int_len[r];
+  int32_t lo = 0;
+  bool high = false;
+  for (int32_t q = 0; q < len; ++q) {
+    const bool below = ent[base + (int64_t)q * kSlice].x < h;
+    if (below && high) *bad = 1;
+    if (below) ++lo;
+    else high = true;
+  }
+  len_lo[r] = lo;
+}
+
 __global__ void k_fill_slice_mat(int32_t* __restrict__ slice_mat, int64_t first, int64_t count, int32_t b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) slice_mat[first + i] = b;
@@ -291,7 +312,34 @@ int fill_side(SideLayout& L, const std::vector<int64_t>& counts, const int64_t* 
   return MFE_OK;
 }
 
+// Two-part layout of direction L, whose entries gather from `other`, if that table (at
+// 8 bytes per index) exceeds kSplitBytes.  Single-matrix plans only: in a batched plan
+// the slices running at one time belong to a few matrices, whose tables are small.
+int build_split(SideLayout& L, const SideLayout& other, int count, hipStream_t st) {
+  if (count != 1 || other.nint * 8 <= kSplitBytes) return MFE_OK;
+  const int64_t h = (other.norig / 2 / kWindow) * kWindow;
+  if (h <= 0) return MFE_OK;
+  Buf b_bad;
+  int* bad;
+  MFE_CHECK(talloc(b_bad, &bad, 1));
+  MFE_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+  MFE_CHECK(dalloc(&L.len_lo, L.nint));
+  k_split_len<<<grid_for(L.nint), 256, 0, st>>>(L.slice_off, L.len, L.ent, L.nint, h, L.len_lo, bad);
+  MFE_HIP(hipGetLastError());
+  int bad_h = 0;
+  MFE_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  if (bad_h) {
+    (void)hipFree(L.len_lo);
+    L.len_lo = nullptr;
+    return MFE_OK;
+  }
+  L.split_at = h;
+  return MFE_OK;
+}
+
 void free_side(SideLayout& L) {
+  (void)hipFree(L.len_lo);
   (void)hipFree(L.slice_off);
   (void)hipFree(L.slice_mat);
   (void)hipFree(L.len);
@@ -315,6 +363,7 @@ void plan_free(mfe_plan* p) {
     (void)hipFree(p->desc_row[i]);
     (void)hipFree(p->desc_col[i]);
     (void)hipFree(p->signs[i]);
+    (void)hipFree(p->part[i]);
   }
   (void)hipFree(p->segs);
   (void)hipFree(p->seg_prefix);
@@ -462,6 +511,8 @@ int plan_build(const mfe_matrix* mats, int32_t count, int32_t max_probes, hipStr
   MFE_CHECK(build_side_order(p->cols, ncount, ccnt, cmat, st));
   MFE_CHECK(fill_side(p->rows, mcount, gptr, gcol, gval, p->cols.orig2int, st));
   MFE_CHECK(fill_side(p->cols, ncount, cptr, crow, cval, p->rows.orig2int, st));
+  MFE_CHECK(build_split(p->rows, p->cols, count, st));
+  MFE_CHECK(build_split(p->cols, p->rows, count, st));
   {
     int64_t rb = 0, cb = 0;
     for (int b = 0; b < count; ++b) {

@@ -110,7 +110,7 @@ __device__ __forceinline__ void st_stream(Desc* p, Desc v) {
   st_stream(reinterpret_cast<u64x2*>(p), w);
 }
 
-template <int KP, bool PACKED>
+template <int KP, bool PACKED, int NB>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
   using C = Codec<KP, PACKED>;
@@ -119,27 +119,40 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   if (r >= S.nint) return;  // nint is a multiple of 64: whole wavefronts leave together
   const int64_t s = r >> 6;
   const int lane = (int)(threadIdx.x & 63);
+  const int mode = S.part_mode;  // uniform over the launch
   const int len = ld_stream(S.len + r);
+  const int split = mode != 0 ? ld_stream(S.len_lo + r) : 0;
+  const int q_beg = mode == 2 ? split : 0;
+  const int q_end = mode == 1 ? split : len;
+  // The epilogue's operands are loaded before the gather loop so their latency overlaps it.
+  int32_t li = 0, mi = 0;
+  double x_old = 0.0, xbar_old = 0.0;
+  if (mode != 1) {
+    li = ld_stream(S.orig + r);
+    x_old = ld_stream(S.x + r);
+    xbar_old = ld_stream(S.xbar + r);
+    mi = S.slice_mat[s];
+  }
   const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
   const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
   double acc[KP];
 #pragma unroll
-  for (int p = 0; p < KP; ++p) acc[p] = 0.0;
-  // Batches of kBatch slots: all entry loads of a batch are issued, then all descriptor
-  // gathers, then the accumulation, so a wavefront keeps 2 x kBatch independent memory
+  for (int p = 0; p < KP; ++p) acc[p] = (mode == 2 && p < k) ? ld_stream(S.part + (int64_t)p * S.nint + r) : 0.0;
+  // Batches of NB slots: all entry loads of a batch are issued, then all descriptor
+  // gathers, then the accumulation, so a wavefront keeps 2 x NB independent memory
   // requests in flight instead of one dependent load/gather pair per slot.
-  for (int q0 = 0; q0 < len; q0 += kBatch) {
-    long long en[kBatch];
+  for (int q0 = q_beg; q0 < q_end; q0 += NB) {
+    long long en[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      en[u] = (q0 + u < len) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
-    DT d[kBatch];
+    for (int u = 0; u < NB; ++u)
+      en[u] = (q0 + u < q_end) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
+    DT d[NB];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (q0 + u < len) d[u] = gather[(int32_t)(en[u] & 0xFFFFFFFFll)];
+    for (int u = 0; u < NB; ++u)
+      if (q0 + u < q_end) d[u] = gather[(int32_t)(en[u] & 0xFFFFFFFFll)];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      if (q0 + u < len) {
+    for (int u = 0; u < NB; ++u) {
+      if (q0 + u < q_end) {
         double scale;
         uint64_t bits;
         C::decode(d[u], scale, bits);
@@ -148,15 +161,18 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
       }
     }
   }
-  const int32_t li = ld_stream(S.orig + r);
+  if (mode == 1) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p)
+      if (p < k) st_stream(S.part + (int64_t)p * S.nint + r, acc[p]);
+    return;
+  }
   if (li < 0) return;
-  const MatDev mt = mats[S.slice_mat[s]];
+  const MatDev mt = mats[mi];
   double ss = 0.0;
 #pragma unroll
   for (int p = 0; p < KP; ++p)
     if (p < k) ss += acc[p] * acc[p];
-  const double x_old = ld_stream(S.x + r);
-  const double xbar_old = ld_stream(S.xbar + r);
   const double z = exp(2.0 * x_old) * (ss / (double)k);
   const double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
   const double g = (z - tgt) + sc.gamma * x_old;
@@ -195,10 +211,10 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk)
 
 // One direction of one step; extra workgroups past side_blocks draw the sign words
 // of step t+2 (the row launch carries them).
-template <int KP, bool PACKED>
+template <int KP, bool PACKED, int NB>
 __global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  if (b < a.side_blocks) side_update<KP, PACKED, NB>(a.side, a.mats, a.k, a.sc, b, a.flag);
   else signgen_block(a.gen, b - a.side_blocks);
 }
 
@@ -319,12 +335,15 @@ SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gath
   S.out = out;
   S.next_signs = next_signs;
   S.is_row = is_row;
+  S.part_mode = 0;
+  S.len_lo = L.len_lo;
+  S.part = nullptr;
   return S;
 }
 
-template <int KP, bool PACKED>
+template <int KP, bool PACKED, int NB>
 void launch_phase(const PhaseArgs& a, hipStream_t st) {
-  k_phase<KP, PACKED><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
+  k_phase<KP, PACKED, NB><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
 }
 
 template <int KP, bool PACKED>
@@ -352,9 +371,20 @@ void dispatch(int k, bool packed, Args&&... args) {
   }
 }
 
+// Loads in flight per lane: 4, 8 or 16 slots (16 only up to 16 probes, where the
+// accumulators leave room for it).
 template <int KP, bool PACKED>
 struct PhaseLauncher {
-  static void run(const PhaseArgs& a, hipStream_t st) { launch_phase<KP, PACKED>(a, st); }
+  static void run(const PhaseArgs& a, int nb, hipStream_t st) {
+    if (nb <= 4) {
+      launch_phase<KP, PACKED, 4>(a, st);
+    } else if constexpr (KP <= 16) {
+      if (nb >= 16) launch_phase<KP, PACKED, 16>(a, st);
+      else launch_phase<KP, PACKED, 8>(a, st);
+    } else {
+      launch_phase<KP, PACKED, 8>(a, st);
+    }
+  }
 };
 
 template <int KP, bool PACKED>
@@ -451,7 +481,19 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   // Step t = two launches (Jacobi order: both read the descriptors of step t-1):
   // the row direction (plus the sign words of step t+2), then the column direction.
   // Keeping the directions apart lets each launch's L2 hold only the table it gathers.
-  auto phase_args = [&](int t, bool rows) {
+  // A direction with a two-part layout runs as two launches, each gathering from one
+  // half of the table, when the plan's tuning says so.
+  const bool split_rows = p->rows.len_lo && p->tune_split[0];
+  const bool split_cols = p->cols.len_lo && p->tune_split[1];
+  const int nb = p->tune_batch;
+  for (int i = 0; i < 2; ++i) {
+    const bool need = i == 0 ? split_rows : split_cols;
+    if (need && !p->part[i]) {
+      const int64_t n = (i == 0 ? p->rows.nint : p->cols.nint) * (int64_t)p->max_probes;
+      MFE_CHECK(ensure(&p->part[i], n));
+    }
+  }
+  auto phase_args = [&](int t, bool rows, int mode) {
     PhaseArgs a;
     const int par = t & 1, prev = par ^ 1;
     if (rows)
@@ -460,8 +502,10 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     else
       a.side = make_side(p->cols, p->x_col, p->xbar_col, p->desc_row[prev], p->desc_col[par],
                          p->signs[(t + 1) & 1], 0);
+    a.side.part_mode = mode;
+    a.side.part = p->part[rows ? 0 : 1];
     const uint64_t gen_step = (uint64_t)t + 2;
-    const bool gen = rows && (int64_t)gen_step <= (int64_t)T + 1;
+    const bool gen = rows && mode != 2 && (int64_t)gen_step <= (int64_t)T + 1;
     a.gen = make_gen(p, seed, gen_step, p->signs[t & 1]);
     a.mats = p->mats;
     a.k = k;
@@ -475,21 +519,29 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     a.flag = p->flag;
     return a;
   };
-  auto launch_steps = [&](hipStream_t s) {
-    for (int t = 1; t <= T; ++t) {
-      dispatch<PhaseLauncher>(k, packed, phase_args(t, true), s);
-      dispatch<PhaseLauncher>(k, packed, phase_args(t, false), s);
+  auto launch_step = [&](int t, hipStream_t s) {
+    for (const bool rows : {true, false}) {
+      if (rows ? split_rows : split_cols) {
+        dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 1), nb, s);
+        dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 2), nb, s);
+      } else {
+        dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 0), nb, s);
+      }
     }
   };
+  auto launch_steps = [&](hipStream_t s) {
+    for (int t = 1; t <= T; ++t) launch_step(t, s);
+  };
 
-  // The step loop runs either as 2T launches or as one cached HIP graph of those
-  // launches (captured once per (k, T, t0, gamma, M, seed, batch)).
+  // The step loop runs either as 2T (or more) launches or as one cached HIP graph of
+  // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
-    const double key[8] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
-                           (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch};
+    const double key[11] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+                            (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
+                            (double)nb, (double)split_rows, (double)split_cols};
     bool hit = p->graph_exec != nullptr;
-    for (int i = 0; i < 8 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    for (int i = 0; i < 11 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     if (!hit) {
       if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -500,7 +552,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-      for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
+      for (int i = 0; i < 11; ++i) p->graph_key[i] = key[i];
     }
     if (st == nullptr) {
       // graphs are replayed on the plan's own stream, ordered after the default stream
@@ -516,10 +568,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     for (int t0 = 1; t0 <= T; t0 += trace_every) {
       const int t1 = std::min(T, t0 + trace_every - 1);
       MFE_HIP(hipEventRecord(p->ev0, run_st));
-      for (int t = t0; t <= t1; ++t) {
-        dispatch<PhaseLauncher>(k, packed, phase_args(t, true), run_st);
-        dispatch<PhaseLauncher>(k, packed, phase_args(t, false), run_st);
-      }
+      for (int t = t0; t <= t1; ++t) launch_step(t, run_st);
       MFE_HIP(hipGetLastError());
       MFE_HIP(hipEventRecord(p->ev1, run_st));
       MFE_HIP(hipEventSynchronize(p->ev1));
@@ -555,6 +604,74 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   }
   if (flag & 2) return set_error(MFE_EINVAL, "warm start u0/v0 outside the box [-M, M] (or NaN)");
   if (flag & 1) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
+  return MFE_OK;
+}
+
+}  // namespace mfe
+
+namespace mfe {
+
+int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, const double* beta_b,
+                  int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates) {
+  if (trial_steps < 1 || trial_steps > 100000) return set_error(MFE_EINVAL, "trial_steps must be in 1..100000");
+  const int k = prm->probes;
+  if (k < 1 || k > p->max_probes)
+    return set_error(MFE_EINVAL, "probes = %d outside 1..%d (the plan's max_probes)", k, p->max_probes);
+  struct Cand {
+    int nb, sr, sc;
+  };
+  std::vector<Cand> cands;
+  for (int nb : {4, 8, 16}) {
+    if (nb == 16 && k > 16) continue;
+    for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
+      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc});
+  }
+  double *d = nullptr, *e = nullptr;
+  MFE_CHECK(ensure(&d, p->M));
+  struct Free {
+    double*& a;
+    double*& b;
+    ~Free() {
+      (void)hipFree(a);
+      (void)hipFree(b);
+    }
+  } fr{d, e};
+  MFE_CHECK(ensure(&e, p->N));
+  mfe_equil_params trial = *prm;
+  trial.steps = trial_steps;
+  const int32_t keep_batch = p->tune_batch, keep_sr = p->tune_split[0], keep_sc = p->tune_split[1];
+  double best = 0.0;
+  int best_i = -1;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    p->tune_batch = cands[i].nb;
+    p->tune_split[0] = cands[i].sr;
+    p->tune_split[1] = cands[i].sc;
+    double t = 0.0;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code objects
+      const int rc = plan_run(p, &trial, alpha_b, beta_b, 0, d, e, nullptr, nullptr);
+      if (rc != MFE_OK) {
+        p->tune_batch = keep_batch;
+        p->tune_split[0] = keep_sr;
+        p->tune_split[1] = keep_sc;
+        return rc;
+      }
+      t = p->last_step_ms;
+    }
+    if (best_i < 0 || t < best) {
+      best = t;
+      best_i = (int)i;
+    }
+  }
+  p->tune_batch = cands[best_i].nb;
+  p->tune_split[0] = cands[best_i].sr;
+  p->tune_split[1] = cands[best_i].sc;
+  if (chosen) {
+    chosen[0] = p->tune_batch;
+    chosen[1] = p->tune_split[0];
+    chosen[2] = p->tune_split[1];
+  }
+  if (best_step_ms) *best_step_ms = best;
+  if (n_candidates) *n_candidates = (int32_t)cands.size();
   return MFE_OK;
 }
 

@@ -105,6 +105,12 @@ def test_plan_rejects_bad_probe_counts(lib):
     assert lib.mfe_plan_create(C.byref(s), 0, 4, None, C.byref(h)) == -1
 
 
+def test_autotune_argument_checks(lib):
+    p = _params()
+    assert lib.mfe_plan_autotune(None, C.byref(p), None, None, 10, None, None, None) == -1
+    assert lib.mfe_plan_autotune(C.c_void_p(16), None, None, None, 10, None, None, None) == -1
+
+
 def test_version(lib):
     assert "gfx950" in lib.mfe_version().decode()
 
