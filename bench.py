@@ -36,6 +36,10 @@ BF16_PEAK_TFLOPS = 2500.0
 M_ROWS, N_COLS, NNZ_ROW, SIGMA = 1_000_000, 500_000, 10, 2.0
 T_STEPS, K_PROBES, GAMMA, BOX_M = 2000, 16, 0.1, 10.0
 GEN_SEED, PROBE_SEED = 1001, 2001
+# HBM-side bytes per step of k_phase<16, true, 8> on the headline workload, from rocprofv3
+# FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) per launch, calibrated against a plain
+# 512 MiB copy (profiles/k_phase_csr_1e6x5e5_k16.md).  Set to None when the kernel changes.
+TRAFFIC_BYTES_PER_STEP = (174.9 + 666.2 + 27.0 + 12.0) * 1e6
 
 
 def sparse_algorithmic_bytes(m, n, nnz, k):
@@ -275,7 +279,7 @@ def bench_lsqr(mfe, plan, csr, out):
 
 
 def profile_run():
-    """Counter run: autotuning, then 20 steps of the headline workload (per-launch counters are what is
+    """Counter run: 20 steps of the headline workload (per-launch counters are what is
     read), then a plain device copy of 512 MiB whose FETCH_SIZE / WRITE_SIZE calibrate
     the counters (the source is flushed from the caches by a 2 GiB fill first)."""
     import torch
@@ -288,8 +292,6 @@ def profile_run():
     A = mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")
     al, be = mfe.default_alpha_beta(csr.m, csr.n)
     plan = mfe.Plan([A], max_probes=K_PROBES)
-    plan.autotune(al, be, GAMMA, BOX_M, K_PROBES, PROBE_SEED, trial_steps=20)
-    # the measured run: the last 20 steps of each launch in the trace
     plan.equilibrate(al, be, GAMMA, BOX_M, 20, K_PROBES, PROBE_SEED, use_graph=False)
     torch.cuda.synchronize()
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
@@ -344,9 +346,6 @@ def main():
     plan = mfe.Plan([A], max_probes=K_PROBES)
     torch.cuda.synchronize()
     prep_ms = (time.time() - t0) * 1e3
-    t0 = time.time()
-    tune = plan.autotune(al, be, GAMMA, BOX_M, K_PROBES, PROBE_SEED, trial_steps=20)
-    tune_s = time.time() - t0
     run = dict(alpha=al, beta=be, gamma=GAMMA, M=BOX_M, steps=T_STEPS, probes=K_PROBES, seed=PROBE_SEED,
                use_graph=not args.no_graph)
     out = None
@@ -366,7 +365,7 @@ def main():
     bytes_launch = sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, K_PROBES)
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
 
-    extra = {"prep_ms": prep_ms, "gen_s": gen_s, "autotune": tune, "autotune_s": tune_s,
+    extra = {"prep_ms": prep_ms, "gen_s": gen_s,
              "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
     for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3), ("c4", bench_c4)):
         if name in work:
@@ -407,8 +406,8 @@ def main():
                    "m": csr.m, "n": csr.n, "nnz": csr.nnz, "probes": K_PROBES, "sgd_steps": T_STEPS,
                    "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_phase<16,true> (row launch + column launch of one step)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES_PER_STEP,
+                     "kernel": "k_phase<16,true,8> (row launch + column launch of one step)",
                      "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch},
         "cpu_baseline": cpu,
         "extra": extra,
