@@ -7,6 +7,10 @@
 // e^x of every index is kept in FP64 (ping-pong by step parity); probe signs come from
 // the same Philox stream contract as the sparse engine.
 //
+// Small dense matrices (config-0 scale) run all T steps in one persistent workgroup
+// instead: one launch for the whole run, LDS barriers between steps, so the run is not
+// bounded by per-step launch latency.
+//
 // Operator: per step the library forms the probe blocks E S (n x k) and D W (m x k) in
 // FP64, calls apply() for A (E S) and A' (D W), and runs the square/step/project update
 // in its own kernels (the unfused path).
@@ -121,6 +125,292 @@ __global__ void k_block_update(int64_t cnt, int k, const double* __restrict__ Y,
   scale_out[i] = exp(xi);
 }
 
+// ---- persistent single-workgroup paths for small matrices
+//
+// The whole run (or a chunk of up to kPersistChunk steps) is one launch of one
+// workgroup; steps are separated by LDS barriers.  The probe sign words of the chunk
+// are drawn beforehand by a parallel launch (k_sign_chunk) and staged into LDS one step
+// ahead, so the Philox rounds stay off the step's critical path.
+constexpr int kPersistThreads = 1024;
+constexpr int kPersistWaves = kPersistThreads / 64;
+constexpr int64_t kPersistMaxDim = 1792;               // m + n (LDS: 32 (m + n) bytes of state)
+constexpr int64_t kPersistMaxWork = (int64_t)1 << 20;  // m n k multiply-adds per direction
+constexpr int kPersistChunk = 4096;                    // steps per launch
+constexpr int kPersistMaxWords = 1024;                 // sign words per step (one per thread)
+// Register-resident variant (k = 1): 8 wavefronts; thread (w, l) keeps
+// A[w + 8 r][l + 64 c] for r < kTinyRM, c < kTinyCM in registers for the whole run
+// (2 wavefronts per SIMD leave each lane 256 registers).
+constexpr int kTinyThreads = 512, kTinyWaves = kTinyThreads / 64;
+constexpr int kTinyRM = 25, kTinyCM = 2;
+
+struct PersistArgs {
+  const double* A;   // m x n, row stride ld
+  const double* AT;  // n x m, row stride m (transposed copy; LDS-state variant only)
+  int64_t m, n, ld;
+  double *u, *ub, *v, *vb;  // iterates and averages: values in, values out
+  int k, nsteps;            // steps t_begin .. t_begin + nsteps - 1
+  double t_begin, t0, gamma, M, tgt_row, tgt_col;
+  const uint64_t* sw;       // sign words of the chunk, step-major
+  int32_t nb0, wps;         // Philox blocks of side 0 (columns); sign words per step
+  int* flag;
+};
+
+// Sign words of steps t_begin .. t_begin + nsteps - 1, step-major (wps words per step):
+// side 0 (columns) at 0, side 1 (rows) at 4 nb0 + 4; Philox block c of a side at counter
+// (c + 1, 0, 0, 0), the same stream as every other path.
+__global__ void k_sign_chunk(uint64_t* __restrict__ sw, int64_t t_begin, int nsteps, int nb0, int nb1, int wps,
+                             uint64_t seed, uint64_t batch) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = nb0 + nb1;
+  if (g >= (int64_t)nsteps * per) return;
+  const int64_t st = g / per;
+  const int c = (int)(g % per);
+  const bool rows = c >= nb0;
+  const int cb = rows ? c - nb0 : c;
+  const U64x4 r = philox4x64_10((uint64_t)cb + 1, 0, 0, 0, seed,
+                                stream_ctrl(batch, (uint64_t)(t_begin + st), rows ? 1 : 0));
+  uint64_t* o = sw + st * wps + (rows ? 4 * (int64_t)nb0 + 4 : 0) + 4 * (int64_t)cb;
+  o[0] = r.x[0];
+  o[1] = r.x[1];
+  o[2] = r.x[2];
+  o[3] = r.x[3];
+}
+
+__device__ __forceinline__ StepScalars persist_scalars(const PersistArgs& a, int s) {
+  StepScalars sc;
+  sc.tau = a.t_begin + (double)s + a.t0;
+  sc.eta = 2.0 / (a.gamma * (sc.tau + 1.0));
+  sc.gamma = a.gamma;
+  sc.M = a.M;
+  return sc;
+}
+
+// Outputs per wavefront iteration: several rows (columns) at once keep their loads in
+// flight together; fewer when the k accumulators are wide.
+template <int KP>
+struct PersistUnroll {
+  static constexpr int U = KP <= 4 ? 4 : (KP <= 8 ? 2 : 1);
+};
+
+// One direction of one step of the LDS-state variant: wavefront w handles outputs
+// w, w + 16, ...; lanes stride the inner dimension of the row-major operand B (rows of A,
+// or rows of A'), the k sums are reduced across the wavefront, and lane r updates the
+// r-th output of the group.  Iterates, averages and scales live in LDS.
+template <int KP>
+__device__ __forceinline__ void persist_side(const double* __restrict__ B, int64_t nout, int64_t ninner, int64_t ldb,
+                                             const double* __restrict__ scale_in, const uint64_t* __restrict__ sw,
+                                             double* __restrict__ scale_out, double* __restrict__ x,
+                                             double* __restrict__ xbar, double target, int k, const StepScalars& sc,
+                                             int* flag) {
+  constexpr int U = PersistUnroll<KP>::U;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int W = kPersistWaves;
+  for (int64_t i0 = wave; i0 < nout; i0 += (int64_t)W * U) {
+    double acc[U][KP];
+#pragma unroll
+    for (int r = 0; r < U; ++r)
+#pragma unroll
+      for (int p = 0; p < KP; ++p) acc[r][p] = 0.0;
+    for (int64_t j = lane; j < ninner; j += 64) {
+      const double s = scale_in[j];
+      const uint64_t bits = extract_bits(sw, j * k, k);
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const int64_t i = i0 + (int64_t)r * W;
+        if (i < nout) accumulate_signed<KP>(acc[r], B[i * ldb + j] * s, bits);
+      }
+    }
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      double sr = 0.0;
+#pragma unroll
+      for (int p = 0; p < KP; ++p) {
+        double a = acc[r][p];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (p < k) sr += a * a;
+      }
+      if (lane == r) ss = sr;
+    }
+    const int64_t i = i0 + (int64_t)lane * W;
+    if (lane < U && i < nout) {
+      double xi = x[i], xb = xbar[i];
+      if (!sgd_update(ss, k, target, sc, xi, xb)) atomicOr(flag, 1);
+      x[i] = xi;
+      xbar[i] = xb;
+      scale_out[i] = exp(xi);
+    }
+  }
+}
+
+template <int KP>
+__global__ __launch_bounds__(kPersistThreads) void k_dense_persistent(PersistArgs a) {
+  extern __shared__ double lds[];
+  // scales by step parity: buffer (s & 1) receives step s, the other holds step s - 1
+  double* sr[2] = {lds, lds + a.m};
+  double* scl[2] = {lds + 2 * a.m, lds + 2 * a.m + a.n};
+  double* xu = lds + 2 * (a.m + a.n);
+  double* xub = xu + a.m;
+  double* xv = xub + a.m;
+  double* xvb = xv + a.n;
+  uint64_t* words = reinterpret_cast<uint64_t*>(xvb + a.n);  // [2][wps], by step parity
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < a.m; i += kPersistThreads) {
+    xu[i] = a.u[i];
+    xub[i] = a.ub[i];
+    sr[1][i] = exp(xu[i]);
+  }
+  for (int64_t j = tid; j < a.n; j += kPersistThreads) {
+    xv[j] = a.v[j];
+    xvb[j] = a.vb[j];
+    scl[1][j] = exp(xv[j]);
+  }
+  if (tid < a.wps) words[tid] = a.sw[tid];
+  __syncthreads();
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int cur = s & 1, prev = cur ^ 1;
+    uint64_t next = 0;
+    if (tid < a.wps && s + 1 < a.nsteps) next = a.sw[(int64_t)(s + 1) * a.wps + tid];
+    const uint64_t* w0 = words + (int64_t)cur * a.wps;
+    const uint64_t* w1 = w0 + 4 * (int64_t)a.nb0 + 4;
+    const StepScalars sc = persist_scalars(a, s);
+    // Jacobi order: both directions read the scales of step s - 1 and write those of step s
+    persist_side<KP>(a.A, a.m, a.n, a.ld, scl[prev], w0, sr[cur], xu, xub, a.tgt_row, a.k, sc, a.flag);
+    persist_side<KP>(a.AT, a.n, a.m, a.m, sr[prev], w1, scl[cur], xv, xvb, a.tgt_col, a.k, sc, a.flag);
+    if (tid < a.wps && s + 1 < a.nsteps) words[(int64_t)prev * a.wps + tid] = next;
+    __syncthreads();
+  }
+  for (int64_t i = tid; i < a.m; i += kPersistThreads) {
+    a.u[i] = xu[i];
+    a.ub[i] = xub[i];
+  }
+  for (int64_t j = tid; j < a.n; j += kPersistThreads) {
+    a.v[j] = xv[j];
+    a.vb[j] = xvb[j];
+  }
+}
+
+// Register-resident variant, k = 1, m <= 8 kTinyRM, n <= 64 kTinyCM.  Row sums: each
+// lane sums its kTinyCM entries of a row, the wavefront reduces.  Column sums: each
+// wavefront sums its kTinyRM rows per column into LDS, then one thread per column adds
+// the 8 wavefront partials.
+__global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
+  constexpr int NR = kTinyWaves * kTinyRM, NC = 64 * kTinyCM;
+  __shared__ double sr[2][NR], scl[2][NC], xu[NR], xub[NR], xv[NC], xvb[NC];
+  __shared__ double gsr[NR];  // (-1)^w_i e^(u_i) of the previous step, with this step's sign
+  __shared__ double part[kTinyWaves][NC];
+  __shared__ uint64_t words[2][kPersistMaxWords];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int m = (int)a.m, n = (int)a.n;
+  double Ar[kTinyRM][kTinyCM];
+#pragma unroll
+  for (int r = 0; r < kTinyRM; ++r)
+#pragma unroll
+    for (int c = 0; c < kTinyCM; ++c) {
+      const int i = w + kTinyWaves * r, j = l + 64 * c;
+      Ar[r][c] = (i < m && j < n) ? a.A[(int64_t)i * a.ld + j] : 0.0;
+    }
+  for (int i = tid; i < m; i += kTinyThreads) {
+    xu[i] = a.u[i];
+    xub[i] = a.ub[i];
+    sr[1][i] = exp(xu[i]);
+  }
+  for (int j = tid; j < n; j += kTinyThreads) {
+    xv[j] = a.v[j];
+    xvb[j] = a.vb[j];
+    scl[1][j] = exp(xv[j]);
+  }
+  if (tid < a.wps) words[0][tid] = a.sw[tid];
+  __syncthreads();
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int cur = s & 1, prev = cur ^ 1;
+    uint64_t next = 0;
+    if (tid < a.wps && s + 1 < a.nsteps) next = a.sw[(int64_t)(s + 1) * a.wps + tid];
+    const uint64_t* w0 = words[cur];
+    const uint64_t* w1 = w0 + 4 * a.nb0 + 4;
+    const StepScalars sc = persist_scalars(a, s);
+    // signed row scales of this step (one thread per row), then one pass over the register
+    // tile: each row's partial over this lane's columns (reduced across the wavefront) and
+    // each column's partial over this wavefront's rows.  Multiplying by a signed scale
+    // gives the same product as negating the unsigned one.
+    for (int i = tid; i < m; i += kTinyThreads) gsr[i] = extract_bits(w1, i, 1) ? -sr[prev][i] : sr[prev][i];
+    double gsj[kTinyCM], cacc[kTinyCM];
+#pragma unroll
+    for (int c = 0; c < kTinyCM; ++c) {
+      const int j = l + 64 * c;
+      gsj[c] = j < n ? (extract_bits(w0, j, 1) ? -scl[prev][j] : scl[prev][j]) : 0.0;
+      cacc[c] = 0.0;
+    }
+    __syncthreads();
+    double ss = 0.0;
+#pragma unroll
+    for (int r0 = 0; r0 < kTinyRM; r0 += 4) {
+      double racc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        racc[q] = 0.0;
+        const int r = r0 + q, i = w + kTinyWaves * r;
+        if (r < kTinyRM && i < m) {
+          const double gi = gsr[i];
+#pragma unroll
+          for (int c = 0; c < kTinyCM; ++c) {
+            racc[q] += Ar[r][c] * gsj[c];
+            cacc[c] += Ar[r][c] * gi;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (r0 + q < kTinyRM) {
+          double v = racc[q];
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+          if (l == r0 + q) ss = v * v;
+        }
+      }
+    }
+    {
+      const int i = w + kTinyWaves * l;
+      if (l < kTinyRM && i < m) {
+        double xi = xu[i], xb = xub[i];
+        if (!sgd_update(ss, 1, a.tgt_row, sc, xi, xb)) atomicOr(a.flag, 1);
+        xu[i] = xi;
+        xub[i] = xb;
+        sr[cur][i] = exp(xi);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kTinyCM; ++c) part[w][l + 64 * c] = cacc[c];
+    if (tid < a.wps && s + 1 < a.nsteps) words[prev][tid] = next;
+    __syncthreads();
+    for (int j = tid; j < n; j += kTinyThreads) {
+      double y = 0.0;
+#pragma unroll
+      for (int q = 0; q < kTinyWaves; ++q) y += part[q][j];
+      double xj = xv[j], xb = xvb[j];
+      if (!sgd_update(y * y, 1, a.tgt_col, sc, xj, xb)) atomicOr(a.flag, 1);
+      xv[j] = xj;
+      xvb[j] = xb;
+      scl[cur][j] = exp(xj);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < m; i += kTinyThreads) {
+    a.u[i] = xu[i];
+    a.ub[i] = xub[i];
+  }
+  for (int j = tid; j < n; j += kTinyThreads) {
+    a.v[j] = xv[j];
+    a.vb[j] = xvb[j];
+  }
+}
+
+__global__ void k_transpose(const double* __restrict__ A, int64_t m, int64_t n, int64_t ld, double* __restrict__ AT) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  AT[j * m + i] = A[i * ld + j];
+}
+
 struct Bufs {
   std::vector<void*> p;
   ~Bufs() {
@@ -229,6 +519,59 @@ int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double
   k_dense_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, su[0], flag);
   k_dense_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv[0], flag);
   const double* Ad = (const double*)A->data;
+  const int32_t nb0 = (int32_t)ceil_div(n * k, 256), nb1 = (int32_t)ceil_div(m * k, 256);
+  const int32_t wps = 4 * (nb0 + nb1) + 8;
+  const bool tiny = k == 1 && m <= kTinyWaves * kTinyRM && n <= 64 * kTinyCM && wps <= kTinyThreads;
+  const size_t lds = sizeof(double) * (size_t)(4 * (m + n)) + sizeof(uint64_t) * (size_t)(2 * wps);
+  const bool persistent =
+      tiny || (k <= 16 && m + n <= kPersistMaxDim && m * n * k <= kPersistMaxWork && lds <= 65536 &&
+               wps <= kPersistMaxWords);
+  if (persistent && p->steps > 0) {
+    double* AT = nullptr;
+    if (!tiny) {
+      MFE_CHECK(B.alloc(&AT, m * n));
+      k_transpose<<<dim3((unsigned)ceil_div(m * n, 256)), dim3(256), 0, st>>>(Ad, m, n, A->ld, AT);
+    }
+    const int chunk = std::min(p->steps, kPersistChunk);
+    uint64_t* sw;
+    MFE_CHECK(B.alloc(&sw, (int64_t)chunk * wps));
+    MFE_HIP(hipMemsetAsync(sw, 0, sizeof(uint64_t) * (size_t)chunk * wps, st));
+    PersistArgs pa;
+    pa.A = Ad;
+    pa.AT = AT;
+    pa.m = m;
+    pa.n = n;
+    pa.ld = A->ld;
+    pa.u = u;
+    pa.ub = ub;
+    pa.v = v;
+    pa.vb = vb;
+    pa.k = k;
+    pa.t0 = (double)p->t0;
+    pa.gamma = p->gamma;
+    pa.M = p->box_M;
+    pa.tgt_row = p->alpha * p->alpha;
+    pa.tgt_col = p->beta * p->beta;
+    pa.sw = sw;
+    pa.nb0 = nb0;
+    pa.wps = wps;
+    pa.flag = flag;
+    for (int t1 = 1; t1 <= p->steps; t1 += chunk) {
+      const int ns = std::min(chunk, p->steps - t1 + 1);
+      k_sign_chunk<<<dim3((unsigned)ceil_div((int64_t)ns * (nb0 + nb1), 256)), dim3(256), 0, st>>>(
+          sw, t1, ns, nb0, nb1, wps, p->seed, p->batch);
+      pa.t_begin = (double)t1;
+      pa.nsteps = ns;
+      const dim3 g(1), b(kPersistThreads);
+      if (tiny) k_dense_tiny<<<g, dim3(kTinyThreads), 0, st>>>(pa);
+      else if (k <= 1) k_dense_persistent<1><<<g, b, lds, st>>>(pa);
+      else if (k <= 2) k_dense_persistent<2><<<g, b, lds, st>>>(pa);
+      else if (k <= 4) k_dense_persistent<4><<<g, b, lds, st>>>(pa);
+      else if (k <= 8) k_dense_persistent<8><<<g, b, lds, st>>>(pa);
+      else k_dense_persistent<16><<<g, b, lds, st>>>(pa);
+      MFE_HIP(hipGetLastError());
+    }
+  } else {
   for (int t = 1; t <= p->steps; ++t) {
     MFE_CHECK(S.draw(p->seed, (uint64_t)t, st));
     const int cur = t & 1, prev = cur ^ 1;
@@ -242,6 +585,7 @@ int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double
     else if (k <= 16) launch_dense_step<16>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
     else if (k <= 32) launch_dense_step<32>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
     else launch_dense_step<64>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+  }
   }
   MFE_HIP(hipGetLastError());
   k_dense_output<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, ub, d, u_bar);

@@ -98,6 +98,47 @@ def test_dense_whole_run_elementwise(config0, k):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("m,n,k", [(1700, 38, 16), (1500, 170, 4), (3500, 18, 16), (3000, 700, 4)])
+def test_dense_one_step_maps_persistent_limit_and_multi_launch(m, n, k):
+    """Small dense matrices run all steps in one persistent workgroup: (1700, 38, k = 16)
+    sits near its LDS limit, (1500, 170, k = 4) near its work limit; (3500, 18) and
+    (3000, 700) exceed them and run one launch per direction and step.  One step from random in-box states
+    (t0 as in a warm start) against one oracle step.  Whole runs on tall matrices are not
+    comparable elementwise: with beta^2 = sqrt(m/n) large, |1 - eta (2 z + gamma)| > 1 for
+    ~100 steps and the oracle's own u_bar moves by 0.1-0.5 under 1e-16 perturbations."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(m, n, 1.0, m + n)
+    al, be = A1.default_alpha_beta(m, n)
+    rng = np.random.default_rng(m)
+    worst = 0.0
+    for t0 in (0, 5, 50):
+        u = np.clip(rng.normal(0, 1.0, m), -10, 10)
+        v = np.clip(rng.normal(0, 1.0, n), -10, 10)
+        g = equilibrate(_dense(A), al, be, 0.1, 10.0, 1, k, 19, t0=t0, u0=torch.tensor(u, device="cuda"),
+                        v0=torch.tensor(v, device="cuda"))
+        o = A1.equilibrate(A, al, be, 0.1, 10.0, 1, k=k, seed=19, t0=t0, u0=u, v0=v)
+        for key in ("u_bar", "v_bar"):
+            d = np.abs(g[key].cpu().numpy() - o[key]) / np.maximum(1.0, np.abs(o[key]))
+            worst = max(worst, d.max())
+    _say("dense one-step", m, n, k, worst)
+    assert worst <= 1e-11
+
+
+def test_dense_multi_launch_whole_run():
+    """3000 x 700, k = 16, T = 100 (one launch per direction and step), elementwise; the
+    oracle's own spread here is 1.5e-8."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(3000, 700, 1.0, 3700)
+    al, be = A1.default_alpha_beta(3000, 700)
+    g = equilibrate(_dense(A), al, be, 0.1, 10.0, 100, 16, 17)
+    o = A1.equilibrate(A, al, be, 0.1, 10.0, 100, k=16, seed=17)
+    err = max(np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max(), np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max())
+    _say("dense multi-launch err", err)
+    assert err <= TOL
+
+
 def test_dense_ragged_shape_and_padded_ld():
     """Shapes that are not multiples of the wavefront, and a padded leading dimension."""
     from paper_1602_06621_amd import Dense, equilibrate
