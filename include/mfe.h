@@ -228,6 +228,16 @@ int mfe_mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, co
                   int64_t count, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,
                   void* stream);
 
+/* The whole warm start in one stream-ordered call: sketch features of every row and
+ * column of the plan (as mfe_plan_sketch_features), the network's corrections (when
+ * learned != 0; params device FP32 [n_params], else the sketch initialisation alone), and
+ * u0 / v0 = clip(sketch + correction, -M, M), device FP64 [sum m] / [sum n], ready for
+ * mfe_plan_equilibrate with t0 > 0.  Scratch is kept in the plan between calls.
+ * EINVAL: plan or an output NULL, probes not in {4, 8, 16}, learned with params NULL. */
+int mfe_plan_warmstart(mfe_plan* plan, const float* params, uint64_t seed, int32_t probes, const double* alpha_b,
+                       const double* beta_b, double gamma, double box_M, int32_t learned, double* u0, double* v0,
+                       void* stream);
+
 /* out[i] = clip(sketch[i] + delta[i], -M, M) (delta FP32, nullable = 0); device arrays. */
 int mfe_warmstart_apply(int64_t n, const double* sketch, const float* delta, double box_M, double* out,
                         void* stream);

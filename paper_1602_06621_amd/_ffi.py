@@ -80,6 +80,7 @@ def _lib():
         "mfe_draw_signs": [u64, i32, i64, i32, i64, vp, vp],
         "mfe_plan_equilibrate_trace": [vp, C.POINTER(_Params), i32, C.POINTER(dbl), vp, vp, vp, vp],
         "mfe_plan_autotune": [vp, C.POINTER(_Params), vp, vp, i32, vp, C.POINTER(dbl), C.POINTER(i32)],
+        "mfe_plan_warmstart": [vp, vp, u64, i32, vp, vp, dbl, dbl, i32, vp, vp, vp],
         "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
         "mfe_mlp_sizes": [C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "mfe_mlp_forward": [vp, vp, i64, vp, vp],
@@ -384,6 +385,19 @@ class Plan:
                                                float(gamma), float(M), _ptr(fr), _ptr(fc), _ptr(us), _ptr(vs),
                                                _stream(stream)))
         return dict(feat_rows=fr, feat_cols=fc, u_sketch=us, v_sketch=vs)
+
+    def warm_start(self, params, seed, probes=4, gamma=0.1, M=10.0, learned=True, alpha=None, beta=None,
+                   stream=None, device="cuda"):
+        """(u0, v0) for every matrix of the plan in one call: sketch, network, clip (see mfe.h)."""
+        ah = bh = None
+        if alpha is not None:
+            ah, bh, _, _ = self._targets(alpha, beta)
+        u0 = torch.empty(self.M, dtype=torch.float64, device=device)
+        v0 = torch.empty(self.N, dtype=torch.float64, device=device)
+        _check(_lib().mfe_plan_warmstart(self._h, _ptr(params, torch.float32, "params") if learned else None,
+                                         int(seed) & ((1 << 64) - 1), int(probes), ah, bh, float(gamma), float(M),
+                                         int(bool(learned)), _ptr(u0), _ptr(v0), _stream(stream)))
+        return u0, v0
 
     def lsqr(self, b, d=None, e=None, tol=1e-6, max_iter=1000, check_every=10, stream=None, device="cuda"):
         x = torch.empty(self.N, dtype=torch.float64, device=device)

@@ -247,6 +247,17 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
   return plan_equilibrate_trace(plan, p, trace_every, rms_trace, d, e, u_bar, v_bar);
 }
 
+int mfe_plan_warmstart(mfe_plan* plan, const float* params, uint64_t seed, int32_t probes, const double* alpha_b,
+                       const double* beta_b, double gamma, double box_M, int32_t learned, double* u0, double* v0,
+                       void* stream) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  if (!u0 || !v0) return set_error(MFE_EINVAL, "NULL output");
+  if (!(gamma > 0) || !(box_M > 0)) return set_error(MFE_EINVAL, "gamma and M must be positive");
+  return plan_warmstart(plan, params, seed, probes, alpha_b, beta_b, gamma, box_M, learned, u0, v0,
+                        (hipStream_t)stream);
+}
+
 int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
                       int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates) {
   clear_error();

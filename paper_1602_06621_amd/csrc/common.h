@@ -137,6 +137,31 @@ __device__ __forceinline__ bool sgd_update(double ss, int k, double target, cons
   return ok;
 }
 
+// Sum of a double over the 64 lanes of a wavefront, returned to every lane.  Data
+// parallel primitives (DPP) add within quads, half rows and rows of 16 lanes on the
+// vector ALU; the four row sums are then read as wavefront-uniform values.  Must be
+// called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]: pairs
+  v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]: quads
+  v += dpp_mov<0x141>(v);  // row_half_mirror: groups of 8
+  v += dpp_mov<0x140>(v);  // row_mirror: rows of 16
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Gathered per-index record of the sparse path: the scale e^x of the index (FP64) and
 // the sign bits of its probes for the step that consumes it.
 struct __align__(16) Desc {

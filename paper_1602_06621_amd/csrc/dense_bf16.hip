@@ -13,8 +13,12 @@
 // kernel.  Probe blocks use the matching operand layout (per k chunk, lane l holds probe
 // 32 nb + l%32 at the same 8 k values).  Both are padded with zeros to whole tiles.
 //
-// Work split: one workgroup of 4 wavefronts per 32-row block; the wavefronts split the
-// k chunks round-robin and their 32 x 64 FP32 accumulators are summed in LDS.
+// Work split: one workgroup of 4 wavefronts per (32-row block, k range); the k chunks
+// of a block are split into `splits` ranges so that a pass launches ~1024 workgroups
+// (enough bytes in flight per CU to stream A at HBM rate).  The wavefronts of a
+// workgroup take the chunks of its range round-robin; their 32 x 64 FP32 accumulators
+// are summed in LDS (in FP64) and stored as one FP32 partial per range.  A second
+// launch adds the ranges in FP64 and runs the square / step / project / average update.
 #include <cmath>
 #include <vector>
 
@@ -118,6 +122,8 @@ struct Bf16Side {
   const u32x4* tiles;   // [RB][KC][64]
   const u32x4* probes;  // [KC][NB][64]
   int64_t R, RB, KC;
+  int splits;           // k ranges per row block
+  float* part;          // [splits][RB * 32][32 NB] partial products
   double* x;
   double* xbar;
   double* scale_out;
@@ -130,12 +136,15 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) {
   return r;
 }
 
-// One 32-row block per workgroup: Y (32 x 32 NB) = tiles . probes, then the SGD epilogue.
+// One (32-row block, k range) per workgroup: partial Y (32 x 32 NB) = tiles . probes.
 template <int NB>
-__global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S, int k, StepScalars sc, int* flag) {
+__global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S) {
   __shared__ float red[kWaves][kRows][32 * NB];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t rb = blockIdx.x;
+  const int split = blockIdx.y;
+  const int64_t per = (S.KC + S.splits - 1) / S.splits;
+  const int64_t kbeg = (int64_t)split * per, kend = kbeg + per < S.KC ? kbeg + per : S.KC;
   f32x16 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -143,9 +152,9 @@ __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S, int k, StepScalar
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
   const u32x4* __restrict__ at = S.tiles + rb * S.KC * 64 + lane;
   const u32x4* __restrict__ pt = S.probes + lane;
-  int64_t kc = wave;
+  int64_t kc = kbeg + wave;
   // four chunks in flight per wavefront
-  for (; kc + 3 * kWaves < S.KC; kc += 4 * kWaves) {
+  for (; kc + 3 * kWaves < kend; kc += 4 * kWaves) {
     u32x4 a[4], p[4][NB];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S, int k, StepScalar
       for (int b = 0; b < NB; ++b)
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u]), as_bf16x8(p[u][b]), acc[b], 0, 0, 0);
   }
-  for (; kc < S.KC; kc += kWaves) {
+  for (; kc < kend; kc += kWaves) {
     const u32x4 a = __builtin_nontemporal_load(at + kc * 64);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -172,17 +181,33 @@ __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S, int k, StepScalar
 #pragma unroll
     for (int v = 0; v < 16; ++v) red[wave][(v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)][b * 32 + (lane & 31)] = acc[b][v];
   __syncthreads();
-  // 8 threads per row: sum the four wavefronts, square, add over probes
-  const int row = threadIdx.x >> 3, part = threadIdx.x & 7;
+  // the four wavefronts' sums of this range, one FP32 partial per (row, probe)
+  float* __restrict__ out = S.part + ((int64_t)split * S.RB + rb) * kRows * 32 * NB;
+  for (int e = threadIdx.x; e < kRows * 32 * NB; e += 256) {
+    const int row = e / (32 * NB), p = e % (32 * NB);
+    out[e] = (float)((double)red[0][row][p] + (double)red[1][row][p] + (double)red[2][row][p] + (double)red[3][row][p]);
+  }
+}
+
+// Update of every index from the FP32 partials of its row block: 8 threads per row add
+// the ranges in FP64, square, and sum over the probes.
+template <int NB>
+__global__ __launch_bounds__(256) void k_bf16_update(Bf16Side S, int k, StepScalars sc, int* flag) {
+  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+  const int part = threadIdx.x & 7;
   double ss = 0.0;
-  for (int p = part; p < 32 * NB; p += 8) {
-    if (p < k) {
-      const double y = (double)red[0][row][p] + (double)red[1][row][p] + (double)red[2][row][p] + (double)red[3][row][p];
-      ss += y * y;
+  if (r < S.RB * kRows) {
+    const int64_t stride = S.RB * kRows * 32 * NB;
+    const float* __restrict__ base = S.part + r * 32 * NB;
+    for (int p = part; p < 32 * NB; p += 8) {
+      if (p < k) {
+        double y = 0.0;
+        for (int sp = 0; sp < S.splits; ++sp) y += (double)base[sp * stride + p];
+        ss += y * y;
+      }
     }
   }
   for (int off = 4; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 8);
-  const int64_t r = rb * kRows + row;
   if (part == 0 && r < S.R) {
     double x = S.x[r], xb = S.xbar[r];
     if (!sgd_update(ss, k, S.target, sc, x, xb)) atomicOr(flag, 1);
@@ -232,7 +257,15 @@ struct Bufs {
 
 template <int NB>
 void launch_pass(const Bf16Side& S, int k, const StepScalars& sc, int* flag, hipStream_t st) {
-  k_bf16_pass<NB><<<dim3((unsigned)S.RB), dim3(256), 0, st>>>(S, k, sc, flag);
+  k_bf16_pass<NB><<<dim3((unsigned)S.RB, (unsigned)S.splits), dim3(256), 0, st>>>(S);
+  k_bf16_update<NB><<<dim3((unsigned)ceil_div(S.RB * kRows * 8, 256)), dim3(256), 0, st>>>(S, k, sc, flag);
+}
+
+// k ranges per row block: about 1024 workgroups per pass, at least 16 chunks per range.
+int bf16_splits(int64_t RB, int64_t KC) {
+  int64_t s = 1;
+  while (RB * s < 1024 && KC / (2 * s) >= 16) s *= 2;
+  return (int)s;
 }
 
 }  // namespace
@@ -266,6 +299,10 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
     MFE_CHECK(B.alloc(&sv[i], n));
   }
   MFE_CHECK(B.alloc(&flag, 1));
+  const int Su = bf16_splits(RBu, KCu), Sv = bf16_splits(RBv, KCv);
+  float *partu, *partv;
+  MFE_CHECK(B.alloc(&partu, (int64_t)Su * RBu * kRows * 32 * NB));
+  MFE_CHECK(B.alloc(&partv, (int64_t)Sv * RBv * kRows * 32 * NB));
   // sign words: side 0 (n * k bits) then side 1 (m * k bits), one slot refilled per step
   SignSeg segs_h[2];
   segs_h[0].ctrl_lo = ((uint64_t)p->batch << 34) | 0ull;
@@ -318,8 +355,8 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
     sc.eta = 2.0 / (p->gamma * (sc.tau + 1.0));
     sc.gamma = p->gamma;
     sc.M = p->box_M;
-    Bf16Side R{tu, pu, m, RBu, KCu, u, ub, su[cur], p->alpha * p->alpha};
-    Bf16Side Cc{tv, pv, n, RBv, KCv, v, vb, sv[cur], p->beta * p->beta};
+    Bf16Side R{tu, pu, m, RBu, KCu, Su, partu, u, ub, su[cur], p->alpha * p->alpha};
+    Bf16Side Cc{tv, pv, n, RBv, KCv, Sv, partv, v, vb, sv[cur], p->beta * p->beta};
     if (NB == 1) {
       launch_pass<1>(R, k, sc, flag, st);
       launch_pass<1>(Cc, k, sc, flag, st);

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_dense_rows(const double* __restrict__ A
     accumulate_signed<KP>(acc, A[i * ld + j] * S.scale_in[j], extract_bits(S.sign_in, j * k, k));
 #pragma unroll
   for (int p = 0; p < KP; ++p)
-    for (int off = 32; off > 0; off >>= 1) acc[p] += __shfl_xor(acc[p], off);
+    acc[p] = wave_sum(acc[p]);
   if (lane != 0) return;
   double ss = 0.0;
 #pragma unroll
@@ -227,7 +227,7 @@ __device__ __forceinline__ void persist_side(const double* __restrict__ B, int64
 #pragma unroll
       for (int p = 0; p < KP; ++p) {
         double a = acc[r][p];
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        a = wave_sum(a);
         if (p < k) sr += a * a;
       }
       if (lane == r) ss = sr;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
       for (int q = 0; q < 4; ++q) {
         if (r0 + q < kTinyRM) {
           double v = racc[q];
-          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+          v = wave_sum(v);
           if (l == r0 + q) ss = v * v;
         }
       }

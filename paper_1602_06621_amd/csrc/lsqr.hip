@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kRed) void k_dense_fwd(const double* __restrict__ A
   if (i < m) {
     double acc = 0.0;
     for (int64_t j = lane; j < n; j += 64) acc += A[i * ld + j] * g[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    acc = wave_sum(acc);
     if (lane == 0) {
       const double so = sout ? sout[i] : 1.0;
       double v = so * (acc * (inv ? *inv : 1.0));

@@ -135,6 +135,9 @@ struct mfe_plan {
   // each direction (rows, columns) with a two-part layout runs as two launches.
   int32_t tune_batch = mfe::kBatch;
   int32_t tune_split[2] = {0, 0};
+  // scratch of the warm-start calls (sketch, features, network outputs)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
   int64_t sign_words = 0;           // words per slot
   int32_t sign_k = 0;               // k the sign layout was built for
   int64_t sign_batch_base = -1;     // batch index of matrix 0 in that layout
@@ -173,6 +176,9 @@ int plan_equilibrate_trace(mfe_plan* p, const mfe_equil_params* prm, int32_t tra
 int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
                          double gamma, double M, float* feat_rows, float* feat_cols, double* u_sketch,
                          double* v_sketch, hipStream_t st);
+int plan_warmstart(mfe_plan* p, const float* params, uint64_t seed, int32_t ks, const double* alpha_b,
+                   const double* beta_b, double gamma, double M, int learned, double* u0, double* v0,
+                   hipStream_t st);
 int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st);
 int mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
               int64_t total, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,

@@ -365,6 +365,7 @@ void plan_free(mfe_plan* p) {
     (void)hipFree(p->signs[i]);
     (void)hipFree(p->part[i]);
   }
+  (void)hipFree(p->ws);
   (void)hipFree(p->segs);
   (void)hipFree(p->seg_prefix);
   (void)hipFree(p->mats);

@@ -51,6 +51,20 @@ struct Work {
   }
 };
 
+// Bump allocation inside one device buffer (256-byte aligned pieces); a first pass with
+// base == nullptr only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* r = reinterpret_cast<T*>(base + off);
+    off += sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    return base ? r : nullptr;
+  }
+};
+
 // ---------------------------------------------------------------- sketch
 
 // Per index (internal order, one direction): y_p = sum_q a_q (-1)^bit(other index, p)
@@ -348,11 +362,13 @@ __global__ void k_apply_delta(int64_t n, const double* __restrict__ s, const flo
 
 // ---------------------------------------------------------------- drivers
 
-int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
-                         double gamma, double M, float* feat_rows, float* feat_cols, double* u_sketch,
-                         double* v_sketch, hipStream_t st) {
-  if (ks != 4 && ks != 8 && ks != 16) return set_error(MFE_EINVAL, "sketch probes must be 4, 8 or 16");
-  MFE_CHECK(ensure_mats(p, st));
+namespace {
+
+// Sketch features with all scratch carved from `ws` (base == nullptr: measure only;
+// the needed bytes are added to *bytes).
+int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b, double gamma,
+                double M, float* feat_rows, float* feat_cols, double* u_sketch, double* v_sketch, hipStream_t st,
+                char* ws, size_t* bytes) {
   const int count = p->count;
   // sketch sign words: side 2 (indexed by column) and side 3 (by row), step 0, batch b
   std::vector<SignSeg> segs;
@@ -371,27 +387,26 @@ int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* a
       prefix.push_back(blocks);
       segs.push_back(sg);
     }
-  Work W;
-  SignSeg* d_segs;
-  int64_t *d_prefix, *d_wb_col, *d_wb_row, *d_rbase, *d_cbase;
-  uint64_t* sw;
+  Carver cv{ws};
+  SignSeg* d_segs = cv.take<SignSeg>((int64_t)segs.size());
+  int64_t* d_prefix = cv.take<int64_t>((int64_t)prefix.size());
+  int64_t* d_wb_col = cv.take<int64_t>(count);
+  int64_t* d_wb_row = cv.take<int64_t>(count);
+  uint64_t* sw = cv.take<uint64_t>(words);
+  double* est_r = cv.take<double>(p->M);
+  double* est_c = cv.take<double>(p->N);
+  double* rat_r = cv.take<double>(p->M);
+  double* rat_c = cv.take<double>(p->N);
+  double* st_r = cv.take<double>(3 * count);
+  double* st_c = cv.take<double>(3 * count);
+  int64_t* d_rbase = cv.take<int64_t>(count + 1);
+  int64_t* d_cbase = cv.take<int64_t>(count + 1);
+  FeatMat* d_fm = cv.take<FeatMat>(count);
+  if (!ws) {
+    *bytes += cv.off + 256;
+    return MFE_OK;
+  }
   int32_t *mat_of_row_slice, *mat_of_col_slice;
-  double *est_r, *est_c, *rat_r, *rat_c, *st_r, *st_c;
-  FeatMat* d_fm;
-  MFE_CHECK(W.alloc(&d_segs, (int64_t)segs.size()));
-  MFE_CHECK(W.alloc(&d_prefix, (int64_t)prefix.size()));
-  MFE_CHECK(W.alloc(&d_wb_col, count));
-  MFE_CHECK(W.alloc(&d_wb_row, count));
-  MFE_CHECK(W.alloc(&sw, words));
-  MFE_CHECK(W.alloc(&est_r, p->M));
-  MFE_CHECK(W.alloc(&est_c, p->N));
-  MFE_CHECK(W.alloc(&rat_r, p->M));
-  MFE_CHECK(W.alloc(&rat_c, p->N));
-  MFE_CHECK(W.alloc(&st_r, 3 * count));
-  MFE_CHECK(W.alloc(&st_c, 3 * count));
-  MFE_CHECK(W.alloc(&d_rbase, count + 1));
-  MFE_CHECK(W.alloc(&d_cbase, count + 1));
-  MFE_CHECK(W.alloc(&d_fm, count));
   mat_of_row_slice = p->rows.slice_mat;
   mat_of_col_slice = p->cols.slice_mat;
   MFE_HIP(hipMemcpyAsync(d_segs, segs.data(), sizeof(SignSeg) * segs.size(), hipMemcpyHostToDevice, st));
@@ -470,9 +485,83 @@ int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* a
   k_features<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(est_c, rat_c, st_c, d_fm, count, 0, p->N, gamma, M, feat_cols,
                                                              v_sketch);
   MFE_HIP(hipGetLastError());
+  return MFE_OK;
+}
+
+}  // namespace
+
+// Plan-owned scratch of the warm-start calls, grown on demand.
+int plan_workspace(mfe_plan* p, size_t bytes, char** out) {
+  if (p->ws_bytes < bytes) {
+    (void)hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    hipError_t e = hipMalloc(&p->ws, bytes);
+    if (e != hipSuccess)
+      return set_error(e == hipErrorOutOfMemory ? MFE_ENOMEM : MFE_EDEVICE, "hipMalloc failed: %s",
+                       hipGetErrorString(e));
+    p->ws_bytes = bytes;
+  }
+  *out = (char*)p->ws;
+  return MFE_OK;
+}
+
+int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
+                         double gamma, double M, float* feat_rows, float* feat_cols, double* u_sketch,
+                         double* v_sketch, hipStream_t st) {
+  if (ks != 4 && ks != 8 && ks != 16) return set_error(MFE_EINVAL, "sketch probes must be 4, 8 or 16");
+  MFE_CHECK(ensure_mats(p, st));
+  size_t bytes = 0;
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, nullptr, nullptr, nullptr, nullptr, st, nullptr,
+                        &bytes));
+  char* ws;
+  MFE_CHECK(plan_workspace(p, bytes, &ws));
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, feat_rows, feat_cols, u_sketch, v_sketch, st, ws,
+                        &bytes));
   MFE_HIP(hipStreamSynchronize(st));
   return MFE_OK;
 }
+
+int plan_warmstart(mfe_plan* p, const float* params, uint64_t seed, int32_t ks, const double* alpha_b,
+                   const double* beta_b, double gamma, double M, int learned, double* u0, double* v0,
+                   hipStream_t st) {
+  if (ks != 4 && ks != 8 && ks != 16) return set_error(MFE_EINVAL, "sketch probes must be 4, 8 or 16");
+  if (learned && !params) return set_error(MFE_EINVAL, "learned warm start needs the network parameters");
+  MFE_CHECK(ensure_mats(p, st));
+  // layout: features and sketch initialisations of rows and columns, network outputs,
+  // then the sketch scratch
+  Carver head{nullptr};
+  head.take<float>(p->M * kF);
+  head.take<float>(p->N * kF);
+  head.take<double>(p->M);
+  head.take<double>(p->N);
+  head.take<float>(p->M);
+  head.take<float>(p->N);
+  const size_t head_bytes = (head.off + 255) & ~(size_t)255;
+  size_t bytes = head_bytes;
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, nullptr, nullptr, nullptr, nullptr, st, nullptr,
+                        &bytes));
+  char* ws;
+  MFE_CHECK(plan_workspace(p, bytes, &ws));
+  Carver cv{ws};
+  float* fr = cv.take<float>(p->M * kF);
+  float* fc = cv.take<float>(p->N * kF);
+  double* us = cv.take<double>(p->M);
+  double* vs = cv.take<double>(p->N);
+  float* du = cv.take<float>(p->M);
+  float* dv = cv.take<float>(p->N);
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, fr, fc, us, vs, st, ws + head_bytes, &bytes));
+  if (learned) {
+    k_mlp_fwd<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(params, fr, nullptr, p->M, du, nullptr, nullptr);
+    k_mlp_fwd<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(params, fc, nullptr, p->N, dv, nullptr, nullptr);
+  }
+  k_apply_delta<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(p->M, us, learned ? du : nullptr, M, u0);
+  k_apply_delta<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(p->N, vs, learned ? dv : nullptr, M, v0);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
+
 
 int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st) {
   if (count <= 0) return MFE_OK;

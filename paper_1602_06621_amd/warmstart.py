@@ -62,11 +62,8 @@ def train(X, t, iters=1500, batch=4096, lr=2e-3, seed=0, init_seed=1):
 
 def warm_start(plan, params, sketch_seed, probes=4, gamma=0.1, M=10.0, learned=True):
     """(u0, v0) for every matrix of the plan: the sketch initialisation, corrected by the
-    network when learned is True."""
-    f = plan.sketch_features(sketch_seed, probes, gamma, M)
-    du = F.mlp_forward(params, f["feat_rows"]) if learned else None
-    dv = F.mlp_forward(params, f["feat_cols"]) if learned else None
-    return F.warmstart_apply(f["u_sketch"], du, M), F.warmstart_apply(f["v_sketch"], dv, M)
+    network when learned is True (one library call, mfe_plan_warmstart)."""
+    return plan.warm_start(params, sketch_seed, probes, gamma, M, learned)
 
 
 def steps_to_residual(trace, target, every):

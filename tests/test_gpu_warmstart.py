@@ -121,3 +121,21 @@ def test_learned_warm_start_reaches_plain_residual_sooner():
         _say(f"sigma {sigma}: target {target:.4g}; (steps, start residual):", res)
         assert res["mlp"][0] is not None and res["mlp"][0] < res["plain"][0]
         assert res["mlp"][1] < res["sketch"][1]
+
+
+def test_one_call_warm_start_equals_composed_steps():
+    """mfe_plan_warmstart (sketch, network, clip in one call) gives the same (u0, v0) bit for
+    bit as the separate calls, learned and sketch-only, on a batched plan."""
+    from paper_1602_06621_amd import Plan, mlp_forward, warmstart_apply
+    from paper_1602_06621_amd.warmstart import init_params
+
+    mats = [warmstart_matrix(900, 450, 1.5, 21), warmstart_matrix(300, 600, 2.5, 22, lo=1, hi=4)]
+    params = init_params(4)
+    with Plan([_gpu(c) for c in mats], max_probes=4) as plan:
+        for learned in (True, False):
+            u0, v0 = plan.warm_start(params, 77, 4, 0.1, 10.0, learned=learned)
+            f = plan.sketch_features(77, 4, 0.1, 10.0)
+            du = mlp_forward(params, f["feat_rows"]) if learned else None
+            dv = mlp_forward(params, f["feat_cols"]) if learned else None
+            assert torch.equal(u0, warmstart_apply(f["u_sketch"], du, 10.0))
+            assert torch.equal(v0, warmstart_apply(f["v_sketch"], dv, 10.0))
