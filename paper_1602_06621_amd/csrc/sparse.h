@@ -138,6 +138,7 @@ struct mfe_plan {
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  std::vector<char> ws_host;  // host staging of the small tables copied into ws
   int64_t sign_words = 0;           // words per slot
   int32_t sign_k = 0;               // k the sign layout was built for
   int64_t sign_batch_base = -1;     // batch index of matrix 0 in that layout

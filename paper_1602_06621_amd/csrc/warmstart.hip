@@ -24,6 +24,7 @@
 // Training: mean squared error, Adam (Kingma & Ba), mini-batches drawn with replacement
 // by a counter-based Philox stream; every reduction is fixed-order (deterministic).
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "sparse.h"
@@ -157,7 +158,6 @@ __global__ __launch_bounds__(256) void k_side_stats(const double* __restrict__ e
 struct FeatMat {
   double tgt_row, tgt_col;  // alpha^2, beta^2
   double log_mn;            // log(m / n)
-  double c;                 // 1/4 log(alpha^2 F / n)
   int64_t row_base, col_base;
   int64_t m, n;
 };
@@ -165,7 +165,8 @@ struct FeatMat {
 // Features and sketch initialisation of one side (original order), matrix per index
 // found by binary search over the bases.
 __global__ void k_features(const double* __restrict__ est, const double* __restrict__ ratio,
-                           const double* __restrict__ stats, const FeatMat* __restrict__ fm, int count, int is_row,
+                           const double* __restrict__ stats, const double* __restrict__ stats_r,
+                           const double* __restrict__ stats_c, const FeatMat* __restrict__ fm, int count, int is_row,
                            int64_t total, double gamma, double M, float* __restrict__ feat,
                            double* __restrict__ sketch_init) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,13 +178,16 @@ __global__ void k_features(const double* __restrict__ est, const double* __restr
     else hi = mid - 1;
   }
   const FeatMat f = fm[lo];
+  // e^(4c) = alpha^2 F / n, F = (sum of row estimates + sum of column estimates) / 2
+  const double F = 0.5 * (stats_r[3 * lo + 2] + stats_c[3 * lo + 2]);
+  const double fc = F > 0 ? 0.25 * log(f.tgt_row * F / (double)f.n) : 0.0;
   const double tgt = is_row ? f.tgt_row : f.tgt_col;
   const double x = est[i];
   const double mean = stats[3 * lo], sd = stats[3 * lo + 1];
   double s, l;
   if (x > 0) {
     l = log(x);
-    s = -0.5 * l + f.c;
+    s = -0.5 * l + fc;
   } else {
     l = mean;                         // no entries: no information about the norm
     s = fmin(tgt / gamma, M);         // where an index without entries settles (Section 2.3)
@@ -197,7 +201,7 @@ __global__ void k_features(const double* __restrict__ est, const double* __restr
   o[3] = (float)(sd / 4.0);
   o[4] = is_row ? 1.f : 0.f;
   o[5] = (float)f.log_mn;
-  o[6] = (float)f.c;
+  o[6] = (float)fc;
   o[7] = (float)(ratio[i] > 0 ? log(ratio[i]) : 0.0);
 }
 
@@ -372,7 +376,7 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
   const int count = p->count;
   // sketch sign words: side 2 (indexed by column) and side 3 (by row), step 0, batch b
   std::vector<SignSeg> segs;
-  std::vector<int64_t> prefix{0}, wb_col(count), wb_row(count);
+  std::vector<int64_t> prefix{0}, wb_col(count), wb_row(count), rb(count + 1), cb(count + 1);
   int64_t words = 0, blocks = 0;
   for (int side = 2; side < 4; ++side)
     for (int b = 0; b < count; ++b) {
@@ -387,11 +391,31 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
       prefix.push_back(blocks);
       segs.push_back(sg);
     }
+  rb[0] = cb[0] = 0;
+  std::vector<FeatMat> fm(count);
+  for (int b = 0; b < count; ++b) {
+    rb[b + 1] = rb[b] + p->meta[b].m;
+    cb[b + 1] = cb[b] + p->meta[b].n;
+    const double al = alpha_b ? alpha_b[b] : std::pow((double)p->meta[b].n / p->meta[b].m, 0.25);
+    const double be = beta_b ? beta_b[b] : std::pow((double)p->meta[b].m / p->meta[b].n, 0.25);
+    fm[b].tgt_row = al * al;
+    fm[b].tgt_col = be * be;
+    fm[b].log_mn = std::log((double)p->meta[b].m / p->meta[b].n);
+    fm[b].row_base = rb[b];
+    fm[b].col_base = cb[b];
+    fm[b].m = p->meta[b].m;
+    fm[b].n = p->meta[b].n;
+  }
+  // the host-built tables come first in the scratch and travel in one copy
   Carver cv{ws};
   SignSeg* d_segs = cv.take<SignSeg>((int64_t)segs.size());
   int64_t* d_prefix = cv.take<int64_t>((int64_t)prefix.size());
   int64_t* d_wb_col = cv.take<int64_t>(count);
   int64_t* d_wb_row = cv.take<int64_t>(count);
+  int64_t* d_rbase = cv.take<int64_t>(count + 1);
+  int64_t* d_cbase = cv.take<int64_t>(count + 1);
+  FeatMat* d_fm = cv.take<FeatMat>(count);
+  const size_t table_bytes = cv.off;
   uint64_t* sw = cv.take<uint64_t>(words);
   double* est_r = cv.take<double>(p->M);
   double* est_c = cv.take<double>(p->N);
@@ -399,20 +423,24 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
   double* rat_c = cv.take<double>(p->N);
   double* st_r = cv.take<double>(3 * count);
   double* st_c = cv.take<double>(3 * count);
-  int64_t* d_rbase = cv.take<int64_t>(count + 1);
-  int64_t* d_cbase = cv.take<int64_t>(count + 1);
-  FeatMat* d_fm = cv.take<FeatMat>(count);
   if (!ws) {
     *bytes += cv.off + 256;
     return MFE_OK;
   }
-  int32_t *mat_of_row_slice, *mat_of_col_slice;
-  mat_of_row_slice = p->rows.slice_mat;
-  mat_of_col_slice = p->cols.slice_mat;
-  MFE_HIP(hipMemcpyAsync(d_segs, segs.data(), sizeof(SignSeg) * segs.size(), hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemcpyAsync(d_prefix, prefix.data(), sizeof(int64_t) * prefix.size(), hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemcpyAsync(d_wb_col, wb_col.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemcpyAsync(d_wb_row, wb_row.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
+  // staged in the plan: the copy may read the host buffer after this function returns
+  std::vector<char>& host = p->ws_host;
+  host.assign(table_bytes, 0);
+  auto put = [&](const void* dev, const void* src, size_t n) {
+    std::memcpy(host.data() + ((const char*)dev - ws), src, n);
+  };
+  put(d_segs, segs.data(), sizeof(SignSeg) * segs.size());
+  put(d_prefix, prefix.data(), sizeof(int64_t) * prefix.size());
+  put(d_wb_col, wb_col.data(), sizeof(int64_t) * count);
+  put(d_wb_row, wb_row.data(), sizeof(int64_t) * count);
+  put(d_rbase, rb.data(), sizeof(int64_t) * (count + 1));
+  put(d_cbase, cb.data(), sizeof(int64_t) * (count + 1));
+  put(d_fm, fm.data(), sizeof(FeatMat) * count);
+  MFE_HIP(hipMemcpyAsync(ws, host.data(), table_bytes, hipMemcpyHostToDevice, st));
   MFE_HIP(hipMemsetAsync(sw, 0, sizeof(uint64_t) * words, st));
   SignGenDev g;
   g.segs = d_segs;
@@ -438,6 +466,8 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
   C.ent = p->cols.ent;
   C.nint = p->cols.nint;
   C.is_row = 0;
+  const int32_t* mat_of_row_slice = p->rows.slice_mat;
+  const int32_t* mat_of_col_slice = p->cols.slice_mat;
   const unsigned gr = (unsigned)ceil_div(p->rows.nint, 256), gc = (unsigned)ceil_div(p->cols.nint, 256);
   // rows gather column-indexed sketch signs (side 2); columns gather row-indexed (side 3)
   if (ks == 4) {
@@ -450,40 +480,12 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
     k_sketch<16><<<gr, 256, 0, st>>>(R, p->mats, sw, d_wb_col, mat_of_col_slice, p->cols.orig, est_r, rat_r);
     k_sketch<16><<<gc, 256, 0, st>>>(C, p->mats, sw, d_wb_row, mat_of_row_slice, p->rows.orig, est_c, rat_c);
   }
-  std::vector<int64_t> rb(count + 1), cb(count + 1);
-  rb[0] = cb[0] = 0;
-  for (int b = 0; b < count; ++b) {
-    rb[b + 1] = rb[b] + p->meta[b].m;
-    cb[b + 1] = cb[b] + p->meta[b].n;
-  }
-  MFE_HIP(hipMemcpyAsync(d_rbase, rb.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemcpyAsync(d_cbase, cb.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, st));
   k_side_stats<<<count, 256, 0, st>>>(est_r, d_rbase, st_r);
   k_side_stats<<<count, 256, 0, st>>>(est_c, d_cbase, st_c);
-  MFE_HIP(hipGetLastError());
-  std::vector<double> hr(3 * count), hc(3 * count);
-  MFE_HIP(hipMemcpyAsync(hr.data(), st_r, sizeof(double) * 3 * count, hipMemcpyDeviceToHost, st));
-  MFE_HIP(hipMemcpyAsync(hc.data(), st_c, sizeof(double) * 3 * count, hipMemcpyDeviceToHost, st));
-  MFE_HIP(hipStreamSynchronize(st));
-  std::vector<FeatMat> fm(count);
-  for (int b = 0; b < count; ++b) {
-    const double al = alpha_b ? alpha_b[b] : std::pow((double)p->meta[b].n / p->meta[b].m, 0.25);
-    const double be = beta_b ? beta_b[b] : std::pow((double)p->meta[b].m / p->meta[b].n, 0.25);
-    const double F = 0.5 * (hr[3 * b + 2] + hc[3 * b + 2]);
-    fm[b].tgt_row = al * al;
-    fm[b].tgt_col = be * be;
-    fm[b].log_mn = std::log((double)p->meta[b].m / p->meta[b].n);
-    fm[b].c = F > 0 ? 0.25 * std::log(al * al * F / (double)p->meta[b].n) : 0.0;
-    fm[b].row_base = rb[b];
-    fm[b].col_base = cb[b];
-    fm[b].m = p->meta[b].m;
-    fm[b].n = p->meta[b].n;
-  }
-  MFE_HIP(hipMemcpyAsync(d_fm, fm.data(), sizeof(FeatMat) * count, hipMemcpyHostToDevice, st));
-  k_features<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(est_r, rat_r, st_r, d_fm, count, 1, p->M, gamma, M, feat_rows,
-                                                             u_sketch);
-  k_features<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(est_c, rat_c, st_c, d_fm, count, 0, p->N, gamma, M, feat_cols,
-                                                             v_sketch);
+  k_features<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(est_r, rat_r, st_r, st_r, st_c, d_fm, count, 1, p->M,
+                                                             gamma, M, feat_rows, u_sketch);
+  k_features<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(est_c, rat_c, st_c, st_r, st_c, d_fm, count, 0, p->N,
+                                                             gamma, M, feat_cols, v_sketch);
   MFE_HIP(hipGetLastError());
   return MFE_OK;
 }
