@@ -278,6 +278,59 @@ def bench_lsqr(mfe, plan, csr, out):
             **res}
 
 
+def profile_c3():
+    """Counter run for the bf16 workload: 20 steps of config 3, then the calibration copy."""
+    import numpy as np
+    import torch
+
+    from workloads import round_to_bf16, scaled_dense
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    m, n, k = 16384, 8192, 64
+    A = scaled_dense(m, n, 3.0, 1003)
+    bits, _ = round_to_bf16(A)
+    del A
+    D = mfe.Dense(torch.tensor(bits.view(np.int16), device="cuda:0"))
+    al, be = mfe.default_alpha_beta(m, n)
+    mfe.equilibrate(D, al, be, GAMMA, BOX_M, 20, k, 2003)
+    torch.cuda.synchronize()
+    calibration_copy()
+    print(json.dumps({"profile": "c3 done", "step_ms": mfe.last_timing()["step_ms"]}), flush=True)
+
+
+def profile_c4():
+    """Timing run for the warm start on the 200,000 x 100,000 evaluation matrix: ten calls
+    of the one-call warm start (sketch, network, clip) with an untrained network."""
+    import torch
+
+    from paper_1602_06621_amd import warmstart as W
+    from workloads import warmstart_matrix
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    c = warmstart_matrix(200_000, 100_000, 2.0, 9001)
+    params = W.init_params(1)
+    with mfe.Plan([mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0")],
+                  max_probes=16) as plan:
+        for _ in range(10):
+            plan.warm_start(params, 5)
+        torch.cuda.synchronize()
+    print(json.dumps({"profile": "c4 done"}), flush=True)
+
+
+def calibration_copy():
+    import torch
+
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    flush = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    flush.fill_(2.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def profile_run():
     """Counter run: 20 steps of the headline workload (per-launch counters are what is
     read), then a plain device copy of 512 MiB whose FETCH_SIZE / WRITE_SIZE calibrate
@@ -294,15 +347,9 @@ def profile_run():
     plan = mfe.Plan([A], max_probes=K_PROBES)
     plan.equilibrate(al, be, GAMMA, BOX_M, 20, K_PROBES, PROBE_SEED, use_graph=False)
     torch.cuda.synchronize()
-    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-    dst = torch.empty_like(src)
-    flush = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-    flush.fill_(2.0)
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    calibration_copy()
     plan.close()
-    print(json.dumps({"profile": "done", "copy_bytes": src.numel() * 4}), flush=True)
+    print(json.dumps({"profile": "done", "copy_bytes": 512 * 1024 * 1024}), flush=True)
 
 
 def main():
@@ -314,9 +361,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
-    ap.add_argument("--profile", action="store_true",
-                    help="short run for hardware counters: the headline workload with 20 steps, "
-                         "then a 512 MiB device copy used to calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4"],
+                    help="short run for hardware counters: 20 steps of the headline workload (c1, "
+                         "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
+                         "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -325,7 +373,7 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = set(args.workloads.split(","))
     if args.profile:
-        profile_run()
+        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4}[args.profile]()
         return
 
     import numpy as np

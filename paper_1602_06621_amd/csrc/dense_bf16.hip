@@ -13,12 +13,14 @@
 // kernel.  Probe blocks use the matching operand layout (per k chunk, lane l holds probe
 // 32 nb + l%32 at the same 8 k values).  Both are padded with zeros to whole tiles.
 //
-// Work split: one workgroup of 4 wavefronts per (32-row block, k range); the k chunks
-// of a block are split into `splits` ranges so that a pass launches ~1024 workgroups
-// (enough bytes in flight per CU to stream A at HBM rate).  The wavefronts of a
-// workgroup take the chunks of its range round-robin; their 32 x 64 FP32 accumulators
-// are summed in LDS (in FP64) and stored as one FP32 partial per range.  A second
-// launch adds the ranges in FP64 and runs the square / step / project / average update.
+// Work split: a workgroup of 4 wavefronts covers 4 consecutive 32-row blocks over one k
+// range (the k chunks are split into `splits` ranges so that a pass launches ~512
+// workgroups).  The four wavefronts walk the same chunks, so each probe tile is fetched
+// from L2 once per workgroup and read by the other wavefronts from L1 (probe loads were
+// two thirds of the L2 requests when every wavefront walked its own chunks; the pass is
+// bound by L2 requests in flight per CU).  Each wavefront stores its 32 x 32 NB FP32
+// accumulator as the partial of its block and range; a second launch adds the ranges in
+// FP64 and runs the square / step / project / average update.
 #include <cmath>
 #include <vector>
 
@@ -136,12 +138,36 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) {
   return r;
 }
 
-// One (32-row block, k range) per workgroup: partial Y (32 x 32 NB) = tiles . probes.
+// Wavefront w of workgroup (g, split): row block 4 g + w, chunks of range `split`;
+// partial Y (32 x 32 NB) = tiles . probes.
+template <int NB>
+struct ChunkGroup {
+  static constexpr int F = 4;  // chunks per group; two groups are in flight
+  u32x4 a[F];
+  u32x4 p[F][NB];
+  __device__ __forceinline__ void load(const u32x4* __restrict__ at, const u32x4* __restrict__ pt, int64_t kc) {
+#pragma unroll
+    for (int u = 0; u < F; ++u) {
+      a[u] = __builtin_nontemporal_load(at + (kc + u) * 64);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) p[u][b] = pt[((kc + u) * NB + b) * 64];
+    }
+  }
+  __device__ __forceinline__ void mma(f32x16 (&acc)[NB]) const {
+#pragma unroll
+    for (int u = 0; u < F; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u]), as_bf16x8(p[u][b]), acc[b], 0, 0, 0);
+  }
+};
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S) {
-  __shared__ float red[kWaves][kRows][32 * NB];
+  constexpr int F = ChunkGroup<NB>::F;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t rb = blockIdx.x;
+  const int64_t rb = (int64_t)blockIdx.x * kWaves + wave;
+  if (rb >= S.RB) return;
   const int split = blockIdx.y;
   const int64_t per = (S.KC + S.splits - 1) / S.splits;
   const int64_t kbeg = (int64_t)split * per, kend = kbeg + per < S.KC ? kbeg + per : S.KC;
@@ -152,23 +178,23 @@ __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S) {
     for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
   const u32x4* __restrict__ at = S.tiles + rb * S.KC * 64 + lane;
   const u32x4* __restrict__ pt = S.probes + lane;
-  int64_t kc = kbeg + wave;
-  // four chunks in flight per wavefront
-  for (; kc + 3 * kWaves < kend; kc += 4 * kWaves) {
-    u32x4 a[4], p[4][NB];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = __builtin_nontemporal_load(at + (kc + u * kWaves) * 64);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) p[u][b] = pt[((kc + u * kWaves) * NB + b) * 64];
+  // double-buffered groups: the loads of group g + 1 are issued before the products of g
+  const int64_t ngroups = (kend - kbeg) / F;
+  ChunkGroup<NB> g0, g1;
+  int64_t kc = kbeg;
+  if (ngroups > 0) g0.load(at, pt, kc);
+  for (int64_t g = 0; g < ngroups; g += 2) {
+    if (g + 1 < ngroups) g1.load(at, pt, kc + F);
+    g0.mma(acc);
+    if (g + 1 >= ngroups) {
+      kc += F;
+      break;
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u]), as_bf16x8(p[u][b]), acc[b], 0, 0, 0);
+    if (g + 2 < ngroups) g0.load(at, pt, kc + 2 * F);
+    g1.mma(acc);
+    kc += 2 * F;
   }
-  for (; kc < kend; kc += kWaves) {
+  for (; kc < kend; ++kc) {
     const u32x4 a = __builtin_nontemporal_load(at + kc * 64);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -176,39 +202,30 @@ __global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S) {
                                                        0, 0);
   }
   // accumulator layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + v%4, column l%32
+  float* __restrict__ out = S.part + ((int64_t)split * S.RB + rb) * kRows * 32 * NB;
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) red[wave][(v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)][b * 32 + (lane & 31)] = acc[b][v];
-  __syncthreads();
-  // the four wavefronts' sums of this range, one FP32 partial per (row, probe)
-  float* __restrict__ out = S.part + ((int64_t)split * S.RB + rb) * kRows * 32 * NB;
-  for (int e = threadIdx.x; e < kRows * 32 * NB; e += 256) {
-    const int row = e / (32 * NB), p = e % (32 * NB);
-    out[e] = (float)((double)red[0][row][p] + (double)red[1][row][p] + (double)red[2][row][p] + (double)red[3][row][p]);
-  }
+    for (int v = 0; v < 16; ++v)
+      out[((v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)) * 32 * NB + b * 32 + (lane & 31)] = acc[b][v];
 }
 
-// Update of every index from the FP32 partials of its row block: 8 threads per row add
-// the ranges in FP64, square, and sum over the probes.
+// Update of every index from the FP32 partials: one wavefront per row, lane p adds the
+// ranges of probe p in FP64 (coalesced over the probes), the squares are summed across
+// the wavefront, and lane 0 updates the iterate.
 template <int NB>
 __global__ __launch_bounds__(256) void k_bf16_update(Bf16Side S, int k, StepScalars sc, int* flag) {
-  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
-  const int part = threadIdx.x & 7;
-  double ss = 0.0;
-  if (r < S.RB * kRows) {
-    const int64_t stride = S.RB * kRows * 32 * NB;
-    const float* __restrict__ base = S.part + r * 32 * NB;
-    for (int p = part; p < 32 * NB; p += 8) {
-      if (p < k) {
-        double y = 0.0;
-        for (int sp = 0; sp < S.splits; ++sp) y += (double)base[sp * stride + p];
-        ss += y * y;
-      }
-    }
+  const int lane = threadIdx.x & 63;
+  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  if (r >= S.R) return;  // whole wavefronts leave together
+  const int64_t stride = S.RB * kRows * 32 * NB;
+  double y = 0.0;
+  if (lane < 32 * NB && lane < k) {
+    const float* __restrict__ base = S.part + r * 32 * NB + lane;
+    for (int sp = 0; sp < S.splits; ++sp) y += (double)base[sp * stride];
   }
-  for (int off = 4; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 8);
-  if (part == 0 && r < S.R) {
+  const double ss = wave_sum(y * y);
+  if (lane == 0) {
     double x = S.x[r], xb = S.xbar[r];
     if (!sgd_update(ss, k, S.target, sc, x, xb)) atomicOr(flag, 1);
     S.x[r] = x;
@@ -257,14 +274,15 @@ struct Bufs {
 
 template <int NB>
 void launch_pass(const Bf16Side& S, int k, const StepScalars& sc, int* flag, hipStream_t st) {
-  k_bf16_pass<NB><<<dim3((unsigned)S.RB, (unsigned)S.splits), dim3(256), 0, st>>>(S);
-  k_bf16_update<NB><<<dim3((unsigned)ceil_div(S.RB * kRows * 8, 256)), dim3(256), 0, st>>>(S, k, sc, flag);
+  k_bf16_pass<NB><<<dim3((unsigned)ceil_div(S.RB, kWaves), (unsigned)S.splits), dim3(256), 0, st>>>(S);
+  k_bf16_update<NB><<<dim3((unsigned)ceil_div(S.R * 64, 256)), dim3(256), 0, st>>>(S, k, sc, flag);
 }
 
-// k ranges per row block: about 1024 workgroups per pass, at least 16 chunks per range.
+// k ranges per row block: about 512 workgroups (of 4 row blocks) per pass, at least 32
+// chunks per range.
 int bf16_splits(int64_t RB, int64_t KC) {
   int64_t s = 1;
-  while (RB * s < 1024 && KC / (2 * s) >= 16) s *= 2;
+  while (ceil_div(RB, kWaves) * s < 512 && KC / (2 * s) >= 32) s *= 2;
   return (int)s;
 }
 

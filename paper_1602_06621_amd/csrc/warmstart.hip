@@ -111,48 +111,56 @@ __global__ __launch_bounds__(256) void k_sketch(SideDev S, const MatDev* __restr
   ratio[gi] = mean > 0.0 ? mx / mean : 0.0;
 }
 
-// Per matrix and side (one workgroup each): mean and std of log(est) over the non-empty
-// indices, sum of est.  stats[b] = {mean, std, sum}.
-__global__ __launch_bounds__(256) void k_side_stats(const double* __restrict__ est, const int64_t* __restrict__ base,
-                                                    double* __restrict__ stats) {
-  __shared__ double sh[3][256];
-  const int b = blockIdx.x;
+// Per matrix and side: mean and std of log(est) over the non-empty indices, and the sum
+// of est; stats[b] = {mean, std, sum}.  Two stages with a fixed order (deterministic):
+// workgroup (b, c) reduces chunk c of matrix b's range into part[b][c] = {sum log,
+// sum log^2, count, sum}; then one thread per matrix adds the chunks in order.
+constexpr int kStatChunks = 64;
+
+__global__ __launch_bounds__(256) void k_side_partial(const double* __restrict__ est, const int64_t* __restrict__ base,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  const int b = blockIdx.x, c = blockIdx.y;
   const int64_t lo = base[b], hi = base[b + 1];
-  double s1 = 0, s2 = 0, cnt = 0, sum = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+  const int64_t len = (hi - lo + kStatChunks - 1) / kStatChunks;
+  const int64_t c0 = lo + (int64_t)c * len, c1 = c0 + len < hi ? c0 + len : hi;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += 256) {
     const double x = est[i];
-    sum += x;
+    v[3] += x;
     if (x > 0) {
       const double l = log(x);
-      s1 += l;
-      s2 += l * l;
-      cnt += 1;
+      v[0] += l;
+      v[1] += l * l;
+      v[2] += 1.0;
     }
   }
-  sh[0][threadIdx.x] = s1;
-  sh[1][threadIdx.x] = s2;
-  sh[2][threadIdx.x] = cnt;
+  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = v[q];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
     __syncthreads();
   }
-  const double S1 = sh[0][0], S2 = sh[1][0], C = sh[2][0];
-  __syncthreads();
-  sh[0][threadIdx.x] = sum;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
-    __syncthreads();
+  if (threadIdx.x < 4) part[((int64_t)b * kStatChunks + c) * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_side_final(const double* __restrict__ part, int count, double* __restrict__ stats) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  double S1 = 0, S2 = 0, C = 0, sum = 0;
+  for (int c = 0; c < kStatChunks; ++c) {
+    const double* q = part + ((int64_t)b * kStatChunks + c) * 4;
+    S1 += q[0];
+    S2 += q[1];
+    C += q[2];
+    sum += q[3];
   }
-  if (threadIdx.x == 0) {
-    const double mean = C > 0 ? S1 / C : 0.0;
-    const double var = C > 0 ? fmax(S2 / C - mean * mean, 0.0) : 0.0;
-    stats[3 * b + 0] = mean;
-    stats[3 * b + 1] = sqrt(var);
-    stats[3 * b + 2] = sh[0][0];
-  }
+  const double mean = C > 0 ? S1 / C : 0.0;
+  const double var = C > 0 ? fmax(S2 / C - mean * mean, 0.0) : 0.0;
+  stats[3 * b + 0] = mean;
+  stats[3 * b + 1] = sqrt(var);
+  stats[3 * b + 2] = sum;
 }
 
 struct FeatMat {
@@ -423,6 +431,8 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
   double* rat_c = cv.take<double>(p->N);
   double* st_r = cv.take<double>(3 * count);
   double* st_c = cv.take<double>(3 * count);
+  double* part_r = cv.take<double>((int64_t)count * kStatChunks * 4);
+  double* part_c = cv.take<double>((int64_t)count * kStatChunks * 4);
   if (!ws) {
     *bytes += cv.off + 256;
     return MFE_OK;
@@ -480,8 +490,10 @@ int sketch_impl(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, c
     k_sketch<16><<<gr, 256, 0, st>>>(R, p->mats, sw, d_wb_col, mat_of_col_slice, p->cols.orig, est_r, rat_r);
     k_sketch<16><<<gc, 256, 0, st>>>(C, p->mats, sw, d_wb_row, mat_of_row_slice, p->rows.orig, est_c, rat_c);
   }
-  k_side_stats<<<count, 256, 0, st>>>(est_r, d_rbase, st_r);
-  k_side_stats<<<count, 256, 0, st>>>(est_c, d_cbase, st_c);
+  k_side_partial<<<dim3((unsigned)count, kStatChunks), 256, 0, st>>>(est_r, d_rbase, part_r);
+  k_side_partial<<<dim3((unsigned)count, kStatChunks), 256, 0, st>>>(est_c, d_cbase, part_c);
+  k_side_final<<<(unsigned)ceil_div(count, 64), 64, 0, st>>>(part_r, count, st_r);
+  k_side_final<<<(unsigned)ceil_div(count, 64), 64, 0, st>>>(part_c, count, st_c);
   k_features<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(est_r, rat_r, st_r, st_r, st_c, d_fm, count, 1, p->M,
                                                              gamma, M, feat_rows, u_sketch);
   k_features<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(est_c, rat_c, st_c, st_r, st_c, d_fm, count, 0, p->N,
