@@ -81,6 +81,7 @@ def _lib():
         "mfe_plan_equilibrate_trace": [vp, C.POINTER(_Params), i32, C.POINTER(dbl), vp, vp, vp, vp],
         "mfe_plan_autotune": [vp, C.POINTER(_Params), vp, vp, i32, vp, C.POINTER(dbl), C.POINTER(i32)],
         "mfe_plan_warmstart": [vp, vp, u64, i32, vp, vp, dbl, dbl, i32, vp, vp, vp],
+        "mfe_plan_set_tuning": [vp, i32, i32, i32],
         "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
         "mfe_mlp_sizes": [C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "mfe_mlp_forward": [vp, vp, i64, vp, vp],
@@ -344,8 +345,12 @@ class Plan:
         best, n = C.c_double(), C.c_int32()
         _check(_lib().mfe_plan_autotune(self._h, C.byref(p), ah, bh, int(trial_steps), chosen, C.byref(best),
                                         C.byref(n)))
-        return dict(loads_in_flight=chosen[0], two_part_rows=bool(chosen[1]), two_part_cols=bool(chosen[2]),
-                    step_ms=best.value, candidates=n.value)
+        return dict(loads_in_flight=chosen[0], rows_mode=chosen[1], cols_mode=chosen[2], step_ms=best.value,
+                    candidates=n.value)
+
+    def set_tuning(self, loads_in_flight=8, rows_mode=0, cols_mode=0):
+        """Launch configuration of the step kernels (see mfe_plan_set_tuning)."""
+        _check(_lib().mfe_plan_set_tuning(self._h, int(loads_in_flight), int(rows_mode), int(cols_mode)))
 
     def last_timing(self):
         a, b = C.c_double(), C.c_double()

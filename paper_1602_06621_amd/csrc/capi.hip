@@ -258,6 +258,21 @@ int mfe_plan_warmstart(mfe_plan* plan, const float* params, uint64_t seed, int32
                         (hipStream_t)stream);
 }
 
+int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  if (loads_in_flight != 4 && loads_in_flight != 8 && loads_in_flight != 16)
+    return set_error(MFE_EINVAL, "loads_in_flight must be 4, 8 or 16");
+  if (rows_mode < 0 || rows_mode > 1 || cols_mode < 0 || cols_mode > 1)
+    return set_error(MFE_EINVAL, "direction modes must be 0 or 1");
+  if ((rows_mode && !plan->rows.len_lo) || (cols_mode && !plan->cols.len_lo))
+    return set_error(MFE_EUNSUPPORTED, "two-part mode requested for a direction without the two-part layout");
+  plan->tune_batch = loads_in_flight;
+  plan->tune_split[0] = rows_mode;
+  plan->tune_split[1] = cols_mode;
+  return MFE_OK;
+}
+
 int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
                       int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates) {
   clear_error();

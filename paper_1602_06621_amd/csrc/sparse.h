@@ -132,7 +132,8 @@ struct mfe_plan {
   double* part[2] = {nullptr, nullptr};  // partial sums of the two-part mode (rows, columns)
   // Launch configuration of the step kernels, chosen by plan_autotune (results are the
   // same bit for bit under every configuration): loads in flight per lane, and whether
-  // each direction (rows, columns) with a two-part layout runs as two launches.
+  // each direction (rows, columns) with a two-part layout runs as one launch (0) or as
+  // two launches over the halves of its table (1).
   int32_t tune_batch = mfe::kBatch;
   int32_t tune_split[2] = {0, 0};
   // scratch of the warm-start calls (sketch, features, network outputs)

@@ -110,6 +110,8 @@ __device__ __forceinline__ void st_stream(Desc* p, Desc v) {
   st_stream(reinterpret_cast<u64x2*>(p), w);
 }
 
+// part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries [0, len_lo) to the
+// partial sums; 2 partial sums plus entries [len_lo, len), then the update.
 template <int KP, bool PACKED, int NB>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
@@ -120,6 +122,7 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   const int64_t s = r >> 6;
   const int lane = (int)(threadIdx.x & 63);
   const int mode = S.part_mode;  // uniform over the launch
+  const bool partial_out = mode == 1;
   const int len = ld_stream(S.len + r);
   const int split = mode != 0 ? ld_stream(S.len_lo + r) : 0;
   const int q_beg = mode == 2 ? split : 0;
@@ -127,7 +130,7 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   // The epilogue's operands are loaded before the gather loop so their latency overlaps it.
   int32_t li = 0, mi = 0;
   double x_old = 0.0, xbar_old = 0.0;
-  if (mode != 1) {
+  if (!partial_out) {
     li = ld_stream(S.orig + r);
     x_old = ld_stream(S.x + r);
     xbar_old = ld_stream(S.xbar + r);
@@ -161,7 +164,7 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
       }
     }
   }
-  if (mode == 1) {
+  if (partial_out) {
 #pragma unroll
     for (int p = 0; p < KP; ++p)
       if (p < k) st_stream(S.part + (int64_t)p * S.nint + r, acc[p]);
@@ -483,11 +486,11 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   // Keeping the directions apart lets each launch's L2 hold only the table it gathers.
   // A direction with a two-part layout runs as two launches, each gathering from one
   // half of the table, when the plan's tuning says so.
-  const bool split_rows = p->rows.len_lo && p->tune_split[0];
-  const bool split_cols = p->cols.len_lo && p->tune_split[1];
+  const int split_rows = p->rows.len_lo ? p->tune_split[0] : 0;  // 0 one launch, 1 two launches
+  const int split_cols = p->cols.len_lo ? p->tune_split[1] : 0;
   const int nb = p->tune_batch;
   for (int i = 0; i < 2; ++i) {
-    const bool need = i == 0 ? split_rows : split_cols;
+    const bool need = (i == 0 ? split_rows : split_cols) != 0;
     if (need && !p->part[i]) {
       const int64_t n = (i == 0 ? p->rows.nint : p->cols.nint) * (int64_t)p->max_probes;
       MFE_CHECK(ensure(&p->part[i], n));

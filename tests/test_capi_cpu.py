@@ -111,6 +111,10 @@ def test_autotune_argument_checks(lib):
     assert lib.mfe_plan_autotune(C.c_void_p(16), None, None, None, 10, None, None, None) == -1
 
 
+def test_set_tuning_argument_checks(lib):
+    assert lib.mfe_plan_set_tuning(None, 8, 0, 0) == -1
+
+
 def test_version(lib):
     assert "gfx950" in lib.mfe_version().decode()
 

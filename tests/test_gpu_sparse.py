@@ -314,52 +314,72 @@ def _two_part_case(m, n, mean, seed):
     return scaled_sparse(m, n, L, 2.0, seed + 1)
 
 
+def _split_modes(m, n, mode):
+    """(rows mode, columns mode) with `mode` on the direction(s) that have a two-part
+    layout: a direction gets one when the table it gathers (8 bytes per index of the
+    other direction, padded to whole slices) exceeds 6 MiB."""
+    big = lambda cnt: -(-cnt // 64) * 64 * 8 > 6 * 2**20
+    return (mode if big(n) else 0), (mode if big(m) else 0)
+
+
 @pytest.mark.parametrize("m,n,k", [(900_000, 250_000, 8), (200_000, 850_000, 8), (900_000, 250_000, 24)])
-def test_two_part_directions_bitwise_equal_one_part(m, n, k):
-    """A single matrix whose gathered table exceeds one XCD's L2 runs that direction as two
-    launches (halves of the table) with FP64 partial sums in between; the entry order of
-    the accumulation is unchanged, so the result equals the one-launch path bit for bit.
-    The one-launch path is what the same matrix gets inside a batched plan (a second,
-    tiny matrix disables the two-part mode); matrix 0 keeps sign batch index 0."""
+def test_two_part_mode_bitwise_equal_one_part(m, n, k):
+    """A single matrix whose gathered table exceeds one XCD's L2 has a two-part layout for
+    that direction.  Mode 1 (two launches over the halves of the table, FP64 partial sums
+    in between) keeps the entry order of the sums, so it equals mode 0 bit for bit."""
     from paper_1602_06621_amd import Plan
 
     _say(f"two-part {m}x{n} k={k}")
     A = _two_part_case(m, n, 5.0, 700 + k)
-    tiny = scaled_sparse(3, 2, 1, 1.0, 9)
-    with Plan([_gpu(A)], max_probes=k) as p1:
-        a = p1.equilibrate(None, None, 0.1, 10.0, 25, k, 31, use_graph=True)
-        a = {key: v.clone() for key, v in a.items()}
-    with Plan([_gpu(A), _gpu(tiny)], max_probes=k) as p2:
-        b = p2.equilibrate(None, None, 0.1, 10.0, 25, k, 31, use_graph=True)
-    assert torch.equal(a["u_bar"], b["u_bar"][:m])
-    assert torch.equal(a["v_bar"], b["v_bar"][:n])
+    with Plan([_gpu(A)], max_probes=k) as plan:
+        out = {}
+        for mode in (0, 1):
+            plan.set_tuning(8, *_split_modes(m, n, mode))
+            g = plan.equilibrate(None, None, 0.1, 10.0, 25, k, 31, use_graph=True)
+            out[mode] = {key: v.clone() for key, v in g.items()}
+    for key in ("u_bar", "v_bar"):
+        assert torch.equal(out[0][key], out[1][key])
 
 
-@pytest.mark.parametrize("k", [16, 24])
-def test_two_part_one_step_matches_oracle(k):
+@pytest.mark.parametrize("k,mode", [(16, 1), (24, 1), (16, 0)])
+def test_two_part_one_step_matches_oracle(k, mode):
     """Two-part column direction (row table 7.2 MB) with empty rows: one step from random
     in-box states (t0 > 0 as in a warm start) against one oracle step.  Whole runs at this
     size are not comparable elementwise at short T: the oracle's own u_bar moves by 3e-5
     after 40 steps under 1e-16 relative perturbations of z (measured on this matrix and
     on a fixed-length one of the same size)."""
-    from paper_1602_06621_amd import equilibrate
+    from paper_1602_06621_amd import Plan
 
     A = _two_part_case(900_000, 250_000, 5.0, 811)
     al, be = A1.default_alpha_beta(A.m, A.n)
-    As, G = A.to_scipy(), _gpu(A)
+    As = A.to_scipy()
     rng = np.random.default_rng(k)
     worst = 0.0
-    for t0 in (0, 7, 100):
-        u = np.clip(rng.normal(0, 1.5, A.m), -10, 10)
-        v = np.clip(rng.normal(0, 1.5, A.n), -10, 10)
-        g = equilibrate(G, al, be, 0.1, 10.0, 1, k, 43, t0=t0, u0=torch.tensor(u, device="cuda"),
-                        v0=torch.tensor(v, device="cuda"))
-        o = A1.equilibrate(As, al, be, 0.1, 10.0, 1, k=k, seed=43, t0=t0, u0=u, v0=v)
-        for key in ("u_bar", "v_bar"):
-            d = np.abs(g[key].cpu().numpy() - o[key]) / np.maximum(1.0, np.abs(o[key]))
-            worst = max(worst, d.max())
-    _say("two-part one-step worst rel err", worst)
+    with Plan([_gpu(A)], max_probes=k) as plan:
+        plan.set_tuning(8, *_split_modes(A.m, A.n, mode))
+        for t0 in (0, 7, 100):
+            u = np.clip(rng.normal(0, 1.5, A.m), -10, 10)
+            v = np.clip(rng.normal(0, 1.5, A.n), -10, 10)
+            g = plan.equilibrate(al, be, 0.1, 10.0, 1, k, 43, t0=t0, u0=torch.tensor(u, device="cuda"),
+                                 v0=torch.tensor(v, device="cuda"))
+            o = A1.equilibrate(As, al, be, 0.1, 10.0, 1, k=k, seed=43, t0=t0, u0=u, v0=v)
+            for key in ("u_bar", "v_bar"):
+                d = np.abs(g[key].cpu().numpy() - o[key]) / np.maximum(1.0, np.abs(o[key]))
+                worst = max(worst, d.max())
+    _say("two-part one-step worst rel err", mode, worst)
     assert worst <= 1e-11
+
+
+def test_set_tuning_rejects_missing_layout():
+    from paper_1602_06621_amd import Plan
+    from paper_1602_06621_amd._ffi import MfeError
+
+    with Plan([_gpu(scaled_sparse(300, 200, 4, 1.0, 3))], max_probes=4) as plan:
+        with pytest.raises(MfeError):
+            plan.set_tuning(8, 1, 0)
+        with pytest.raises(MfeError):
+            plan.set_tuning(5, 0, 0)
+        plan.set_tuning(16, 0, 0)
 
 
 def test_autotune_keeps_results_bitwise():
@@ -380,7 +400,8 @@ def test_autotune_keeps_results_bitwise():
             assert choice["loads_in_flight"] in (4, 8, 16)
             assert choice["candidates"] == (6 if len(group) == 1 else 3)
             b = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=True)
+            b = {key: v.clone() for key, v in b.items()}
             c = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=False)
             for key in ("u_bar", "v_bar"):
+                assert torch.equal(b[key], c[key])
                 assert torch.equal(a[key], b[key])
-                assert torch.equal(a[key], c[key])
