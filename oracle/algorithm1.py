@@ -3,7 +3,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Readings of the paper taken here (all listed in the design doc of the repository):
+Readings of the paper taken here:
   * Jacobi order: both the u and the v update at step t use (u^(t-1), v^(t-1)),
     exactly as Algorithm 1 writes D and E from the previous iterate.
   * k probes per step: the squared products are averaged over k independent

@@ -1,6 +1,6 @@
 """GPU parity of the sparse (CSR) path against the FP64 oracle, through the C ABI.
 
-Tolerance: the benchmark spec's bound for (u, v) is 1e-5 (max-abs on u_bar, v_bar, which is
+Tolerance: the target bound for (u, v) is 1e-5 (max-abs on u_bar, v_bar, which is
 the elementwise relative error of d, e).  The GPU path accumulates in FP64, so the
 measured error is far smaller; chaotic amplification of rounding in the first steps
 (eta_1 gamma = 1) is what separates the two at all.
