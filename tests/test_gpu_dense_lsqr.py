@@ -139,6 +139,24 @@ def test_dense_multi_launch_whole_run():
     assert err <= TOL
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 40), (40, 1), (30, 20)])
+def test_dense_degenerate_shapes(m, n):
+    """A single entry, a single row, a single column, and (30 x 20) with an all-zero row and
+    column (indices that cannot be equilibrated: they settle at min(M, target/gamma))."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(m, n, 1.0, 7 + m + n)
+    if (m, n) == (30, 20):
+        A[3, :] = 0.0
+        A[:, 5] = 0.0
+    al, be = A1.default_alpha_beta(m, n)
+    g = equilibrate(_dense(A), al, be, 0.1, 10.0, 50, 4, 11)
+    o = A1.equilibrate(A, al, be, 0.1, 10.0, 50, k=4, seed=11)
+    err = max(np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max(), np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max())
+    _say("dense degenerate", m, n, err)
+    assert err <= TOL
+
+
 def test_dense_ragged_shape_and_padded_ld():
     """Shapes that are not multiples of the wavefront, and a padded leading dimension."""
     from paper_1602_06621_amd import Dense, equilibrate

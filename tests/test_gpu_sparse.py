@@ -138,6 +138,29 @@ def test_warm_start_and_offset():
     assert _err(g, o) <= TOL
 
 
+@pytest.mark.parametrize("k,M", [(8, 20.0), (16, 12.0)])
+def test_wide_descriptors_for_few_probes_and_a_large_box(k, M):
+    """With M > 11, e^x leaves the range of the 8-byte descriptor, so even k <= 16 runs
+    with 16-byte descriptors (FP64 scale, 64 sign bits); parity at T = 80 (the oracle's
+    own spread here is ~1e-10)."""
+    csr = scaled_sparse(300, 170, 7, 1.5, 112 + k)
+    g, o = _both(csr, k, 80, 5, M=M)
+    err = _err(g, o)
+    _say("wide descriptors k", k, "M", M, "err", err)
+    assert err <= TOL
+
+
+def test_warm_start_outside_box_rejected():
+    from paper_1602_06621_amd import MfeError, equilibrate
+
+    csr = scaled_sparse(40, 30, 3, 1.0, 16)
+    u0 = np.zeros(40)
+    u0[7] = 10.5
+    with pytest.raises(MfeError, match="outside the box"):
+        equilibrate(_gpu(csr), None, None, 0.1, 10.0, 5, 2, 1, u0=torch.tensor(u0, device="cuda"),
+                    v0=torch.zeros(30, dtype=torch.float64, device="cuda"))
+
+
 def test_zero_steps_returns_warm_start():
     csr = scaled_sparse(70, 65, 3, 1.0, 15)
     u0 = np.linspace(-1, 1, 70)
@@ -226,6 +249,33 @@ def test_batched_plan_matches_per_matrix_oracle():
     for b, c in enumerate(mats):
         al, be = A1.default_alpha_beta(c.m, c.n)
         o = A1.equilibrate(c.to_scipy(), al, be, 0.1, 10.0, 70, k=8, seed=77, batch=b)
+        assert np.abs(ub[r0:r0 + c.m] - o["u_bar"]).max() <= TOL
+        assert np.abs(vb[c0:c0 + c.n] - o["v_bar"]).max() <= TOL
+        r0 += c.m
+        c0 += c.n
+
+
+def test_batched_plan_with_batch_base_warm_start_and_offset():
+    """Batched plan run with sign batch base 5, per-matrix warm starts (concatenated in plan
+    order) and t0 = 10: matrix b must equal the oracle with batch 5 + b and its slice of
+    the warm start."""
+    from paper_1602_06621_amd import Plan
+
+    shapes = [(150, 60), (40, 90), (1, 5), (300, 120)]
+    mats = [scaled_sparse(m, n, poisson_lengths(m, 4.0, n, 70 + i), 1.5, 80 + i) for i, (m, n) in enumerate(shapes)]
+    rng = np.random.default_rng(3)
+    u0s = [rng.normal(0, 0.5, m) for m, _ in shapes]
+    v0s = [rng.normal(0, 0.5, n) for _, n in shapes]
+    with Plan([_gpu(c) for c in mats], max_probes=8) as plan:
+        out = plan.equilibrate(None, None, 0.1, 10.0, 60, 8, 9, t0=10, batch=5,
+                               u0=torch.tensor(np.concatenate(u0s), device="cuda"),
+                               v0=torch.tensor(np.concatenate(v0s), device="cuda"), use_graph=True)
+        ub, vb = out["u_bar"].cpu().numpy(), out["v_bar"].cpu().numpy()
+    r0 = c0 = 0
+    for b, c in enumerate(mats):
+        al, be = A1.default_alpha_beta(c.m, c.n)
+        o = A1.equilibrate(c.to_scipy(), al, be, 0.1, 10.0, 60, k=8, seed=9, t0=10, u0=u0s[b], v0=v0s[b],
+                           batch=5 + b)
         assert np.abs(ub[r0:r0 + c.m] - o["u_bar"]).max() <= TOL
         assert np.abs(vb[c0:c0 + c.n] - o["v_bar"]).max() <= TOL
         r0 += c.m
