@@ -360,7 +360,7 @@ def main():
     ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
