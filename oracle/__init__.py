@@ -15,6 +15,8 @@ Contents
                 Phi and the condition-number bound (Section 2.2).
   metrics    -- RMS equilibration error (Section 4), relative optimality gap.
   lsqr       -- LSQR (Paige & Saunders) on the scaled system of Section 5.1.
+  variants   -- Section 6: symmetric equilibration (Algorithm 2), varying row and
+                column norms, block equilibration.
 
 Every function is pinned by a test in tests/test_oracle_*.py against something
 other than itself (closed forms, enumeration, library routines, theorems).
