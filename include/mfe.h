@@ -272,6 +272,45 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
  * direction without the layout. */
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode);
 
+/* ---- Section 6 variants (sparse plans) ------------------------------------------- */
+
+/* Symmetric equilibration (Section 6, problem (prob:sym-equil), Algorithm 2): a plan for
+ * one square CSR FP32 matrix A = A' (pattern and value bits checked on the device).
+ * mfe_plan_equilibrate then runs Algorithm 2 with k probes per step: one product
+ * D A D s per step, u <- clip(u - eta (z - alpha^2 + gamma u), -M, M) with
+ * z_i = e^(2u_i) mean_p (A e^u s_p)_i^2 and the running average as in Algorithm 1.
+ * The probes s are the side-0 stream of the probe contract (indexed by j = 0..n-1).
+ * p->beta and p->v0 are ignored; d and e both receive e^(u_bar), u_bar and v_bar both
+ * u_bar.  Autotuning, LSQR and the residual work as on other plans; the residual
+ * trace, warm starts, targets and blocks are EUNSUPPORTED.
+ * EDIM: m != n; EINVAL: A not symmetric or invalid CSR; EUNSUPPORTED: another kind. */
+int mfe_plan_create_symmetric(const mfe_matrix* A, int32_t max_probes, void* stream, mfe_plan** out);
+
+/* Varying row and column norms (Section 6, problem (prob:equil-vary-norms)): later runs
+ * of the plan aim at squared row norms row_target[i] and squared column norms
+ * col_target[j] instead of alpha^2 and beta^2 (the gradient is |DAE|^2 1 - r + gamma u).
+ * Device FP64 arrays of sum m and sum n values in the plan's concatenated original
+ * order, copied into the plan; NULL restores alpha^2 (beta^2) on that side.  The sums
+ * of both should agree (sum of squared row norms = sum of squared column norms), as
+ * m alpha^2 = n beta^2 does for the standard targets; this is not checked.
+ * EINVAL: a value that is not positive and finite (nothing is changed);
+ * EUNSUPPORTED: symmetric plan.  Synchronises `stream` (hipStream_t or NULL). */
+int mfe_plan_set_targets(mfe_plan* plan, const double* row_target, const double* col_target, void* stream);
+
+/* Block equilibration (Section 6, problem (prob:block-equil)), single-matrix plans:
+ * rows [row_ptr[b], row_ptr[b+1]) share one scaling e^(u_b) (row_blocks blocks), and
+ * columns likewise; host int64 arrays of blocks + 1 offsets from 0 to m (n), strictly
+ * increasing, copied into the plan; NULL for a side without blocks.  Later runs step
+ * the block variables with the sum of the block's row estimates (same probes as
+ * Algorithm 1) minus the block target (the sum of its rows' squared targets: alpha^2
+ * times the block size by default) plus gamma u_b.  In those runs p->u0 / p->v0 hold
+ * one value per block, u_bar / v_bar receive one value per block, and d / e one value
+ * per row / column (the block's scaling).
+ * EINVAL: offsets invalid (nothing is changed); EUNSUPPORTED: plan of several matrices
+ * or symmetric plan. */
+int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_blocks, const int64_t* col_ptr,
+                        int64_t col_blocks);
+
 /* Thread-local description of the last non-OK status (or a warning), never NULL. */
 const char* mfe_last_error(void);
 

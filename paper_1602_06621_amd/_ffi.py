@@ -82,6 +82,9 @@ def _lib():
         "mfe_plan_autotune": [vp, C.POINTER(_Params), vp, vp, i32, vp, C.POINTER(dbl), C.POINTER(i32)],
         "mfe_plan_warmstart": [vp, vp, u64, i32, vp, vp, dbl, dbl, i32, vp, vp, vp],
         "mfe_plan_set_tuning": [vp, i32, i32, i32],
+        "mfe_plan_create_symmetric": [C.POINTER(_Matrix), i32, vp, C.POINTER(vp)],
+        "mfe_plan_set_targets": [vp, vp, vp, vp],
+        "mfe_plan_set_blocks": [vp, vp, i64, vp, i64],
         "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
         "mfe_mlp_sizes": [C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "mfe_mlp_forward": [vp, vp, i64, vp, vp],
@@ -270,15 +273,54 @@ def equilibrate(A, alpha=None, beta=None, gamma=0.1, M=10.0, steps=100, probes=1
 class Plan:
     """Preprocessed CSR matrices (one or a batch) for repeated equilibration / LSQR runs."""
 
-    def __init__(self, mats: Sequence[Csr], max_probes: int = 16, stream=None):
+    def __init__(self, mats: Sequence[Csr], max_probes: int = 16, stream=None, symmetric=False):
         lib = _lib()
         self.mats = list(mats)
-        arr = (_Matrix * len(self.mats))(*[m.struct() for m in self.mats])
         h = C.c_void_p()
-        _check(lib.mfe_plan_create(arr, len(self.mats), int(max_probes), _stream(stream), C.byref(h)))
+        if symmetric:
+            if len(self.mats) != 1:
+                raise ValueError("a symmetric plan holds one matrix")
+            m0 = self.mats[0].struct()
+            _check(lib.mfe_plan_create_symmetric(C.byref(m0), int(max_probes), _stream(stream), C.byref(h)))
+        else:
+            arr = (_Matrix * len(self.mats))(*[m.struct() for m in self.mats])
+            _check(lib.mfe_plan_create(arr, len(self.mats), int(max_probes), _stream(stream), C.byref(h)))
         self._h = h
+        self.symmetric = bool(symmetric)
         self.M = sum(m.m for m in self.mats)
         self.N = sum(m.n for m in self.mats)
+        self._blocks = (None, None)
+        self._targets_dev = (None, None)
+
+    @classmethod
+    def symmetric_plan(cls, A: Csr, max_probes: int = 16, stream=None) -> "Plan":
+        """Plan for Algorithm 2 (symmetric equilibration, Section 6) of a symmetric matrix."""
+        return cls([A], max_probes=max_probes, stream=stream, symmetric=True)
+
+    def set_targets(self, row_target=None, col_target=None, stream=None):
+        """Squared row / column norm targets per index (Section 6, varying norms); None
+        restores alpha^2 / beta^2 on that side.  Device FP64 tensors of sum m / sum n."""
+        rt = None if row_target is None else row_target.to(torch.float64).contiguous()
+        ct = None if col_target is None else col_target.to(torch.float64).contiguous()
+        if rt is not None and rt.numel() != self.M:
+            raise ValueError("row_target needs one value per row")
+        if ct is not None and ct.numel() != self.N:
+            raise ValueError("col_target needs one value per column")
+        _check(_lib().mfe_plan_set_targets(self._h, _ptr(rt), _ptr(ct), _stream(stream)))
+        self._targets_dev = (rt, ct)
+
+    def set_blocks(self, row_ptr=None, col_ptr=None):
+        """Block equilibration (Section 6): offsets of row / column blocks (host sequences
+        from 0 to m / n), or None for a side without blocks."""
+        def arr(ptr):
+            if ptr is None:
+                return None, 0
+            vals = [int(x) for x in ptr]
+            return (C.c_int64 * len(vals))(*vals), len(vals) - 1
+        ra, rn = arr(row_ptr)
+        ca, cn = arr(col_ptr)
+        _check(_lib().mfe_plan_set_blocks(self._h, ra, rn, ca, cn))
+        self._blocks = (rn if row_ptr is not None else None, cn if col_ptr is not None else None)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -317,10 +359,12 @@ class Plan:
         else:
             a0, b0 = alpha, beta
         if out is None:
+            nu = self._blocks[0] if self._blocks[0] is not None else self.M
+            nv = self._blocks[1] if self._blocks[1] is not None else self.N
             out = dict(d=torch.empty(self.M, dtype=torch.float64, device=device),
                        e=torch.empty(self.N, dtype=torch.float64, device=device),
-                       u_bar=torch.empty(self.M, dtype=torch.float64, device=device),
-                       v_bar=torch.empty(self.N, dtype=torch.float64, device=device))
+                       u_bar=torch.empty(nu, dtype=torch.float64, device=device),
+                       v_bar=torch.empty(nv, dtype=torch.float64, device=device))
         p = _params(a0, b0, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream)
         _check(lib.mfe_plan_equilibrate(self._h, C.byref(p), ah, bh, int(bool(use_graph)), _ptr(out["d"]),
                                         _ptr(out["e"]), _ptr(out.get("u_bar")), _ptr(out.get("v_bar"))))

@@ -244,6 +244,8 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   MFE_CHECK(check_params(p, true));
   if (p->probes > plan->max_probes) return set_error(MFE_EINVAL, "probes exceed the plan's max_probes");
+  if (plan_has_variant(plan))
+    return set_error(MFE_EUNSUPPORTED, "the residual trace measures the standard problem (no variant settings)");
   return plan_equilibrate_trace(plan, p, trace_every, rms_trace, d, e, u_bar, v_bar);
 }
 
@@ -254,8 +256,28 @@ int mfe_plan_warmstart(mfe_plan* plan, const float* params, uint64_t seed, int32
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   if (!u0 || !v0) return set_error(MFE_EINVAL, "NULL output");
   if (!(gamma > 0) || !(box_M > 0)) return set_error(MFE_EINVAL, "gamma and M must be positive");
+  if (plan_has_variant(plan))
+    return set_error(MFE_EUNSUPPORTED, "warm starts are trained for the standard problem (no variant settings)");
   return plan_warmstart(plan, params, seed, probes, alpha_b, beta_b, gamma, box_M, learned, u0, v0,
                         (hipStream_t)stream);
+}
+
+int mfe_plan_create_symmetric(const mfe_matrix* A, int32_t max_probes, void* stream, mfe_plan** out) {
+  clear_error();
+  return plan_build_symmetric(A, max_probes, (hipStream_t)stream, out);
+}
+
+int mfe_plan_set_targets(mfe_plan* plan, const double* row_target, const double* col_target, void* stream) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  return plan_set_targets(plan, row_target, col_target, (hipStream_t)stream);
+}
+
+int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_blocks, const int64_t* col_ptr,
+                        int64_t col_blocks) {
+  clear_error();
+  if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
+  return plan_set_blocks(plan, row_ptr, row_blocks, col_ptr, col_blocks, nullptr);
 }
 
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode) {

@@ -91,6 +91,23 @@ struct SideDev {
   int part_mode;
   const int32_t* len_lo;
   double* part;               // [k][nint] FP64 partial sums
+  // Section 6 variants (read by the variant kernel only): per-index squared targets in
+  // internal order (null: the matrix's alpha^2 / beta^2), and for a side with blocks the
+  // buffer receiving each index's estimate z instead of the update.
+  const double* tgt;
+  double* zout;
+};
+
+// One side of a block-equilibrated plan (Section 6): indices [ptr[b], ptr[b+1]) of the
+// original order share the variable x_b.
+struct BlockDev {
+  const int64_t* ptr;         // [nb + 1]
+  int64_t nb;
+  const int32_t* orig2int;    // original index -> internal index
+  const double* tgt;          // [nb] block targets (sums of the indices' squared targets)
+  double* bx;                 // [nb] block iterate
+  double* bxbar;              // [nb] running average
+  const double* z;            // [nint] per-index estimates of the current step
 };
 
 struct SignGenDev {
@@ -155,7 +172,25 @@ struct mfe_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  double graph_key[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double graph_key[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // ---- Section 6 variants
+  // Symmetric plan (Algorithm 2): one square symmetric matrix; the row entries are also
+  // stored with indices into the rows' own internal order, and a step is one launch.
+  bool symmetric = false;
+  int2* ent_sym = nullptr;
+  // Varying norms: per-index squared targets, original and internal order (rows, cols).
+  double* tgt_orig[2] = {nullptr, nullptr};
+  double* tgt_int[2] = {nullptr, nullptr};
+  // Block equilibration (single-matrix plans): per side, block offsets and state.
+  struct BlockSide {
+    int64_t nb = 0;                      // 0: no blocks on this side
+    int64_t* ptr = nullptr;              // [nb + 1] on the device
+    double* tgt = nullptr;               // [nb]
+    double* bx = nullptr;                // [nb]
+    double* bxbar = nullptr;             // [nb]
+    double* z = nullptr;                 // [nint]
+  } blk[2];
+  int64_t variant_epoch = 0;             // bumped by every variant setting (graph key)
 };
 
 namespace mfe {
@@ -194,6 +229,15 @@ int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, do
               int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t s);
 int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta,
                   double* rms, double* rms_nonempty, int64_t* n_empty, hipStream_t s);
+// Section 6 variants.
+int plan_build_symmetric(const mfe_matrix* A, int32_t max_probes, hipStream_t s, mfe_plan** out);
+int plan_set_targets(mfe_plan* p, const double* row_target, const double* col_target, hipStream_t s);
+int plan_set_blocks(mfe_plan* p, const int64_t* row_ptr, int64_t nrb, const int64_t* col_ptr, int64_t ncb,
+                    hipStream_t s);
+void plan_free_variants(mfe_plan* p);
+inline bool plan_has_variant(const mfe_plan* p) {
+  return p->symmetric || p->tgt_int[0] || p->tgt_int[1] || p->blk[0].nb || p->blk[1].nb;
+}
 
 // Makes sure the per-matrix device table exists (original-index bases are all that
 // LSQR and the residual need from it).

@@ -366,6 +366,7 @@ void plan_free(mfe_plan* p) {
     (void)hipFree(p->part[i]);
   }
   (void)hipFree(p->ws);
+  plan_free_variants(p);
   (void)hipFree(p->segs);
   (void)hipFree(p->seg_prefix);
   (void)hipFree(p->mats);

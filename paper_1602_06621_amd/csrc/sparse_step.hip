@@ -112,7 +112,9 @@ __device__ __forceinline__ void st_stream(Desc* p, Desc v) {
 
 // part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries [0, len_lo) to the
 // partial sums; 2 partial sums plus entries [len_lo, len), then the update.
-template <int KP, bool PACKED, int NB>
+// VAR (the Section 6 variant kernel): per-index targets, or the estimate z written out
+// for the block update instead of the update itself.
+template <int KP, bool PACKED, int NB, bool VAR = false>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
   using C = Codec<KP, PACKED>;
@@ -129,12 +131,15 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   const int q_end = mode == 1 ? split : len;
   // The epilogue's operands are loaded before the gather loop so their latency overlaps it.
   int32_t li = 0, mi = 0;
-  double x_old = 0.0, xbar_old = 0.0;
+  double x_old = 0.0, xbar_old = 0.0, tgt_r = 0.0;
   if (!partial_out) {
     li = ld_stream(S.orig + r);
     x_old = ld_stream(S.x + r);
-    xbar_old = ld_stream(S.xbar + r);
+    if (!VAR || !S.zout) xbar_old = ld_stream(S.xbar + r);
     mi = S.slice_mat[s];
+    if constexpr (VAR) {
+      if (S.tgt) tgt_r = ld_stream(S.tgt + r);
+    }
   }
   const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
   const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
@@ -171,26 +176,40 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
     return;
   }
   if (li < 0) return;
-  const MatDev mt = mats[mi];
-  double ss = 0.0;
+  {
+    // Every product and sum of the update is rounded on its own (no fused multiply-add),
+    // as in the plain definition, so that all kernels that finish an update agree bit
+    // for bit.
+#pragma clang fp contract(off)
+    const MatDev mt = mats[mi];
+    double ss = 0.0;
 #pragma unroll
-  for (int p = 0; p < KP; ++p)
-    if (p < k) ss += acc[p] * acc[p];
-  const double z = exp(2.0 * x_old) * (ss / (double)k);
-  const double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
-  const double g = (z - tgt) + sc.gamma * x_old;
-  double xn = x_old - sc.eta * g;
-  xn = fmin(fmax(xn, -sc.M), sc.M);
-  const bool bad = !isfinite(z) || !isfinite(xn);
-  if (bad) {
-    atomicOr(flag, 1);
-    xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
+    for (int p = 0; p < KP; ++p)
+      if (p < k) ss += acc[p] * acc[p];
+    const double z = exp(2.0 * x_old) * (ss / (double)k);
+    double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
+    if constexpr (VAR) {
+      if (S.zout) {  // block side: the estimate goes to the block update
+        if (!isfinite(z)) atomicOr(flag, 1);
+        st_stream(S.zout + r, z);
+        return;
+      }
+      if (S.tgt) tgt = tgt_r;
+    }
+    const double g = (z - tgt) + sc.gamma * x_old;
+    double xn = x_old - sc.eta * g;
+    xn = fmin(fmax(xn, -sc.M), sc.M);
+    const bool bad = !isfinite(z) || !isfinite(xn);
+    if (bad) {
+      atomicOr(flag, 1);
+      xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
+    }
+    st_stream(S.x + r, xn);
+    st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
+    const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
+    st_stream(reinterpret_cast<DT*>(S.out) + r,
+              C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
   }
-  st_stream(S.x + r, xn);
-  st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
-  const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
-  st_stream(reinterpret_cast<DT*>(S.out) + r,
-            C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
 }
 
 __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk) {
@@ -221,7 +240,91 @@ __global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
   else signgen_block(a.gen, b - a.side_blocks);
 }
 
+// The same for the Section 6 variants (per-index targets, block sides, symmetric plans).
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
+  const int64_t b = blockIdx.x;
+  if (b < a.side_blocks) side_update<KP, PACKED, 8, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else signgen_block(a.gen, b - a.side_blocks);
+}
+
 __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
+
+// Block update of one side (Section 6, block equilibration), one wavefront per block:
+// the sum of the indices' estimates over the block (original index order, each lane a
+// strided part, then the wavefront sum), the projected step and the average of the
+// block variable, then every index of the block gets the new value and its descriptor
+// for the next step.  init != 0: the block variables start from x0 (or 0) instead.
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k, StepScalars sc,
+                                                    int64_t wbase, const double* __restrict__ x0, int init,
+                                                    int* flag) {
+#pragma clang fp contract(off)
+  using C = Codec<KP, PACKED>;
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (b >= B.nb) return;  // whole wavefronts
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t j0 = B.ptr[b], j1 = B.ptr[b + 1];
+  double xn;
+  if (init) {
+    xn = x0 ? x0[b] : 0.0;
+    if (!(fabs(xn) <= sc.M)) {
+      if (lane == 0) atomicOr(flag, 2);
+      xn = 0.0;
+    }
+    if (lane == 0) {
+      B.bx[b] = xn;
+      B.bxbar[b] = xn;
+    }
+  } else {
+    double part = 0.0;
+    for (int64_t j = j0 + lane; j < j1; j += 64) part += B.z[B.orig2int[j]];
+    const double zb = wave_sum(part);
+    const double x_old = B.bx[b];
+    const double g = (zb - B.tgt[b]) + sc.gamma * x_old;
+    xn = x_old - sc.eta * g;
+    xn = fmin(fmax(xn, -sc.M), sc.M);
+    if (!isfinite(zb) || !isfinite(xn)) {
+      if (lane == 0) atomicOr(flag, 1);
+      xn = 0.0;
+    }
+    if (lane == 0) {
+      B.bx[b] = xn;
+      B.bxbar[b] = 2.0 * xn / (sc.tau + 2.0) + sc.tau * B.bxbar[b] / (sc.tau + 2.0);
+    }
+  }
+  const double sx = exp(xn);
+  for (int64_t j = j0 + lane; j < j1; j += 64) {
+    const int32_t r = B.orig2int[j];
+    S.x[r] = xn;
+    reinterpret_cast<typename C::T*>(S.out)[r] = C::encode(sx, extract_bits(S.next_signs + wbase, j * k, k));
+  }
+}
+
+// Targets of the blocks of one side: the sum over each block of the indices' squared
+// targets (t2 each when no per-index targets are set), wavefront per block.
+__global__ __launch_bounds__(256) void k_block_targets(const int64_t* __restrict__ ptr, int64_t nb,
+                                                       const double* __restrict__ tgt, double t2,
+                                                       double* __restrict__ out) {
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (b >= nb) return;
+  const int lane = (int)(threadIdx.x & 63);
+  double part = 0.0;
+  for (int64_t j = ptr[b] + lane; j < ptr[b + 1]; j += 64) part += tgt ? tgt[j] : t2;
+  const double sum = wave_sum(part);
+  if (lane == 0) out[b] = sum;
+}
+
+// Per-index outputs of a block side: e^(x_bar) of the index's block.
+__global__ void k_block_output(BlockDev B, double* __restrict__ dout, double* __restrict__ xbar_out) {
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (b >= B.nb) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const double xb = B.bxbar[b];
+  const double dv = exp(xb);
+  for (int64_t j = B.ptr[b] + lane; j < B.ptr[b + 1]; j += 64) dout[j] = dv;
+  if (lane == 0 && xbar_out) xbar_out[b] = xb;
+}
 
 template <int KP, bool PACKED>
 __global__ void k_init(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ x0, int k, double M,
@@ -341,6 +444,8 @@ SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gath
   S.part_mode = 0;
   S.len_lo = L.len_lo;
   S.part = nullptr;
+  S.tgt = nullptr;
+  S.zout = nullptr;
   return S;
 }
 
@@ -379,7 +484,9 @@ void dispatch(int k, bool packed, Args&&... args) {
 template <int KP, bool PACKED>
 struct PhaseLauncher {
   static void run(const PhaseArgs& a, int nb, hipStream_t st) {
-    if (nb <= 4) {
+    if (a.side.tgt || a.side.zout) {
+      k_phase_var<KP, PACKED><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
+    } else if (nb <= 4) {
       launch_phase<KP, PACKED, 4>(a, st);
     } else if constexpr (KP <= 16) {
       if (nb >= 16) launch_phase<KP, PACKED, 16>(a, st);
@@ -387,6 +494,15 @@ struct PhaseLauncher {
     } else {
       launch_phase<KP, PACKED, 8>(a, st);
     }
+  }
+};
+
+template <int KP, bool PACKED>
+struct BlockLauncher {
+  static void run(const SideDev& S, const BlockDev& B, int k, const StepScalars& sc, int64_t wbase,
+                  const double* x0, int init, int* flag, hipStream_t st) {
+    k_block_step<KP, PACKED><<<dim3((unsigned)ceil_div(B.nb, 4)), dim3(256), 0, st>>>(S, B, k, sc, wbase, x0, init,
+                                                                                        flag);
   }
 };
 
@@ -460,11 +576,38 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     md[b].col_orig_base = co;
     md[b].sign_word_col = p->segs_host[b].word_off;              // side 0
     md[b].sign_word_row = p->segs_host[p->count + b].word_off;   // side 1
+    // Algorithm 2 draws one probe block s, indexed like the columns (side 0)
+    if (p->symmetric) md[b].sign_word_row = md[b].sign_word_col;
     ro += p->meta[b].m;
     co += p->meta[b].n;
   }
   MFE_HIP(hipMemcpyAsync(p->mats, md.data(), sizeof(MatDev) * p->count, hipMemcpyHostToDevice, st));
   MFE_HIP(hipMemsetAsync(p->flag, 0, sizeof(int), st));
+
+  // Block sides: targets of this run (sums of the indices' squared targets), state.
+  const bool blocked[2] = {p->blk[0].nb > 0, p->blk[1].nb > 0};
+  BlockDev bd[2];
+  for (int i = 0; i < 2; ++i) {
+    if (!blocked[i]) continue;
+    mfe_plan::BlockSide& bs = p->blk[i];
+    const SideLayout& L = i == 0 ? p->rows : p->cols;
+    MFE_CHECK(ensure(&bs.tgt, bs.nb));
+    MFE_CHECK(ensure(&bs.bx, bs.nb));
+    MFE_CHECK(ensure(&bs.bxbar, bs.nb));
+    MFE_CHECK(ensure(&bs.z, L.nint));
+    const double t2 = i == 0 ? md[0].tgt_row : md[0].tgt_col;
+    k_block_targets<<<dim3((unsigned)ceil_div(bs.nb, 4)), dim3(256), 0, st>>>(bs.ptr, bs.nb, p->tgt_orig[i], t2,
+                                                                                bs.tgt);
+    MFE_HIP(hipGetLastError());
+    bd[i].ptr = bs.ptr;
+    bd[i].nb = bs.nb;
+    bd[i].orig2int = L.orig2int;
+    bd[i].tgt = bs.tgt;
+    bd[i].bx = bs.bx;
+    bd[i].bxbar = bs.bxbar;
+    bd[i].z = bs.z;
+  }
+  const int64_t wbase[2] = {md[0].sign_word_row, md[0].sign_word_col};
 
   const uint64_t seed = prm->seed;
   const int T = prm->steps;
@@ -476,8 +619,16 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   {
     SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[0], p->signs[1], 1);
     SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[0], p->signs[1], 0);
-    dispatch<InitLauncher>(k, packed, R, (const MatDev*)p->mats, prm->u0, k, prm->box_M, p->flag, st);
-    dispatch<InitLauncher>(k, packed, C, (const MatDev*)p->mats, prm->v0, k, prm->box_M, p->flag, st);
+    StepScalars sc0{};
+    sc0.M = prm->box_M;
+    if (blocked[0])
+      dispatch<BlockLauncher>(k, packed, R, bd[0], k, sc0, wbase[0], prm->u0, 1, p->flag, st);
+    else
+      dispatch<InitLauncher>(k, packed, R, (const MatDev*)p->mats, prm->u0, k, prm->box_M, p->flag, st);
+    if (blocked[1])
+      dispatch<BlockLauncher>(k, packed, C, bd[1], k, sc0, wbase[1], prm->v0, 1, p->flag, st);
+    else if (!p->symmetric)
+      dispatch<InitLauncher>(k, packed, C, (const MatDev*)p->mats, prm->v0, k, prm->box_M, p->flag, st);
     MFE_HIP(hipGetLastError());
   }
 
@@ -486,7 +637,8 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   // Keeping the directions apart lets each launch's L2 hold only the table it gathers.
   // A direction with a two-part layout runs as two launches, each gathering from one
   // half of the table, when the plan's tuning says so.
-  const int split_rows = p->rows.len_lo ? p->tune_split[0] : 0;  // 0 one launch, 1 two launches
+  // (Symmetric plans gather with their own entries, which have no two-part layout.)
+  const int split_rows = p->rows.len_lo && !p->symmetric ? p->tune_split[0] : 0;  // 0 one launch, 1 two
   const int split_cols = p->cols.len_lo ? p->tune_split[1] : 0;
   const int nb = p->tune_batch;
   for (int i = 0; i < 2; ++i) {
@@ -499,14 +651,23 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   auto phase_args = [&](int t, bool rows, int mode) {
     PhaseArgs a;
     const int par = t & 1, prev = par ^ 1;
-    if (rows)
+    if (rows && p->symmetric) {
+      // Algorithm 2: D A D s, the row entries gathering the rows' own descriptors
+      a.side = make_side(p->rows, p->x_row, p->xbar_row, p->desc_row[prev], p->desc_row[par],
+                         p->signs[(t + 1) & 1], 1);
+      a.side.ent = p->ent_sym;
+    } else if (rows) {
       a.side = make_side(p->rows, p->x_row, p->xbar_row, p->desc_col[prev], p->desc_row[par],
                          p->signs[(t + 1) & 1], 1);
-    else
+    } else {
       a.side = make_side(p->cols, p->x_col, p->xbar_col, p->desc_row[prev], p->desc_col[par],
                          p->signs[(t + 1) & 1], 0);
+    }
     a.side.part_mode = mode;
     a.side.part = p->part[rows ? 0 : 1];
+    const int si = rows ? 0 : 1;
+    if (blocked[si]) a.side.zout = p->blk[si].z;
+    else a.side.tgt = p->tgt_int[si];
     const uint64_t gen_step = (uint64_t)t + 2;
     const bool gen = rows && mode != 2 && (int64_t)gen_step <= (int64_t)T + 1;
     a.gen = make_gen(p, seed, gen_step, p->signs[t & 1]);
@@ -522,13 +683,21 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     a.flag = p->flag;
     return a;
   };
+  // A block side adds one launch after its direction: the block sums, steps and the
+  // descriptors of the block's indices (which the other direction reads at step t+1).
   auto launch_step = [&](int t, hipStream_t s) {
     for (const bool rows : {true, false}) {
+      if (!rows && p->symmetric) break;
       if (rows ? split_rows : split_cols) {
         dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 1), nb, s);
         dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 2), nb, s);
       } else {
         dispatch<PhaseLauncher>(k, packed, phase_args(t, rows, 0), nb, s);
+      }
+      const int si = rows ? 0 : 1;
+      if (blocked[si]) {
+        const PhaseArgs a = phase_args(t, rows, 0);
+        dispatch<BlockLauncher>(k, packed, a.side, bd[si], k, a.sc, wbase[si], nullptr, 0, p->flag, s);
       }
     }
   };
@@ -540,11 +709,11 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
-    const double key[11] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+    const double key[12] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
                             (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
-                            (double)nb, (double)split_rows, (double)split_cols};
+                            (double)nb, (double)split_rows, (double)split_cols, (double)p->variant_epoch};
     bool hit = p->graph_exec != nullptr;
-    for (int i = 0; i < 11 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    for (int i = 0; i < 12 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     if (!hit) {
       if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -555,7 +724,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-      for (int i = 0; i < 11; ++i) p->graph_key[i] = key[i];
+      for (int i = 0; i < 12; ++i) p->graph_key[i] = key[i];
     }
     if (st == nullptr) {
       // graphs are replayed on the plan's own stream, ordered after the default stream
@@ -592,8 +761,11 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     const int par = T & 1;
     SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[par], nullptr, 1);
     SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[par], nullptr, 0);
-    k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, d, u_bar);
-    k_output<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, run_st>>>(C, p->mats, e, v_bar);
+    if (blocked[0]) k_block_output<<<dim3((unsigned)ceil_div(bd[0].nb, 4)), dim3(256), 0, run_st>>>(bd[0], d, u_bar);
+    else k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, d, u_bar);
+    if (blocked[1]) k_block_output<<<dim3((unsigned)ceil_div(bd[1].nb, 4)), dim3(256), 0, run_st>>>(bd[1], e, v_bar);
+    else if (p->symmetric) k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, e, v_bar);
+    else k_output<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, run_st>>>(C, p->mats, e, v_bar);
     MFE_HIP(hipGetLastError());
   }
   int flag = 0;

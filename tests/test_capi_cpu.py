@@ -115,6 +115,20 @@ def test_set_tuning_argument_checks(lib):
     assert lib.mfe_plan_set_tuning(None, 8, 0, 0) == -1
 
 
+def test_variant_argument_checks(lib):
+    """Section 6 entry points reject NULL plans, non-square symmetric requests and other
+    kinds before any device work."""
+    assert lib.mfe_plan_set_targets(None, None, None, None) == -1
+    assert lib.mfe_plan_set_blocks(None, None, 0, None, 0) == -1
+    h = C.c_void_p()
+    assert lib.mfe_plan_create_symmetric(None, 4, None, C.byref(h)) == -1
+    assert lib.mfe_plan_create_symmetric(None, 4, None, None) == -1
+    s = _csr_struct()   # 4 x 3
+    assert lib.mfe_plan_create_symmetric(C.byref(s), 4, None, C.byref(h)) == -2
+    s.kind = 0          # dense FP64
+    assert lib.mfe_plan_create_symmetric(C.byref(s), 4, None, C.byref(h)) == -6
+
+
 def test_version(lib):
     assert "gfx950" in lib.mfe_version().decode()
 

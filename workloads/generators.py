@@ -118,6 +118,33 @@ def scaled_sparse(
     return CSR(m, n, row_ptr.astype(np.int32), col_idx, vals.astype(np.float32))
 
 
+def symmetric_sparse(n: int, half_nnz_per_row: int, sigma: float, seed: int) -> CSR:
+    """Square symmetric CSR FP32: G with half_nnz_per_row uniform random distinct columns
+    per row and N(0,1) values, A = diag(e^r) (G + G') diag(e^r) with r iid N(0, sigma^2),
+    computed in FP64 (entry (i, j) and (j, i) by the same operations) and rounded once to
+    FP32, so that A equals its transpose bit for bit.  About 2 half_nnz_per_row entries
+    per row."""
+    g = rng(seed)
+    lengths = np.full(n, int(half_nnz_per_row), dtype=np.int64)
+    cols = _distinct_columns(g, lengths, n)
+    rows = np.repeat(np.arange(n), lengths)
+    vals = g.standard_normal(rows.size)
+    G = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    S = (G + G.T).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    r = g.normal(0.0, sigma, n)
+    er = np.exp(r)
+    ri = np.repeat(np.arange(n), np.diff(S.indptr))
+    data = (S.data * er[ri]) * er[S.indices]
+    keep = data != 0.0
+    A = sp.csr_matrix((data[keep], S.indices[keep], np.concatenate([[0], np.cumsum(
+        np.bincount(ri[keep], minlength=n))])), shape=(n, n))
+    if A.nnz >= 2**31:
+        raise ValueError("nnz does not fit int32 row pointers")
+    return CSR(n, n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float32))
+
+
 def poisson_lengths(m: int, mean: float, n: int, seed: int) -> np.ndarray:
     """Per-row nonzero counts ~ Poisson(mean), capped at n (empty rows allowed)."""
     g = rng(seed)
