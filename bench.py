@@ -15,8 +15,10 @@ The other workloads of the build are measured under "extra" (same run, same GPU)
   c3    dense bf16 16384 x 8192, k = 64, T = 500 on the matrix cores
   c4    learned warm start vs plain SGD: steps and seconds to equal residual (200000 x 100000)
   lsqr  LSQR on the headline matrix to 1e-6 with (d, e), with (1, e) and without
+  var   Section 6 variants: per-index targets and blocks (16 rows / 8 columns) on the
+        headline matrix; Algorithm 2 on a symmetric 1,000,000 x 1,000,000 matrix
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,c4,lsqr]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,c4,lsqr,var]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -52,6 +54,21 @@ def sparse_algorithmic_bytes(m, n, nnz, k):
     """
     desc = 8 if k <= 16 else 16
     return 2 * nnz * 8 + (m + n) * (16 + 16 + 2 * desc + 8 + k / 4.0)
+
+
+def block_algorithmic_bytes(m, n, nnz, k):
+    """One step with blocks on both sides: per stored entry and direction 8 B; per index,
+    in the direction launch its length and original index (8 B), iterate read (8 B) and
+    estimate write (8 B), in the block launch the index map (4 B), estimate read (8 B),
+    iterate write (8 B) and descriptor write (8 B), plus the descriptor's compulsory read
+    (8 B) and the sign bits (k/4 B).  Block variables are negligible."""
+    return 2 * nnz * 8 + (m + n) * (8 + 8 + 8 + 4 + 8 + 8 + 8 + 8 + k / 4.0)
+
+
+def symmetric_algorithmic_bytes(n, nnz, k):
+    """One step of Algorithm 2: one product (8 B per stored entry) and the per-index
+    state of one side (as sparse_algorithmic_bytes)."""
+    return nnz * 8 + n * (16 + 16 + 2 * 8 + 8 + k / 4.0)
 
 
 def bf16_algorithmic(m, n, k):
@@ -278,6 +295,55 @@ def bench_lsqr(mfe, plan, csr, out):
             **res}
 
 
+def bench_variants(mfe, plan, csr, al, be):
+    """Section 6 variants, 500 graph-replayed steps each (k = 16)."""
+    import numpy as np
+    import torch
+
+    from workloads import symmetric_sparse
+
+    T, k = 500, K_PROBES
+    res = {}
+    g = np.random.default_rng(5)
+    rt = torch.tensor(al**2 * g.uniform(0.5, 2.0, csr.m), device="cuda:0")
+    ct = torch.tensor(be**2 * g.uniform(0.5, 2.0, csr.n), device="cuda:0")
+    run = dict(alpha=al, beta=be, gamma=GAMMA, M=BOX_M, steps=T, probes=k, seed=PROBE_SEED, use_graph=True)
+
+    def measure(label, by, prs):
+        out = None
+        for _ in range(2):
+            out = plan_ref[0].equilibrate(**run, out=None)
+        step_ms = plan_ref[0].last_timing()["step_ms"]
+        res[label] = {"step_ms": step_ms, "pairs_per_s": prs / (step_ms / 1e3), "algorithmic_bytes": by,
+                      "algorithmic_gbs": by / (step_ms / 1e3) / 1e9,
+                      "hbm_frac": by / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                      "finite": bool(torch.isfinite(out["d"]).all().item())}
+
+    plan_ref = [plan]
+    plan.set_targets(rt, ct)
+    measure("targets", sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, k) + 8 * (csr.m + csr.n), k)
+    plan.set_targets(None, None)
+    plan.set_blocks(list(range(0, csr.m, 16)) + [csr.m], list(range(0, csr.n, 8)) + [csr.n])
+    measure("blocks_16x8", block_algorithmic_bytes(csr.m, csr.n, csr.nnz, k), k)
+    plan.set_blocks(None, None)
+    res["targets"]["workload"] = "headline matrix, per-row/column squared targets, k=16"
+    res["blocks_16x8"]["workload"] = "headline matrix, row blocks of 16, column blocks of 8, k=16"
+
+    t0 = time.time()
+    S = symmetric_sparse(1_000_000, 5, SIGMA, 1005)
+    gen_s = time.time() - t0
+    As = mfe.Csr.from_arrays(S.n, S.n, S.row_ptr, S.col_idx, S.val, device="cuda:0")
+    sym = mfe.Plan.symmetric_plan(As, max_probes=k)
+    plan_ref[0] = sym
+    run["alpha"] = run["beta"] = 1.0
+    # one pair = one probe column through A (= A'), the only product of a step
+    measure("symmetric", symmetric_algorithmic_bytes(S.n, S.nnz, k), k)
+    res["symmetric"].update({"workload": "Algorithm 2, symmetric CSR f32 1e6x1e6 (G + G', 5 random columns "
+                                         "per row of G, sigma=2 scales), k=16", "nnz": S.nnz, "gen_s": gen_s})
+    sym.close()
+    return res
+
+
 def profile_c3():
     """Counter run for the bf16 workload: 20 steps of config 3, then the calibration copy."""
     import numpy as np
@@ -357,7 +423,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr")
+    ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr,var")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
@@ -422,6 +488,9 @@ def main():
     if "lsqr" in work:
         print("# measuring lsqr", file=sys.stderr, flush=True)
         extra["lsqr"] = bench_lsqr(mfe, plan, csr, out)
+    if "var" in work:
+        print("# measuring var", file=sys.stderr, flush=True)
+        extra["var"] = bench_variants(mfe, plan, csr, al, be)
 
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:

@@ -108,6 +108,7 @@ struct BlockDev {
   double* bx;                 // [nb] block iterate
   double* bxbar;              // [nb] running average
   const double* z;            // [nint] per-index estimates of the current step
+  int32_t group;              // lanes per block (power of two, 1..64)
 };
 
 struct SignGenDev {
@@ -184,6 +185,7 @@ struct mfe_plan {
   // Block equilibration (single-matrix plans): per side, block offsets and state.
   struct BlockSide {
     int64_t nb = 0;                      // 0: no blocks on this side
+    int32_t group = 64;                  // lanes per block in the block kernels
     int64_t* ptr = nullptr;              // [nb + 1] on the device
     double* tgt = nullptr;               // [nb]
     double* bx = nullptr;                // [nb]

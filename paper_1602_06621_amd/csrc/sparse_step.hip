@@ -250,51 +250,68 @@ __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
 
-// Block update of one side (Section 6, block equilibration), one wavefront per block:
-// the sum of the indices' estimates over the block (original index order, each lane a
-// strided part, then the wavefront sum), the projected step and the average of the
-// block variable, then every index of the block gets the new value and its descriptor
-// for the next step.  init != 0: the block variables start from x0 (or 0) instead.
+// Lane groups of the block kernels: G lanes (a power of two, 1..64, chosen from the
+// mean block size) share one block; the wavefront holds 64 / G blocks.  group_sum adds
+// the G lanes' values in a fixed butterfly order and returns the group's first lane's
+// result in every lane of the group, so the value is the same on every run.
+__device__ __forceinline__ double group_sum(double v, int G) {
+  for (int off = G >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = (int)(threadIdx.x & 63);
+  return G > 1 ? __shfl(v, lane & ~(G - 1), 64) : v;
+}
+
+// Block update of one side (Section 6, block equilibration): the sum of the indices'
+// estimates over each block (original index order, each lane of the block's group a
+// strided part, then the group sum), the projected step and the average of the block
+// variable, then every index of the block gets the new value and its descriptor for
+// the next step.  init != 0: the block variables start from x0 (or 0) instead.
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k, StepScalars sc,
                                                     int64_t wbase, const double* __restrict__ x0, int init,
                                                     int* flag) {
 #pragma clang fp contract(off)
   using C = Codec<KP, PACKED>;
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (b >= B.nb) return;  // whole wavefronts
-  const int lane = (int)(threadIdx.x & 63);
-  const int64_t j0 = B.ptr[b], j1 = B.ptr[b + 1];
-  double xn;
+  const int G = B.group;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gt / G;
+  const int sub = (int)(gt % G);
+  const bool valid = b < B.nb;
+  const int64_t j0 = valid ? B.ptr[b] : 0, j1 = valid ? B.ptr[b + 1] : 0;
+  double xn = 0.0;
   if (init) {
-    xn = x0 ? x0[b] : 0.0;
-    if (!(fabs(xn) <= sc.M)) {
-      if (lane == 0) atomicOr(flag, 2);
-      xn = 0.0;
-    }
-    if (lane == 0) {
-      B.bx[b] = xn;
-      B.bxbar[b] = xn;
+    if (valid) {
+      xn = x0 ? x0[b] : 0.0;
+      if (!(fabs(xn) <= sc.M)) {
+        if (sub == 0) atomicOr(flag, 2);
+        xn = 0.0;
+      }
+      if (sub == 0) {
+        B.bx[b] = xn;
+        B.bxbar[b] = xn;
+      }
     }
   } else {
     double part = 0.0;
-    for (int64_t j = j0 + lane; j < j1; j += 64) part += B.z[B.orig2int[j]];
-    const double zb = wave_sum(part);
-    const double x_old = B.bx[b];
-    const double g = (zb - B.tgt[b]) + sc.gamma * x_old;
-    xn = x_old - sc.eta * g;
-    xn = fmin(fmax(xn, -sc.M), sc.M);
-    if (!isfinite(zb) || !isfinite(xn)) {
-      if (lane == 0) atomicOr(flag, 1);
-      xn = 0.0;
-    }
-    if (lane == 0) {
-      B.bx[b] = xn;
-      B.bxbar[b] = 2.0 * xn / (sc.tau + 2.0) + sc.tau * B.bxbar[b] / (sc.tau + 2.0);
+    for (int64_t j = j0 + sub; j < j1; j += G) part += B.z[B.orig2int[j]];
+    const double zb = group_sum(part, G);  // every lane takes part
+    if (valid) {
+      const double x_old = B.bx[b];
+      const double g = (zb - B.tgt[b]) + sc.gamma * x_old;
+      xn = x_old - sc.eta * g;
+      xn = fmin(fmax(xn, -sc.M), sc.M);
+      if (!isfinite(zb) || !isfinite(xn)) {
+        if (sub == 0) atomicOr(flag, 1);
+        xn = 0.0;
+      }
+      if (sub == 0) {
+        B.bx[b] = xn;
+        B.bxbar[b] = 2.0 * xn / (sc.tau + 2.0) + sc.tau * B.bxbar[b] / (sc.tau + 2.0);
+      }
     }
   }
+  if (!valid) return;
   const double sx = exp(xn);
-  for (int64_t j = j0 + lane; j < j1; j += 64) {
+  for (int64_t j = j0 + sub; j < j1; j += G) {
     const int32_t r = B.orig2int[j];
     S.x[r] = xn;
     reinterpret_cast<typename C::T*>(S.out)[r] = C::encode(sx, extract_bits(S.next_signs + wbase, j * k, k));
@@ -302,29 +319,37 @@ __global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k
 }
 
 // Targets of the blocks of one side: the sum over each block of the indices' squared
-// targets (t2 each when no per-index targets are set), wavefront per block.
-__global__ __launch_bounds__(256) void k_block_targets(const int64_t* __restrict__ ptr, int64_t nb,
+// targets (t2 each when no per-index targets are set), one lane group per block.
+__global__ __launch_bounds__(256) void k_block_targets(const int64_t* __restrict__ ptr, int64_t nb, int G,
                                                        const double* __restrict__ tgt, double t2,
                                                        double* __restrict__ out) {
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (b >= nb) return;
-  const int lane = (int)(threadIdx.x & 63);
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gt / G;
+  const int sub = (int)(gt % G);
+  const bool valid = b < nb;
   double part = 0.0;
-  for (int64_t j = ptr[b] + lane; j < ptr[b + 1]; j += 64) part += tgt ? tgt[j] : t2;
-  const double sum = wave_sum(part);
-  if (lane == 0) out[b] = sum;
+  if (valid)
+    for (int64_t j = ptr[b] + sub; j < ptr[b + 1]; j += G) part += tgt ? tgt[j] : t2;
+  const double sum = group_sum(part, G);
+  if (valid && sub == 0) out[b] = sum;
 }
 
 // Per-index outputs of a block side: e^(x_bar) of the index's block.
 __global__ void k_block_output(BlockDev B, double* __restrict__ dout, double* __restrict__ xbar_out) {
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int G = B.group;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gt / G;
+  const int sub = (int)(gt % G);
   if (b >= B.nb) return;
-  const int lane = (int)(threadIdx.x & 63);
   const double xb = B.bxbar[b];
   const double dv = exp(xb);
-  for (int64_t j = B.ptr[b] + lane; j < B.ptr[b + 1]; j += 64) dout[j] = dv;
-  if (lane == 0 && xbar_out) xbar_out[b] = xb;
+  for (int64_t j = B.ptr[b] + sub; j < B.ptr[b + 1]; j += G) dout[j] = dv;
+  if (sub == 0 && xbar_out) xbar_out[b] = xb;
 }
+
+// Workgroups of 256 threads covering nb blocks of G lanes.
+inline unsigned block_grid(int64_t nb, int G) { return (unsigned)ceil_div(nb * G, 256); }
+
 
 template <int KP, bool PACKED>
 __global__ void k_init(SideDev S, const MatDev* __restrict__ mats, const double* __restrict__ x0, int k, double M,
@@ -501,8 +526,8 @@ template <int KP, bool PACKED>
 struct BlockLauncher {
   static void run(const SideDev& S, const BlockDev& B, int k, const StepScalars& sc, int64_t wbase,
                   const double* x0, int init, int* flag, hipStream_t st) {
-    k_block_step<KP, PACKED><<<dim3((unsigned)ceil_div(B.nb, 4)), dim3(256), 0, st>>>(S, B, k, sc, wbase, x0, init,
-                                                                                        flag);
+    k_block_step<KP, PACKED><<<dim3(block_grid(B.nb, B.group)), dim3(256), 0, st>>>(S, B, k, sc, wbase, x0,
+                                                                                       init, flag);
   }
 };
 
@@ -596,8 +621,8 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     MFE_CHECK(ensure(&bs.bxbar, bs.nb));
     MFE_CHECK(ensure(&bs.z, L.nint));
     const double t2 = i == 0 ? md[0].tgt_row : md[0].tgt_col;
-    k_block_targets<<<dim3((unsigned)ceil_div(bs.nb, 4)), dim3(256), 0, st>>>(bs.ptr, bs.nb, p->tgt_orig[i], t2,
-                                                                                bs.tgt);
+    k_block_targets<<<dim3(block_grid(bs.nb, bs.group)), dim3(256), 0, st>>>(bs.ptr, bs.nb, bs.group,
+                                                                               p->tgt_orig[i], t2, bs.tgt);
     MFE_HIP(hipGetLastError());
     bd[i].ptr = bs.ptr;
     bd[i].nb = bs.nb;
@@ -606,6 +631,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     bd[i].bx = bs.bx;
     bd[i].bxbar = bs.bxbar;
     bd[i].z = bs.z;
+    bd[i].group = bs.group;
   }
   const int64_t wbase[2] = {md[0].sign_word_row, md[0].sign_word_col};
 
@@ -761,9 +787,9 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     const int par = T & 1;
     SideDev R = make_side(p->rows, p->x_row, p->xbar_row, nullptr, p->desc_row[par], nullptr, 1);
     SideDev C = make_side(p->cols, p->x_col, p->xbar_col, nullptr, p->desc_col[par], nullptr, 0);
-    if (blocked[0]) k_block_output<<<dim3((unsigned)ceil_div(bd[0].nb, 4)), dim3(256), 0, run_st>>>(bd[0], d, u_bar);
+    if (blocked[0]) k_block_output<<<dim3(block_grid(bd[0].nb, bd[0].group)), dim3(256), 0, run_st>>>(bd[0], d, u_bar);
     else k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, d, u_bar);
-    if (blocked[1]) k_block_output<<<dim3((unsigned)ceil_div(bd[1].nb, 4)), dim3(256), 0, run_st>>>(bd[1], e, v_bar);
+    if (blocked[1]) k_block_output<<<dim3(block_grid(bd[1].nb, bd[1].group)), dim3(256), 0, run_st>>>(bd[1], e, v_bar);
     else if (p->symmetric) k_output<<<dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, run_st>>>(R, p->mats, e, v_bar);
     else k_output<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, run_st>>>(C, p->mats, e, v_bar);
     MFE_HIP(hipGetLastError());

@@ -197,6 +197,10 @@ int plan_set_blocks(mfe_plan* p, const int64_t* row_ptr, int64_t nrb, const int6
     MFE_CHECK(dev_alloc(&bs.ptr, nb + 1));
     MFE_HIP(hipMemcpyAsync(bs.ptr, ptr, sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, st));
     bs.nb = nb;
+    // lanes per block: the power of two at or above the mean block size, at most 64
+    const int64_t mean = ceil_div(ptr[nb], nb);
+    bs.group = 1;
+    while (bs.group < 64 && bs.group < mean) bs.group *= 2;
   }
   MFE_HIP(hipStreamSynchronize(st));
   ++p->variant_epoch;
