@@ -41,7 +41,7 @@ GEN_SEED, PROBE_SEED = 1001, 2001
 # HBM-side bytes per step of k_phase<16, true, 8> on the headline workload, from rocprofv3
 # FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) per launch, calibrated against a plain
 # 512 MiB copy (profiles/k_phase_csr_1e6x5e5_k16.md).  Set to None when the kernel changes.
-TRAFFIC_BYTES_PER_STEP = (174.9 + 666.2 + 27.0 + 12.0) * 1e6
+TRAFFIC_BYTES_PER_STEP = (175.0 + 665.1 + 27.0 + 12.0) * 1e6
 
 
 def sparse_algorithmic_bytes(m, n, nnz, k):
@@ -385,6 +385,37 @@ def profile_c4():
     print(json.dumps({"profile": "c4 done"}), flush=True)
 
 
+def profile_var():
+    """Timing run for the Section 6 variants: 20 eager steps each of per-index targets and
+    of blocks (16 rows / 8 columns) on the headline matrix, then of Algorithm 2 on the
+    symmetric 1,000,000 x 1,000,000 matrix."""
+    import numpy as np
+    import torch
+
+    from workloads import scaled_sparse, symmetric_sparse
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    csr = scaled_sparse(M_ROWS, N_COLS, NNZ_ROW, SIGMA, GEN_SEED)
+    al, be = mfe.default_alpha_beta(csr.m, csr.n)
+    g = np.random.default_rng(5)
+    run = dict(gamma=GAMMA, M=BOX_M, steps=20, probes=K_PROBES, seed=PROBE_SEED)
+    with mfe.Plan([mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")],
+                  max_probes=K_PROBES) as plan:
+        plan.set_targets(torch.tensor(al**2 * g.uniform(0.5, 2.0, csr.m), device="cuda:0"),
+                         torch.tensor(be**2 * g.uniform(0.5, 2.0, csr.n), device="cuda:0"))
+        plan.equilibrate(al, be, **run)
+        plan.set_targets(None, None)
+        plan.set_blocks(list(range(0, csr.m, 16)) + [csr.m], list(range(0, csr.n, 8)) + [csr.n])
+        plan.equilibrate(al, be, **run)
+    S = symmetric_sparse(1_000_000, 5, SIGMA, 1005)
+    with mfe.Plan.symmetric_plan(mfe.Csr.from_arrays(S.n, S.n, S.row_ptr, S.col_idx, S.val, device="cuda:0"),
+                                 max_probes=K_PROBES) as sym:
+        sym.equilibrate(1.0, 1.0, **run)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "var done"}), flush=True)
+
+
 def calibration_copy():
     import torch
 
@@ -427,10 +458,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
-    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4"],
+    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4", "var"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
-                         "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls")
+                         "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls; var: 20 steps "
+                         "of each Section 6 variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -439,7 +471,7 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = set(args.workloads.split(","))
     if args.profile:
-        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4}[args.profile]()
+        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4, "var": profile_var}[args.profile]()
         return
 
     import numpy as np
