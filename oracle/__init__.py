@@ -17,6 +17,8 @@ Contents
   lsqr       -- LSQR (Paige & Saunders) on the scaled system of Section 5.1.
   variants   -- Section 6: symmetric equilibration (Algorithm 2), varying row and
                 column norms, block equilibration.
+  ccp        -- Chambolle-Cremers-Pock on the Lasso, with and without equilibration
+                (Section 5.2).
 
 Every function is pinned by a test in tests/test_oracle_*.py against something
 other than itself (closed forms, enumeration, library routines, theorems).

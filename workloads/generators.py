@@ -145,6 +145,36 @@ def symmetric_sparse(n: int, half_nnz_per_row: int, sigma: float, seed: int) -> 
     return CSR(n, n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float32))
 
 
+def paper_sparse(m: int, n: int, density: float, seed: int) -> CSR:
+    """The construction of the paper's experiments (Section 4): a sparse matrix with each
+    entry nonzero with probability `density` (per-row counts Binomial(n, density), distinct
+    uniform columns), N(0,1) nonzeros, scaled as diag(e^u) A diag(e^v) with u, v iid
+    N(1, 1); FP64, rounded once to FP32."""
+    g = rng(seed)
+    lengths = g.binomial(n, density, size=m).astype(np.int64)
+    col_idx = _distinct_columns(g, lengths, n)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lengths, out=row_ptr[1:])
+    u = g.normal(1.0, 1.0, m)
+    v = g.normal(1.0, 1.0, n)
+    rows = np.repeat(np.arange(m), lengths)
+    vals = g.standard_normal(row_ptr[-1]) * np.exp(u[rows] + v[col_idx])
+    return CSR(m, n, row_ptr.astype(np.int32), col_idx, vals.astype(np.float32))
+
+
+def lasso_rhs(A, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Right-hand side of the Lasso experiment (Section 5.2): x_hat with n/10 nonzero
+    entries at uniform random positions, drawn N(0,1); b = A x_hat + nu, nu iid N(0,1).
+    A is any matrix with a product (values taken as stored, in FP64)."""
+    g = rng(seed)
+    m, n = A.shape
+    x_hat = np.zeros(n)
+    idx = g.choice(n, n // 10, replace=False)
+    x_hat[idx] = g.standard_normal(idx.size)
+    b = np.asarray(A @ x_hat, dtype=np.float64).ravel() + g.standard_normal(m)
+    return b, x_hat
+
+
 def poisson_lengths(m: int, mean: float, n: int, seed: int) -> np.ndarray:
     """Per-row nonzero counts ~ Poisson(mean), capped at n (empty rows allowed)."""
     g = rng(seed)
