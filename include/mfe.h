@@ -103,6 +103,14 @@ typedef struct {
   double normal_eq;        /* ||Abar' rbar|| / (||Abar|| ||rbar||) estimate at the last check */
 } mfe_lsqr_info;
 
+typedef struct {
+  int32_t iters;           /* CCP iterations run */
+  int32_t norm_iters;      /* power iterations spent on ||D A E||_2 (0 when it was given) */
+  double op_norm;          /* ||D A E||_2 used for the step sizes */
+  double tau, sigma;       /* step sizes 0.9 / op_norm */
+  double objective;        /* ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1 at the end */
+} mfe_ccp_info;
+
 typedef struct mfe_plan mfe_plan;
 
 /* alpha = (n/m)^(1/4), beta = (m/n)^(1/4): the choice of Section 4, which satisfies
@@ -271,6 +279,32 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
  * direction without the layout. */
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode);
+
+/* ---- Chambolle-Cremers-Pock on the Lasso (Section 5.2), sparse plans ---------------- */
+
+/* ||D A E||_2 of the plan's matrix (block diagonal for a batched plan) by power iteration
+ * on (DAE)'(DAE) from the normalised all-ones vector; the estimate is ||DAE v|| for the
+ * current unit vector v (a lower bound), and the run stops when it changes by at most
+ * tol (relative) over 10 iterations, or after max_iter iterations.  d [sum m], e [sum n]:
+ * device FP64, NULL = identity.  norm, iters: host (iters nullable).
+ * EINVAL: NULL plan or norm, max_iter < 1, tol < 0. */
+int mfe_plan_op_norm(mfe_plan* plan, const double* d, const double* e, int32_t max_iter, double tol,
+                     double* norm, int32_t* iters, void* stream);
+
+/* The Lasso of Section 5.2, minimise ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1, by the
+ * Chambolle-Pock primal-dual method with theta = 1 and tau = sigma = 0.9 / ||D A E||_2 from
+ * zero iterates, run on D A E with x = E xbar (D = E = I without equilibration):
+ *   y  <- (y + sigma (D A E xt - d b)) / (1 + sigma d^2 sqrt(lam) / 2)   (prox of sigma g*)
+ *   x' <- soft(x - tau E A' D y, tau sqrt(lam) e),  xt <- 2 x' - x,  x <- x'
+ * One product with D A E and one with its transpose per iteration, each fused with its
+ * proximal step; FP64 vectors.  b [sum m], d, e (NULL = identity) and x [sum n] are device
+ * FP64; x receives E xbar.  op_norm > 0 is used as ||D A E||_2, otherwise it is estimated
+ * (mfe_plan_op_norm, tol 1e-10, at most 1000 iterations).  trace (host, nullable) receives
+ * the objective every trace_every iterations (iters / trace_every values).  info: host,
+ * nullable.  EINVAL: NULL plan, b or x, lam <= 0, iters < 0, trace without trace_every > 0. */
+int mfe_plan_ccp_lasso(mfe_plan* plan, const double* b, const double* d, const double* e, double lam,
+                       double op_norm, int32_t iters, int32_t trace_every, double* trace, double* x,
+                       mfe_ccp_info* info, void* stream);
 
 /* ---- Section 6 variants (sparse plans) ------------------------------------------- */
 

@@ -43,6 +43,11 @@ class _Params(C.Structure):
                 ("batch", C.c_int32), ("u0", C.c_void_p), ("v0", C.c_void_p), ("stream", C.c_void_p)]
 
 
+class _CcpInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("norm_iters", C.c_int32), ("op_norm", C.c_double), ("tau", C.c_double),
+                ("sigma", C.c_double), ("objective", C.c_double)]
+
+
 class _LsqrInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("stop_reason", C.c_int32), ("rel_resid", C.c_double),
                 ("normal_eq", C.c_double)]
@@ -83,6 +88,8 @@ def _lib():
         "mfe_plan_warmstart": [vp, vp, u64, i32, vp, vp, dbl, dbl, i32, vp, vp, vp],
         "mfe_plan_set_tuning": [vp, i32, i32, i32],
         "mfe_plan_create_symmetric": [C.POINTER(_Matrix), i32, vp, C.POINTER(vp)],
+        "mfe_plan_op_norm": [vp, vp, vp, i32, dbl, C.POINTER(dbl), C.POINTER(i32), vp],
+        "mfe_plan_ccp_lasso": [vp, vp, vp, vp, dbl, dbl, i32, i32, vp, vp, C.POINTER(_CcpInfo), vp],
         "mfe_plan_set_targets": [vp, vp, vp, vp],
         "mfe_plan_set_blocks": [vp, vp, i64, vp, i64],
         "mfe_plan_sketch_features": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp],
@@ -447,6 +454,29 @@ class Plan:
                                          int(seed) & ((1 << 64) - 1), int(probes), ah, bh, float(gamma), float(M),
                                          int(bool(learned)), _ptr(u0), _ptr(v0), _stream(stream)))
         return u0, v0
+
+    def op_norm(self, d=None, e=None, max_iter=1000, tol=1e-10, stream=None):
+        """||D A E||_2 by power iteration (see mfe_plan_op_norm).  Returns (norm, iterations)."""
+        nrm, it = C.c_double(), C.c_int32()
+        _check(_lib().mfe_plan_op_norm(self._h, _ptr(d, torch.float64), _ptr(e, torch.float64), int(max_iter),
+                                       float(tol), C.byref(nrm), C.byref(it), _stream(stream)))
+        return nrm.value, it.value
+
+    def ccp_lasso(self, b, lam, d=None, e=None, iters=1000, op_norm=0.0, trace_every=0, stream=None,
+                  device="cuda"):
+        """CCP on the Lasso of Section 5.2 (see mfe_plan_ccp_lasso).  Returns (x, info, trace)."""
+        import numpy as np
+
+        x = torch.empty(self.N, dtype=torch.float64, device=device)
+        n_tr = int(iters) // int(trace_every) if trace_every > 0 else 0
+        tr = (C.c_double * max(n_tr, 1))() if trace_every > 0 else None
+        info = _CcpInfo()
+        _check(_lib().mfe_plan_ccp_lasso(self._h, _ptr(b, torch.float64), _ptr(d, torch.float64),
+                                         _ptr(e, torch.float64), float(lam), float(op_norm), int(iters),
+                                         int(trace_every), tr, _ptr(x), C.byref(info), _stream(stream)))
+        inf = dict(iters=info.iters, norm_iters=info.norm_iters, op_norm=info.op_norm, tau=info.tau,
+                   sigma=info.sigma, objective=info.objective)
+        return x, inf, (np.array(tr[:n_tr]) if tr is not None else np.zeros(0))
 
     def lsqr(self, b, d=None, e=None, tol=1e-6, max_iter=1000, check_every=10, stream=None, device="cuda"):
         x = torch.empty(self.N, dtype=torch.float64, device=device)

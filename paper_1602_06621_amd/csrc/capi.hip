@@ -262,6 +262,25 @@ int mfe_plan_warmstart(mfe_plan* plan, const float* params, uint64_t seed, int32
                         (hipStream_t)stream);
 }
 
+int mfe_plan_op_norm(mfe_plan* plan, const double* d, const double* e, int32_t max_iter, double tol, double* norm,
+                     int32_t* iters, void* stream) {
+  clear_error();
+  if (!plan || !norm) return set_error(MFE_EINVAL, "plan or norm is NULL");
+  if (max_iter < 1 || !(tol >= 0)) return set_error(MFE_EINVAL, "max_iter must be >= 1 and tol >= 0");
+  return plan_op_norm(plan, d, e, max_iter, tol, norm, iters, (hipStream_t)stream);
+}
+
+int mfe_plan_ccp_lasso(mfe_plan* plan, const double* b, const double* d, const double* e, double lam,
+                       double op_norm, int32_t iters, int32_t trace_every, double* trace, double* x,
+                       mfe_ccp_info* info, void* stream) {
+  clear_error();
+  if (!plan || !b || !x) return set_error(MFE_EINVAL, "plan, b or x is NULL");
+  if (!(lam > 0) || !std::isfinite(lam)) return set_error(MFE_EINVAL, "lambda must be positive and finite");
+  if (iters < 0) return set_error(MFE_EINVAL, "iters must be >= 0");
+  if (trace && trace_every <= 0) return set_error(MFE_EINVAL, "a trace needs trace_every > 0");
+  return plan_ccp_lasso(plan, b, d, e, lam, op_norm, iters, trace_every, trace, x, info, (hipStream_t)stream);
+}
+
 int mfe_plan_create_symmetric(const mfe_matrix* A, int32_t max_probes, void* stream, mfe_plan** out) {
   clear_error();
   return plan_build_symmetric(A, max_probes, (hipStream_t)stream, out);

@@ -702,4 +702,209 @@ int dense_f64_residual(const mfe_matrix* A, const double* d, const double* e, do
   return MFE_OK;
 }
 
+
+// ------------------------------------------- Chambolle-Cremers-Pock on the Lasso (Section 5.2)
+//
+// minimise ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1 by the first-order primal-dual
+// method with theta = 1 on Abar = D A E (x = E xbar): per iteration one product with Abar
+// and one with Abar', each fused with its proximal step (closed forms of the separable
+// functions; see mfe.h).  FP64 throughout; vectors in the plan's internal order.
+
+// Dual step over the rows: y <- (y + sigma D A gx - sigma d b) / (1 + sigma d^2 sqrt(lam)/2),
+// gy = d y (gathered by the primal step); gx = e xt in the columns' internal order.
+__global__ __launch_bounds__(kRed) void k_ccp_dual(SideDev S, const double* __restrict__ gx,
+                                                   const double* __restrict__ d, const double* __restrict__ b,
+                                                   double sigma, double half_sqrt_lam, double* __restrict__ y,
+                                                   double* __restrict__ gy) {
+  const int64_t r = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  if (r >= S.nint || S.orig[r] < 0) return;
+  const int64_t s = r >> 6;
+  const int lane = (int)(r & 63);
+  const int len = S.len[r];
+  const int2* e = S.ent + S.slice_off[s] + lane;
+  double acc = 0.0;
+  for (int q = 0; q < len; ++q) {
+    const int2 en = e[(int64_t)q * kSlice];
+    acc += (double)__int_as_float(en.y) * gx[en.x];
+  }
+  const double dr = d[r];
+  const double yn = (y[r] + sigma * (dr * acc) - sigma * dr * b[r]) / (1.0 + sigma * dr * dr * half_sqrt_lam);
+  y[r] = yn;
+  gy[r] = dr * yn;
+}
+
+// Primal step over the columns: u = x - tau e A' gy, x' = soft(u, tau sqrt(lam) e),
+// xt = x' + theta (x' - x), gx = e xt.
+__global__ __launch_bounds__(kRed) void k_ccp_primal(SideDev S, const double* __restrict__ gy,
+                                                     const double* __restrict__ e_sc, double tau, double thr,
+                                                     double theta, double* __restrict__ x, double* __restrict__ gx) {
+  const int64_t c = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  if (c >= S.nint || S.orig[c] < 0) return;
+  const int64_t s = c >> 6;
+  const int lane = (int)(c & 63);
+  const int len = S.len[c];
+  const int2* e = S.ent + S.slice_off[s] + lane;
+  double acc = 0.0;
+  for (int q = 0; q < len; ++q) {
+    const int2 en = e[(int64_t)q * kSlice];
+    acc += (double)__int_as_float(en.y) * gy[en.x];
+  }
+  const double ec = e_sc[c];
+  const double u = x[c] - tau * (ec * acc);
+  const double t = thr * ec;
+  const double xn = u > t ? u - t : (u < -t ? u + t : 0.0);
+  const double xt = xn + theta * (xn - x[c]);
+  x[c] = xn;
+  gx[c] = ec * xt;
+}
+
+// Block partials of sum_c |e_c x_c| (the l1 term of the objective at x = E xbar).
+__global__ __launch_bounds__(kRed) void k_l1_partial(int64_t n, const double* __restrict__ e_sc,
+                                                     const double* __restrict__ x, double* __restrict__ partial) {
+  const int64_t c = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  const double v = c < n ? fabs(e_sc[c] * x[c]) : 0.0;
+  const double bs = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+}
+
+__global__ void k_set1(double* p, double v) { *p = v; }
+
+__global__ void k_fill_valid(int64_t n, const int32_t* __restrict__ orig, double v, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = orig[i] >= 0 ? v : 0.0;
+}
+
+__global__ void k_scale_by(int64_t n, const double* __restrict__ nrm2, double* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double s = *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
+  if (i < n) v[i] *= s;
+}
+
+// ||D A E||_2 by power iteration on Abar' Abar from the normalised all-ones vector: each
+// iteration y = Abar v, z = Abar' y, estimate ||Abar v|| (the square root of the Rayleigh
+// quotient, a lower bound converging to the largest singular value), v = z / ||z||.  Stops
+// when the estimate changes by at most tol relative over 10 iterations, or at max_iter.
+int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t max_iter, double tol, double* norm,
+                int32_t* iters, hipStream_t st) {
+  const int64_t nr = ops.rows(), nc = ops.cols();
+  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks());
+  Work W;
+  double *v, *g, *y, *gy, *z, *part, *sq;
+  MFE_CHECK(W.alloc(&v, nc));
+  MFE_CHECK(W.alloc(&g, nc));
+  MFE_CHECK(W.alloc(&y, nr));
+  MFE_CHECK(W.alloc(&gy, nr));
+  MFE_CHECK(W.alloc(&z, nc));
+  MFE_CHECK(W.alloc(&part, pb));
+  MFE_CHECK(W.alloc(&sq, 2));
+  const unsigned cg = (unsigned)ceil_div(nc, 256);
+  k_fill_valid<<<cg, 256, 0, st>>>(nc, ops.col_valid(), 1.0, v);
+  k_mul<<<cg, 256, 0, st>>>(nc, v, v, z);
+  k_reduce<<<1, kRed, 0, st>>>(z, nc, sq + 1);
+  k_scale_by<<<cg, 256, 0, st>>>(nc, sq + 1, v);
+  double prev = -1.0, est = 0.0;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    k_mul<<<cg, 256, 0, st>>>(nc, ee, v, g);
+    ops.fwd(dd, g, nullptr, nullptr, nullptr, y, gy, part, st);  // y = D A E v, gy = D y
+    k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sq);    // ||Abar v||^2
+    ops.bwd(ee, gy, nullptr, nullptr, nullptr, z, nullptr, part, st);  // z = E A' D y
+    k_reduce<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sq + 1);
+    k_scale_by<<<cg, 256, 0, st>>>(nc, sq + 1, z);
+    std::swap(v, z);
+    MFE_HIP(hipGetLastError());
+    if (it % 10 == 0 || it == max_iter) {
+      double h[2];
+      MFE_HIP(hipMemcpyAsync(h, sq, sizeof h, hipMemcpyDeviceToHost, st));
+      MFE_HIP(hipStreamSynchronize(st));
+      est = std::sqrt(h[0]);
+      if (prev > 0 && std::fabs(est - prev) <= tol * est) break;
+      prev = est;
+    }
+  }
+  *norm = est;
+  if (iters) *iters = std::min(it, max_iter);
+  return MFE_OK;
+}
+
+int plan_op_norm(mfe_plan* p, const double* d, const double* e, int32_t max_iter, double tol, double* norm,
+                 int32_t* iters, hipStream_t st) {
+  MFE_CHECK(ensure_mats(p, st));
+  SellOps ops(p);
+  Work W;
+  double *dd, *ee;
+  MFE_CHECK(W.alloc(&dd, ops.rows()));
+  MFE_CHECK(W.alloc(&ee, ops.cols()));
+  ops.to_op(true, d, 1.0, 0, dd, st);
+  ops.to_op(false, e, 1.0, 0, ee, st);
+  return run_op_norm(ops, dd, ee, max_iter, tol, norm, iters, st);
+}
+
+int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* e, double lam, double op_norm,
+                   int32_t iters, int32_t trace_every, double* trace, double* x_out, mfe_ccp_info* info,
+                   hipStream_t st) {
+  MFE_CHECK(ensure_mats(p, st));
+  SellOps ops(p);
+  const int64_t nr = ops.rows(), nc = ops.cols();
+  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks()) + ceil_div(nc, kRed);
+  Work W;
+  double *bb, *dd, *ee, *y, *gy, *x, *gx, *res, *wx, *part, *obj, *neg1;
+  MFE_CHECK(W.alloc(&neg1, 1));
+  k_set1<<<1, 1, 0, st>>>(neg1, -1.0);
+  MFE_CHECK(W.alloc(&bb, nr));
+  MFE_CHECK(W.alloc(&dd, nr));
+  MFE_CHECK(W.alloc(&ee, nc));
+  MFE_CHECK(W.alloc(&y, nr));
+  MFE_CHECK(W.alloc(&gy, nr));
+  MFE_CHECK(W.alloc(&x, nc));
+  MFE_CHECK(W.alloc(&gx, nc));
+  MFE_CHECK(W.alloc(&res, nr));
+  MFE_CHECK(W.alloc(&wx, nc));
+  MFE_CHECK(W.alloc(&part, pb));
+  MFE_CHECK(W.alloc(&obj, 2));
+  ops.to_op(true, b, 0.0, 0, bb, st);
+  ops.to_op(true, d, 1.0, 0, dd, st);
+  ops.to_op(false, e, 1.0, 0, ee, st);
+  for (double* v : {y, gy}) MFE_HIP(hipMemsetAsync(v, 0, sizeof(double) * nr, st));
+  for (double* v : {x, gx}) MFE_HIP(hipMemsetAsync(v, 0, sizeof(double) * nc, st));
+  mfe_ccp_info inf{};
+  if (!(op_norm > 0)) {
+    MFE_CHECK(run_op_norm(ops, dd, ee, 1000, 1e-10, &op_norm, &inf.norm_iters, st));
+    if (!(op_norm > 0)) return set_error(MFE_EINVAL, "the scaled matrix is zero");
+  }
+  const double tau = 0.9 / op_norm, sigma = 0.9 / op_norm, sl = std::sqrt(lam);
+  const unsigned rg = (unsigned)ceil_div(nr, kRed), cg = (unsigned)ceil_div(nc, kRed);
+  // f(x) at x = E xbar: ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1
+  auto objective = [&](double* out) -> int {
+    k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, wx);
+    ops.fwd(nullptr, wx, nullptr, neg1, bb, res, nullptr, part, st);
+    k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), obj);
+    k_l1_partial<<<cg, kRed, 0, st>>>(nc, ee, x, part);
+    k_reduce<<<1, kRed, 0, st>>>(part, cg, obj + 1);
+    MFE_HIP(hipGetLastError());
+    double h[2];
+    MFE_HIP(hipMemcpyAsync(h, obj, sizeof h, hipMemcpyDeviceToHost, st));
+    MFE_HIP(hipStreamSynchronize(st));
+    *out = h[0] / sl + sl * h[1];
+    return MFE_OK;
+  };
+  int tr = 0;
+  for (int it = 1; it <= iters; ++it) {
+    k_ccp_dual<<<rg, kRed, 0, st>>>(ops.R, gx, dd, bb, sigma, 0.5 * sl, y, gy);
+    k_ccp_primal<<<cg, kRed, 0, st>>>(ops.C, gy, ee, tau, tau * sl, 1.0, x, gx);
+    MFE_HIP(hipGetLastError());
+    if (trace && trace_every > 0 && it % trace_every == 0) MFE_CHECK(objective(&trace[tr++]));
+  }
+  MFE_CHECK(objective(&inf.objective));
+  inf.iters = iters;
+  inf.op_norm = op_norm;
+  inf.tau = tau;
+  inf.sigma = sigma;
+  ops.from_op(false, x, ee, x_out, st);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  if (info) *info = inf;
+  return MFE_OK;
+}
+
 }  // namespace mfe

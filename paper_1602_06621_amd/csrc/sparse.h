@@ -231,6 +231,11 @@ int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, do
               int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t s);
 int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta,
                   double* rms, double* rms_nonempty, int64_t* n_empty, hipStream_t s);
+// Consumer of Section 5.2: CCP on the Lasso, and ||D A E||_2 by power iteration.
+int plan_op_norm(mfe_plan* p, const double* d, const double* e, int32_t max_iter, double tol, double* norm,
+                 int32_t* iters, hipStream_t s);
+int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* e, double lam, double op_norm,
+                   int32_t iters, int32_t trace_every, double* trace, double* x, mfe_ccp_info* info, hipStream_t s);
 // Section 6 variants.
 int plan_build_symmetric(const mfe_matrix* A, int32_t max_probes, hipStream_t s, mfe_plan** out);
 int plan_set_targets(mfe_plan* p, const double* row_target, const double* col_target, hipStream_t s);

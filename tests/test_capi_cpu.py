@@ -129,6 +129,18 @@ def test_variant_argument_checks(lib):
     assert lib.mfe_plan_create_symmetric(C.byref(s), 4, None, C.byref(h)) == -6
 
 
+def test_ccp_argument_checks(lib):
+    nrm, it = C.c_double(), C.c_int32()
+    assert lib.mfe_plan_op_norm(None, None, None, 10, 1e-6, C.byref(nrm), C.byref(it), None) == -1
+    assert lib.mfe_plan_ccp_lasso(None, None, None, None, 1.0, 0.0, 10, 0, None, None, None, None) == -1
+    fake = C.c_void_p(16)   # rejected before the plan is touched
+    buf = (C.c_double * 4)()
+    assert lib.mfe_plan_op_norm(fake, None, None, 0, 1e-6, C.byref(nrm), None, None) == -1
+    assert lib.mfe_plan_ccp_lasso(fake, buf, None, None, 0.0, 0.0, 10, 0, None, buf, None, None) == -1
+    assert lib.mfe_plan_ccp_lasso(fake, buf, None, None, 1.0, 0.0, -1, 0, None, buf, None, None) == -1
+    assert lib.mfe_plan_ccp_lasso(fake, buf, None, None, 1.0, 0.0, 10, 0, buf, buf, None, None) == -1
+
+
 def test_version(lib):
     assert "gfx950" in lib.mfe_version().decode()
 
