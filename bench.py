@@ -17,8 +17,11 @@ The other workloads of the build are measured under "extra" (same run, same GPU)
   lsqr  LSQR on the headline matrix to 1e-6 with (d, e), with (1, e) and without
   var   Section 6 variants: per-index targets and blocks (16 rows / 8 columns) on the
         headline matrix; Algorithm 2 on a symmetric 1,000,000 x 1,000,000 matrix
+  ccp   Section 5.2: CCP on the Lasso, 10,000 x 20,000 at 1% density, with D, E from 100
+        iterations of Algorithm 1 against none: iterations and seconds to a relative gap
+        of 1e-6, and the CCP iteration rate
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,c4,lsqr,var]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads c1,c0,c2,c3,c4,lsqr,var,ccp]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -344,6 +347,70 @@ def bench_variants(mfe, plan, csr, al, be):
     return res
 
 
+def ccp_algorithmic_bytes(m, n, nnz):
+    """One CCP iteration: two products (8 B per stored entry each); per row the dual
+    variable read and written, its scaled copy written and gathered once, d and b read
+    (48 B); per column the primal variable read and written, its scaled copy written and
+    gathered once, e read (40 B)."""
+    return 2 * nnz * 8 + 48 * m + 40 * n
+
+
+def bench_ccp(mfe):
+    """Section 5.2 at the paper's size: Lasso on a 10,000 x 20,000 matrix with 1% nonzeros
+    (N(0,1) entries, e^(N(1,1)) row and column scales), b = A x_hat + nu with n/10 nonzeros
+    in x_hat, lam = 1e-3 ||A' b||_inf; D, E from 100 iterations of Algorithm 1 (k = 1,
+    gamma = 0.1, M = ln 1e4); p* from 20,000 equilibrated CCP iterations."""
+    import numpy as np
+    import torch
+
+    from workloads import lasso_rhs, paper_sparse
+
+    csr = paper_sparse(10_000, 20_000, 0.01, 1006)
+    As = csr.to_scipy()
+    b_h, _ = lasso_rhs(As, 1007)
+    lam = 1e-3 * float(np.abs(As.T @ b_h).max())
+    f0 = float(b_h @ b_h) / np.sqrt(lam)
+    A = mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")
+    b = torch.tensor(b_h, device="cuda:0")
+    al, be = mfe.default_alpha_beta(csr.m, csr.n)
+    res = {"workload": "Lasso (Section 5.2) 1e4 x 2e4, 1% dense, D,E from 100 Algorithm-1 iterations",
+           "nnz": csr.nnz, "lambda": lam}
+    with mfe.Plan([A], max_probes=1) as plan:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eq = plan.equilibrate(al, be, GAMMA, float(np.log(1e4)), 100, 1, 2006)
+        torch.cuda.synchronize()
+        eq_s = time.perf_counter() - t0
+        d, e = eq["d"], eq["e"]
+        _, long_info, _ = plan.ccp_lasso(b, lam, d, e, iters=20000)
+        p_star = long_info["objective"]
+        for label, dd, ee in (("plain", None, None), ("equilibrated", d, e)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nrm, nit = plan.op_norm(dd, ee)
+            torch.cuda.synchronize()
+            norm_s = time.perf_counter() - t0
+            _, info, tr = plan.ccp_lasso(b, lam, dd, ee, iters=3000, op_norm=nrm, trace_every=10)
+            gap = (tr - p_star) / f0
+            hit = np.nonzero(gap <= 1e-6)[0]
+            iters = int(10 * (hit[0] + 1)) if hit.size else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.ccp_lasso(b, lam, dd, ee, iters=2000, op_norm=nrm)
+            torch.cuda.synchronize()
+            it_s = (time.perf_counter() - t0) / 2000
+            pre_s = norm_s + (eq_s if dd is not None else 0.0)
+            res[label] = {"iters_to_1e-6": iters, "op_norm": nrm, "norm_iters": nit,
+                          "us_per_iter": it_s * 1e6, "seconds_to_1e-6": None if iters is None else
+                          pre_s + iters * it_s, "setup_s": pre_s, "final_gap": float(gap[-1])}
+    by = ccp_algorithmic_bytes(csr.m, csr.n, csr.nnz)
+    it_s = res["plain"]["us_per_iter"] / 1e6
+    res.update({"p_star": p_star, "f0": f0, "equilibration_s": eq_s, "algorithmic_bytes_per_iter": by,
+                "algorithmic_gbs": by / it_s / 1e9, "hbm_frac": by / it_s / 1e9 / HBM_PEAK_GBS,
+                "paper": "about 1000 iterations without equilibration, over 4x fewer with 100 (its own matrix)"})
+    return res
+
+
 def profile_c3():
     """Counter run for the bf16 workload: 20 steps of config 3, then the calibration copy."""
     import numpy as np
@@ -416,6 +483,31 @@ def profile_var():
     print(json.dumps({"profile": "var done"}), flush=True)
 
 
+def profile_ccp():
+    """Timing run for CCP: the operator norm and 200 CCP iterations, plain and equilibrated
+    (D, E from 100 iterations of Algorithm 1), on the Section 5.2 workload."""
+    import numpy as np
+    import torch
+
+    from workloads import lasso_rhs, paper_sparse
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    csr = paper_sparse(10_000, 20_000, 0.01, 1006)
+    As = csr.to_scipy()
+    b_h, _ = lasso_rhs(As, 1007)
+    lam = 1e-3 * float(np.abs(As.T @ b_h).max())
+    b = torch.tensor(b_h, device="cuda:0")
+    al, be = mfe.default_alpha_beta(csr.m, csr.n)
+    with mfe.Plan([mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")],
+                  max_probes=1) as plan:
+        eq = plan.equilibrate(al, be, GAMMA, float(np.log(1e4)), 100, 1, 2006)
+        for dd, ee in ((None, None), (eq["d"], eq["e"])):
+            plan.ccp_lasso(b, lam, dd, ee, iters=200)
+        torch.cuda.synchronize()
+    print(json.dumps({"profile": "ccp done"}), flush=True)
+
+
 def calibration_copy():
     import torch
 
@@ -454,15 +546,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr,var")
+    ap.add_argument("--workloads", default="c1,c0,c2,c3,c4,lsqr,var,ccp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
-    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4", "var"],
+    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4", "var", "ccp"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
                          "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls; var: 20 steps "
-                         "of each Section 6 variant")
+                         "of each Section 6 variant; ccp: 200 CCP iterations plain and equilibrated")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -471,7 +563,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = set(args.workloads.split(","))
     if args.profile:
-        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4, "var": profile_var}[args.profile]()
+        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4, "var": profile_var,
+         "ccp": profile_ccp}[args.profile]()
         return
 
     import numpy as np
@@ -523,6 +616,9 @@ def main():
     if "var" in work:
         print("# measuring var", file=sys.stderr, flush=True)
         extra["var"] = bench_variants(mfe, plan, csr, al, be)
+    if "ccp" in work:
+        print("# measuring ccp", file=sys.stderr, flush=True)
+        extra["ccp"] = bench_ccp(mfe)
 
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:

@@ -105,7 +105,7 @@ typedef struct {
 
 typedef struct {
   int32_t iters;           /* CCP iterations run */
-  int32_t norm_iters;      /* power iterations spent on ||D A E||_2 (0 when it was given) */
+  int32_t norm_iters;      /* bidiagonalisation steps spent on ||D A E||_2 (0 when it was given) */
   double op_norm;          /* ||D A E||_2 used for the step sizes */
   double tau, sigma;       /* step sizes 0.9 / op_norm */
   double objective;        /* ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1 at the end */
@@ -282,12 +282,13 @@ int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mo
 
 /* ---- Chambolle-Cremers-Pock on the Lasso (Section 5.2), sparse plans ---------------- */
 
-/* ||D A E||_2 of the plan's matrix (block diagonal for a batched plan) by power iteration
- * on (DAE)'(DAE) from the normalised all-ones vector; the estimate is ||DAE v|| for the
- * current unit vector v (a lower bound), and the run stops when it changes by at most
- * tol (relative) over 10 iterations, or after max_iter iterations.  d [sum m], e [sum n]:
- * device FP64, NULL = identity.  norm, iters: host (iters nullable).
- * EINVAL: NULL plan or norm, max_iter < 1, tol < 0. */
+/* ||D A E||_2 of the plan's matrix (block diagonal for a batched plan) by Golub-Kahan
+ * bidiagonalisation (the Lanczos process LSQR uses, started from b = 1, one product with
+ * D A E and one with its transpose per step): the largest singular value of the i-step
+ * bidiagonal matrix is a lower bound that converges to the norm.  Checked every 5 steps;
+ * the run stops when it changes by at most tol (relative), when the process ends exactly,
+ * or after max_iter steps.  d [sum m], e [sum n]: device FP64, NULL = identity.  norm,
+ * iters: host (iters nullable).  EINVAL: NULL plan or norm, max_iter < 1, tol < 0. */
 int mfe_plan_op_norm(mfe_plan* plan, const double* d, const double* e, int32_t max_iter, double tol,
                      double* norm, int32_t* iters, void* stream);
 
@@ -299,7 +300,7 @@ int mfe_plan_op_norm(mfe_plan* plan, const double* d, const double* e, int32_t m
  * One product with D A E and one with its transpose per iteration, each fused with its
  * proximal step; FP64 vectors.  b [sum m], d, e (NULL = identity) and x [sum n] are device
  * FP64; x receives E xbar.  op_norm > 0 is used as ||D A E||_2, otherwise it is estimated
- * (mfe_plan_op_norm, tol 1e-10, at most 1000 iterations).  trace (host, nullable) receives
+ * (mfe_plan_op_norm, tol 1e-10, at most 1000 steps).  trace (host, nullable) receives
  * the objective every trace_every iterations (iters / trace_every values).  info: host,
  * nullable.  EINVAL: NULL plan, b or x, lam <= 0, iters < 0, trace without trace_every > 0. */
 int mfe_plan_ccp_lasso(mfe_plan* plan, const double* b, const double* d, const double* e, double lam,

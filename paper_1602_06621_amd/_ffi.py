@@ -456,7 +456,8 @@ class Plan:
         return u0, v0
 
     def op_norm(self, d=None, e=None, max_iter=1000, tol=1e-10, stream=None):
-        """||D A E||_2 by power iteration (see mfe_plan_op_norm).  Returns (norm, iterations)."""
+        """||D A E||_2 by Golub-Kahan bidiagonalisation (see mfe_plan_op_norm).  Returns
+        (norm, steps)."""
         nrm, it = C.c_double(), C.c_int32()
         _check(_lib().mfe_plan_op_norm(self._h, _ptr(d, torch.float64), _ptr(e, torch.float64), int(max_iter),
                                        float(tol), C.byref(nrm), C.byref(it), _stream(stream)))

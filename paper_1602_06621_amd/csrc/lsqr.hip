@@ -48,37 +48,70 @@ __device__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- sliced products
 //
-// y_r = sout_r * inv * sum_q a_q g[idx_q] + coef * yprev_r  over the rows r of one
-// direction of a plan (internal order); gout_r = sout_r * y_r when requested; block
-// partial of sum y_r^2.  inv and coef are read from device memory (nullable = 1, 0).
-__global__ __launch_bounds__(kRed) void k_sell_product(SideDev S, const double* __restrict__ sout,
-                                                       const double* __restrict__ g, const double* inv,
-                                                       const double* coef, const double* __restrict__ yprev,
-                                                       double* __restrict__ y, double* __restrict__ gout,
-                                                       double* __restrict__ partial) {
-  const int64_t r = (int64_t)blockIdx.x * kRed + threadIdx.x;
-  double contrib = 0.0;
-  if (r < S.nint) {
-    const int64_t s = r >> 6;
-    const int lane = (int)(r & 63);
-    const int len = S.len[r];
-    const int2* e = S.ent + S.slice_off[s] + lane;
-    double acc = 0.0;
-    for (int q = 0; q < len; ++q) {
-      const int2 en = e[(int64_t)q * kSlice];
-      acc += (double)__int_as_float(en.y) * g[en.x];
-    }
-    if (S.orig[r] >= 0) {
-      const double so = sout ? sout[r] : 1.0;
-      double v = so * (acc * (inv ? *inv : 1.0));
-      if (coef) v += *coef * yprev[r];
-      y[r] = v;
-      if (gout) gout[r] = so * v;
-      contrib = v * v;
-    }
+// A workgroup of P wavefronts takes one slice (64 rows): wavefront w walks the slots
+// [w c, (w+1) c) of every row of the slice (c = ceil(width / P)), and wavefront 0 adds
+// the P partial sums in order.  P = 1 (plans with many slices) is one sequential sum per
+// row; long rows in few slices (the Lasso of Section 5.2: 10,000 rows of ~200 entries)
+// get P up to 16, so that thousands of wavefronts share the work instead of 157.
+constexpr int kMaxSplit = 16;
+
+// Row sums sum_q a_q g[idx_q] of slice s, returned in wavefront 0 (0 elsewhere).  Every
+// thread of the workgroup must call it (it has a barrier when P > 1).
+__device__ double slice_row_sum(const SideDev& S, const double* __restrict__ g, int64_t s, int P) {
+  __shared__ double part[kMaxSplit][kSlice];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int64_t base = S.slice_off[s];
+  const int len = S.len[s * kSlice + lane];
+  const int width = (int)((S.slice_off[s + 1] - base) / kSlice);
+  const int chunk = (width + P - 1) / P;
+  const int q0 = w * chunk, q1 = min(len, q0 + chunk);
+  const int2* e = S.ent + base + lane;
+  double acc = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    const int2 en = e[(int64_t)q * kSlice];
+    acc += (double)__int_as_float(en.y) * g[en.x];
   }
-  const double bs = block_sum(contrib);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (P == 1) return acc;
+  part[w][lane] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  if (w == 0)
+    for (int i = 0; i < P; ++i) tot += part[i][lane];
+  return tot;
+}
+
+// Wavefronts per slice for a direction with `nslices` slices: enough workgroups to
+// give the device about 4096 wavefronts, at most kMaxSplit per slice.
+inline int slice_split(int64_t nslices) {
+  const int64_t p = nslices > 0 ? ceil_div(4096, nslices) : 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, p));
+}
+
+// y_r = sout_r * inv * sum_q a_q g[idx_q] + coef * yprev_r  over the rows r of one
+// direction of a plan (internal order); gout_r = sout_r * y_r when requested; one
+// partial of sum y_r^2 per slice.  inv and coef are read from device memory (nullable =
+// 1, 0).  Grid: one workgroup of 64 P threads per slice.
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_sell_product(SideDev S, int P, const double* __restrict__ sout,
+                                                                     const double* __restrict__ g, const double* inv,
+                                                                     const double* coef,
+                                                                     const double* __restrict__ yprev,
+                                                                     double* __restrict__ y, double* __restrict__ gout,
+                                                                     double* __restrict__ partial) {
+  const int64_t s = blockIdx.x;
+  const double acc = slice_row_sum(S, g, s, P);
+  if (threadIdx.x >= kSlice) return;
+  const int64_t r = s * kSlice + threadIdx.x;
+  double contrib = 0.0;
+  if (S.orig[r] >= 0) {
+    const double so = sout ? sout[r] : 1.0;
+    double v = so * (acc * (inv ? *inv : 1.0));
+    if (coef) v += *coef * yprev[r];
+    y[r] = v;
+    if (gout) gout[r] = so * v;
+    contrib = v * v;
+  }
+  const double ws = wave_sum(contrib);
+  if (threadIdx.x == 0) partial[s] = ws;
 }
 
 // RMS-residual pass over one direction: s_r = sum_q a_q^2 g2[idx_q] (g2 = squared scales
@@ -389,18 +422,23 @@ struct SellOps : Ops {
     C.ent = p->cols.ent;
     C.nint = p->cols.nint;
     C.is_row = 0;
+    PR = slice_split(p->rows.nslices);
+    PC = slice_split(p->cols.nslices);
   }
   int64_t rows() const override { return p->rows.nint; }
   int64_t cols() const override { return p->cols.nint; }
-  int64_t fwd_blocks() const override { return ceil_div(p->rows.nint, kRed); }
-  int64_t bwd_blocks() const override { return ceil_div(p->cols.nint, kRed); }
+  int PR = 1, PC = 1;  // wavefronts per slice of each direction
+  int64_t fwd_blocks() const override { return p->rows.nslices; }
+  int64_t bwd_blocks() const override { return p->cols.nslices; }
   void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
            double* gout, double* partial, hipStream_t st) const override {
-    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kRed), 0, st>>>(R, sout, g, inv, coef, yprev, y, gout, partial);
+    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kSlice * PR), 0, st>>>(R, PR, sout, g, inv, coef, yprev, y,
+                                                                                gout, partial);
   }
   void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
            double* gout, double* partial, hipStream_t st) const override {
-    k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kRed), 0, st>>>(C, sout, g, inv, coef, yprev, y, gout, partial);
+    k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kSlice * PC), 0, st>>>(C, PC, sout, g, inv, coef, yprev, y,
+                                                                                gout, partial);
   }
   void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const override {
     const SideDev& S = row ? R : C;
@@ -712,21 +750,17 @@ int dense_f64_residual(const mfe_matrix* A, const double* d, const double* e, do
 
 // Dual step over the rows: y <- (y + sigma D A gx - sigma d b) / (1 + sigma d^2 sqrt(lam)/2),
 // gy = d y (gathered by the primal step); gx = e xt in the columns' internal order.
-__global__ __launch_bounds__(kRed) void k_ccp_dual(SideDev S, const double* __restrict__ gx,
-                                                   const double* __restrict__ d, const double* __restrict__ b,
-                                                   double sigma, double half_sqrt_lam, double* __restrict__ y,
-                                                   double* __restrict__ gy) {
-  const int64_t r = (int64_t)blockIdx.x * kRed + threadIdx.x;
-  if (r >= S.nint || S.orig[r] < 0) return;
-  const int64_t s = r >> 6;
-  const int lane = (int)(r & 63);
-  const int len = S.len[r];
-  const int2* e = S.ent + S.slice_off[s] + lane;
-  double acc = 0.0;
-  for (int q = 0; q < len; ++q) {
-    const int2 en = e[(int64_t)q * kSlice];
-    acc += (double)__int_as_float(en.y) * gx[en.x];
-  }
+// One workgroup of 64 P threads per slice (see slice_row_sum).
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_dual(SideDev S, int P, const double* __restrict__ gx,
+                                                                 const double* __restrict__ d,
+                                                                 const double* __restrict__ b, double sigma,
+                                                                 double half_sqrt_lam, double* __restrict__ y,
+                                                                 double* __restrict__ gy) {
+  const int64_t s = blockIdx.x;
+  const double acc = slice_row_sum(S, gx, s, P);
+  if (threadIdx.x >= kSlice) return;
+  const int64_t r = s * kSlice + threadIdx.x;
+  if (S.orig[r] < 0) return;
   const double dr = d[r];
   const double yn = (y[r] + sigma * (dr * acc) - sigma * dr * b[r]) / (1.0 + sigma * dr * dr * half_sqrt_lam);
   y[r] = yn;
@@ -735,20 +769,15 @@ __global__ __launch_bounds__(kRed) void k_ccp_dual(SideDev S, const double* __re
 
 // Primal step over the columns: u = x - tau e A' gy, x' = soft(u, tau sqrt(lam) e),
 // xt = x' + theta (x' - x), gx = e xt.
-__global__ __launch_bounds__(kRed) void k_ccp_primal(SideDev S, const double* __restrict__ gy,
-                                                     const double* __restrict__ e_sc, double tau, double thr,
-                                                     double theta, double* __restrict__ x, double* __restrict__ gx) {
-  const int64_t c = (int64_t)blockIdx.x * kRed + threadIdx.x;
-  if (c >= S.nint || S.orig[c] < 0) return;
-  const int64_t s = c >> 6;
-  const int lane = (int)(c & 63);
-  const int len = S.len[c];
-  const int2* e = S.ent + S.slice_off[s] + lane;
-  double acc = 0.0;
-  for (int q = 0; q < len; ++q) {
-    const int2 en = e[(int64_t)q * kSlice];
-    acc += (double)__int_as_float(en.y) * gy[en.x];
-  }
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_primal(SideDev S, int P, const double* __restrict__ gy,
+                                                                   const double* __restrict__ e_sc, double tau,
+                                                                   double thr, double theta, double* __restrict__ x,
+                                                                   double* __restrict__ gx) {
+  const int64_t s = blockIdx.x;
+  const double acc = slice_row_sum(S, gy, s, P);
+  if (threadIdx.x >= kSlice) return;
+  const int64_t c = s * kSlice + threadIdx.x;
+  if (S.orig[c] < 0) return;
   const double ec = e_sc[c];
   const double u = x[c] - tau * (ec * acc);
   const double t = thr * ec;
@@ -774,53 +803,117 @@ __global__ void k_fill_valid(int64_t n, const int32_t* __restrict__ orig, double
   if (i < n) out[i] = orig[i] >= 0 ? v : 0.0;
 }
 
-__global__ void k_scale_by(int64_t n, const double* __restrict__ nrm2, double* __restrict__ v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double s = *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
-  if (i < n) v[i] *= s;
+// hist[2 it] = beta, hist[2 it + 1] = alpha of the current bidiagonalisation step.
+__global__ void k_record(const LsqrScal* __restrict__ sc, double* __restrict__ hist, int it) {
+  hist[2 * it] = sc->beta;
+  hist[2 * it + 1] = sc->alpha;
 }
 
-// ||D A E||_2 by power iteration on Abar' Abar from the normalised all-ones vector: each
-// iteration y = Abar v, z = Abar' y, estimate ||Abar v|| (the square root of the Rayleigh
-// quotient, a lower bound converging to the largest singular value), v = z / ||z||.  Stops
-// when the estimate changes by at most tol relative over 10 iterations, or at max_iter.
+// Largest eigenvalue of the symmetric tridiagonal matrix (diag, off) by bisection on the
+// Sturm count (the number of negative pivots of T - x I = L D L').
+double tridiag_max_eig(const std::vector<double>& dg, const std::vector<double>& off) {
+  const size_t k = dg.size();
+  double lo = 0.0, hi = 0.0;
+  for (size_t j = 0; j < k; ++j) {
+    const double r = (j > 0 ? std::fabs(off[j - 1]) : 0.0) + (j + 1 < k ? std::fabs(off[j]) : 0.0);
+    hi = std::max(hi, dg[j] + r);
+    lo = std::min(lo, dg[j] - r);
+  }
+  auto count_above = [&](double x) {  // eigenvalues > x
+    int neg = 0;
+    double dpiv = 1.0;
+    for (size_t j = 0; j < k; ++j) {
+      const double o2 = j > 0 ? off[j - 1] * off[j - 1] : 0.0;
+      dpiv = (dg[j] - x) - (j > 0 ? o2 / dpiv : 0.0);
+      if (dpiv == 0.0) dpiv = -1e-300;
+      if (dpiv < 0.0) ++neg;
+    }
+    return (int)k - neg;
+  };
+  for (int i = 0; i < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_above(mid) >= 1) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
+// ||D A E||_2 by Golub-Kahan bidiagonalisation (the Lanczos process of LSQR, started
+// from b = 1): after i steps the lower bidiagonal B_i (alpha_1..alpha_i on the diagonal,
+// beta_2..beta_{i+1} below it) has largest singular value at most ||D A E||_2 and
+// converging to it; it is the square root of the largest eigenvalue of the tridiagonal
+// B_i' B_i, found by bisection.  Checked every 5 steps; stops when it changes by at most
+// tol (relative), when the process ends exactly (alpha or beta = 0), or at max_iter.
 int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t max_iter, double tol, double* norm,
                 int32_t* iters, hipStream_t st) {
   const int64_t nr = ops.rows(), nc = ops.cols();
   const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks());
   Work W;
-  double *v, *g, *y, *gy, *z, *part, *sq;
+  double *bb, *u, *du, *v, *w, *x, *ev, *res, *part, *hist;
+  LsqrScal* sc;
+  MFE_CHECK(W.alloc(&bb, nr));
+  MFE_CHECK(W.alloc(&u, nr));
+  MFE_CHECK(W.alloc(&du, nr));
+  MFE_CHECK(W.alloc(&res, nr));
   MFE_CHECK(W.alloc(&v, nc));
-  MFE_CHECK(W.alloc(&g, nc));
-  MFE_CHECK(W.alloc(&y, nr));
-  MFE_CHECK(W.alloc(&gy, nr));
-  MFE_CHECK(W.alloc(&z, nc));
+  MFE_CHECK(W.alloc(&w, nc));
+  MFE_CHECK(W.alloc(&x, nc));
+  MFE_CHECK(W.alloc(&ev, nc));
   MFE_CHECK(W.alloc(&part, pb));
-  MFE_CHECK(W.alloc(&sq, 2));
-  const unsigned cg = (unsigned)ceil_div(nc, 256);
-  k_fill_valid<<<cg, 256, 0, st>>>(nc, ops.col_valid(), 1.0, v);
-  k_mul<<<cg, 256, 0, st>>>(nc, v, v, z);
-  k_reduce<<<1, kRed, 0, st>>>(z, nc, sq + 1);
-  k_scale_by<<<cg, 256, 0, st>>>(nc, sq + 1, v);
-  double prev = -1.0, est = 0.0;
+  MFE_CHECK(W.alloc(&hist, 2 * ((int64_t)max_iter + 1)));
+  MFE_CHECK(W.alloc(&sc, 1));
+  for (double* z : {v, w, x, ev}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nc, st));
+  const unsigned row_grid = (unsigned)ceil_div(nr, 256), upd_grid = (unsigned)ceil_div(nc + nr, 256);
+  k_fill_valid<<<row_grid, 256, 0, st>>>(nr, ops.R.orig, 1.0, bb);
+  k_scal_init<<<1, 1, 0, st>>>(sc);
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);  // beta_1 u_1 = D 1
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);
+  k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
+  k_reduce<<<1, kRed, 0, st>>>(res, nr, part);
+  k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
+  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);  // alpha_1 v_1 = Abar' u_1
+  k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
+  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
+  k_record<<<1, 1, 0, st>>>(sc, hist, 0);
+  MFE_HIP(hipGetLastError());
+  std::vector<double> h;
+  double est = 0.0, prev = -1.0;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    k_mul<<<cg, 256, 0, st>>>(nc, ee, v, g);
-    ops.fwd(dd, g, nullptr, nullptr, nullptr, y, gy, part, st);  // y = D A E v, gy = D y
-    k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sq);    // ||Abar v||^2
-    ops.bwd(ee, gy, nullptr, nullptr, nullptr, z, nullptr, part, st);  // z = E A' D y
-    k_reduce<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sq + 1);
-    k_scale_by<<<cg, 256, 0, st>>>(nc, sq + 1, z);
-    std::swap(v, z);
+    k_scal_iter<<<1, 1, 0, st>>>(sc, it);
+    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);  // beta u = Abar v - alpha u
+    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc);
+    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);  // alpha v = Abar' u - beta v
+    k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
+    k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+    k_record<<<1, 1, 0, st>>>(sc, hist, it);
     MFE_HIP(hipGetLastError());
-    if (it % 10 == 0 || it == max_iter) {
-      double h[2];
-      MFE_HIP(hipMemcpyAsync(h, sq, sizeof h, hipMemcpyDeviceToHost, st));
-      MFE_HIP(hipStreamSynchronize(st));
-      est = std::sqrt(h[0]);
-      if (prev > 0 && std::fabs(est - prev) <= tol * est) break;
-      prev = est;
+    if (it % 5 != 0 && it != max_iter) continue;
+    h.resize(2 * (size_t)(it + 1));
+    MFE_HIP(hipMemcpyAsync(h.data(), hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    MFE_HIP(hipStreamSynchronize(st));
+    // columns j = 1..i of B_i: alpha_j = h[2(j-1)+1], beta_{j+1} = h[2j]
+    std::vector<double> dg, off;
+    bool ended = false;
+    for (int j = 1; j <= it; ++j) {
+      const double a = h[2 * (j - 1) + 1], bnext = h[2 * j];
+      if (!(a > 0.0)) {
+        ended = true;
+        break;
+      }
+      dg.push_back(a * a + bnext * bnext);
+      const double anext = h[2 * j + 1];
+      if (j < it) off.push_back(anext * bnext);
+      if (!(bnext > 0.0)) {
+        ended = true;
+        break;
+      }
     }
+    if (dg.empty()) break;
+    off.resize(dg.size() - 1);
+    est = std::sqrt(tridiag_max_eig(dg, off));
+    if (ended || (prev > 0.0 && std::fabs(est - prev) <= tol * est)) break;
+    prev = est;
   }
   *norm = est;
   if (iters) *iters = std::min(it, max_iter);
@@ -873,7 +966,7 @@ int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* 
     if (!(op_norm > 0)) return set_error(MFE_EINVAL, "the scaled matrix is zero");
   }
   const double tau = 0.9 / op_norm, sigma = 0.9 / op_norm, sl = std::sqrt(lam);
-  const unsigned rg = (unsigned)ceil_div(nr, kRed), cg = (unsigned)ceil_div(nc, kRed);
+  const unsigned cg = (unsigned)ceil_div(nc, kRed);
   // f(x) at x = E xbar: ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1
   auto objective = [&](double* out) -> int {
     k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, wx);
@@ -890,8 +983,10 @@ int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* 
   };
   int tr = 0;
   for (int it = 1; it <= iters; ++it) {
-    k_ccp_dual<<<rg, kRed, 0, st>>>(ops.R, gx, dd, bb, sigma, 0.5 * sl, y, gy);
-    k_ccp_primal<<<cg, kRed, 0, st>>>(ops.C, gy, ee, tau, tau * sl, 1.0, x, gx);
+    k_ccp_dual<<<dim3((unsigned)ops.fwd_blocks()), dim3(kSlice * ops.PR), 0, st>>>(ops.R, ops.PR, gx, dd, bb, sigma,
+                                                                                   0.5 * sl, y, gy);
+    k_ccp_primal<<<dim3((unsigned)ops.bwd_blocks()), dim3(kSlice * ops.PC), 0, st>>>(ops.C, ops.PC, gy, ee, tau,
+                                                                                     tau * sl, 1.0, x, gx);
     MFE_HIP(hipGetLastError());
     if (trace && trace_every > 0 && it % trace_every == 0) MFE_CHECK(objective(&trace[tr++]));
   }

@@ -1,5 +1,5 @@
-"""GPU parity of the CCP consumer (Section 5.2): ||D A E||_2 by power iteration against the
-SVD, CCP iterates against the FP64 oracle step for step (same step sizes), the limit
+"""GPU parity of the CCP consumer (Section 5.2): ||D A E||_2 by bidiagonalisation against
+the SVD, CCP iterates against the FP64 oracle step for step (same step sizes), the limit
 against the Lasso optimum, and the effect of equilibration on the iteration count.
 
 CCP is a non-expansive iteration: rounding differences between the two implementations
@@ -52,7 +52,7 @@ def test_op_norm_matches_svd(equilibrated):
         nrm, it = plan.op_norm(_dev(d), _dev(e), max_iter=5000, tol=1e-13)
     _say("norm", nrm, ref, "iterations", it)
     assert abs(nrm - ref) <= 1e-8 * ref
-    assert nrm <= ref * (1 + 1e-12)   # a Rayleigh-quotient estimate never exceeds the norm
+    assert nrm <= ref * (1 + 1e-12)   # a Ritz value never exceeds the norm
 
 
 @pytest.mark.parametrize("equilibrated", [False, True])
@@ -78,7 +78,7 @@ def test_ccp_iterates_match_oracle(equilibrated):
 
 
 def test_ccp_reaches_lasso_optimum():
-    """With the power-iteration norm, 4000 equilibrated iterations reach the optimum of
+    """With the estimated norm, 4000 equilibrated iterations reach the optimum of
     scikit-learn's coordinate descent (same objective rescaled) to 1e-9 relative."""
     from sklearn.linear_model import Lasso
 
