@@ -130,6 +130,7 @@ struct PhaseArgs {
   StepScalars sc;
   int64_t side_blocks, gen_blocks;
   int* flag;                  // bit 0: non-finite value seen; bit 1: warm start outside the box
+  int32_t split;              // wavefronts per slice wanted for the direction (1: one lane per row)
 };
 
 struct mfe_plan_impl;

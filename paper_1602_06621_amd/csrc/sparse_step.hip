@@ -110,10 +110,85 @@ __device__ __forceinline__ void st_stream(Desc* p, Desc v) {
   st_stream(reinterpret_cast<u64x2*>(p), w);
 }
 
-// part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries [0, len_lo) to the
-// partial sums; 2 partial sums plus entries [len_lo, len), then the update.
-// VAR (the Section 6 variant kernel): per-index targets, or the estimate z written out
-// for the block update instead of the update itself.
+// Sums of the signed products of slots [q_beg, q_end) of one row into acc.  Batches of
+// NB slots: all entry loads of a batch are issued, then all descriptor gathers, then the
+// accumulation, so a wavefront keeps 2 x NB independent memory requests in flight
+// instead of one dependent load/gather pair per slot.
+template <int KP, bool PACKED, int NB>
+__device__ __forceinline__ void gather_rows(const long long* __restrict__ e,
+                                            const typename Codec<KP, PACKED>::T* __restrict__ gather, int q_beg,
+                                            int q_end, double (&acc)[KP]) {
+  using C = Codec<KP, PACKED>;
+  using DT = typename C::T;
+  for (int q0 = q_beg; q0 < q_end; q0 += NB) {
+    long long en[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      en[u] = (q0 + u < q_end) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
+    DT d[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (q0 + u < q_end) d[u] = gather[(int32_t)(en[u] & 0xFFFFFFFFll)];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      if (q0 + u < q_end) {
+        double scale;
+        uint64_t bits;
+        C::decode(d[u], scale, bits);
+        const float a = __int_as_float((int32_t)(en[u] >> 32));
+        accumulate<KP>(acc, (double)a * scale, bits);
+      }
+    }
+  }
+}
+
+// Update of internal index r from its k probe sums (a5-a7 and the next descriptor).
+// VAR (the Section 6 variant kernel): per-index target, or the estimate z written out for
+// the block update instead of the update itself.
+template <int KP, bool PACKED, bool VAR>
+__device__ __forceinline__ void finish_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
+                                              const StepScalars& sc, int64_t r, int32_t li, int32_t mi,
+                                              double x_old, double xbar_old, double tgt_r, const double (&acc)[KP],
+                                              int* flag) {
+  // Every product and sum of the update is rounded on its own (no fused multiply-add),
+  // as in the plain definition, so that all kernels that finish an update agree bit
+  // for bit.
+#pragma clang fp contract(off)
+  using C = Codec<KP, PACKED>;
+  using DT = typename C::T;
+  const MatDev mt = mats[mi];
+  double ss = 0.0;
+#pragma unroll
+  for (int p = 0; p < KP; ++p)
+    if (p < k) ss += acc[p] * acc[p];
+  const double z = exp(2.0 * x_old) * (ss / (double)k);
+  double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
+  if constexpr (VAR) {
+    if (S.zout) {  // block side: the estimate goes to the block update
+      if (!isfinite(z)) atomicOr(flag, 1);
+      st_stream(S.zout + r, z);
+      return;
+    }
+    if (S.tgt) tgt = tgt_r;
+  }
+  const double g = (z - tgt) + sc.gamma * x_old;
+  double xn = x_old - sc.eta * g;
+  xn = fmin(fmax(xn, -sc.M), sc.M);
+  const bool bad = !isfinite(z) || !isfinite(xn);
+  if (bad) {
+    atomicOr(flag, 1);
+    xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
+  }
+  st_stream(S.x + r, xn);
+  st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
+  const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
+  st_stream(reinterpret_cast<DT*>(S.out) + r,
+            C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
+}
+
+// One lane per row.  part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries
+// [0, len_lo) to the partial sums; 2 partial sums plus entries [len_lo, len), then the
+// update.
 template <int KP, bool PACKED, int NB, bool VAR = false>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
@@ -146,29 +221,7 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   double acc[KP];
 #pragma unroll
   for (int p = 0; p < KP; ++p) acc[p] = (mode == 2 && p < k) ? ld_stream(S.part + (int64_t)p * S.nint + r) : 0.0;
-  // Batches of NB slots: all entry loads of a batch are issued, then all descriptor
-  // gathers, then the accumulation, so a wavefront keeps 2 x NB independent memory
-  // requests in flight instead of one dependent load/gather pair per slot.
-  for (int q0 = q_beg; q0 < q_end; q0 += NB) {
-    long long en[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u)
-      en[u] = (q0 + u < q_end) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
-    DT d[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u)
-      if (q0 + u < q_end) d[u] = gather[(int32_t)(en[u] & 0xFFFFFFFFll)];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      if (q0 + u < q_end) {
-        double scale;
-        uint64_t bits;
-        C::decode(d[u], scale, bits);
-        const float a = __int_as_float((int32_t)(en[u] >> 32));
-        accumulate<KP>(acc, (double)a * scale, bits);
-      }
-    }
-  }
+  gather_rows<KP, PACKED, NB>(e, gather, q_beg, q_end, acc);
   if (partial_out) {
 #pragma unroll
     for (int p = 0; p < KP; ++p)
@@ -176,44 +229,67 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
     return;
   }
   if (li < 0) return;
-  {
-    // Every product and sum of the update is rounded on its own (no fused multiply-add),
-    // as in the plain definition, so that all kernels that finish an update agree bit
-    // for bit.
-#pragma clang fp contract(off)
-    const MatDev mt = mats[mi];
-    double ss = 0.0;
-#pragma unroll
-    for (int p = 0; p < KP; ++p)
-      if (p < k) ss += acc[p] * acc[p];
-    const double z = exp(2.0 * x_old) * (ss / (double)k);
-    double tgt = S.is_row ? mt.tgt_row : mt.tgt_col;
-    if constexpr (VAR) {
-      if (S.zout) {  // block side: the estimate goes to the block update
-        if (!isfinite(z)) atomicOr(flag, 1);
-        st_stream(S.zout + r, z);
-        return;
-      }
-      if (S.tgt) tgt = tgt_r;
-    }
-    const double g = (z - tgt) + sc.gamma * x_old;
-    double xn = x_old - sc.eta * g;
-    xn = fmin(fmax(xn, -sc.M), sc.M);
-    const bool bad = !isfinite(z) || !isfinite(xn);
-    if (bad) {
-      atomicOr(flag, 1);
-      xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
-    }
-    st_stream(S.x + r, xn);
-    st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
-    const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
-    st_stream(reinterpret_cast<DT*>(S.out) + r,
-              C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
-  }
+  finish_update<KP, PACKED, VAR>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
 }
 
-__device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk) {
-  const int64_t c = gblk * kBlock + threadIdx.x;
+// Long rows in few slices: a workgroup of P wavefronts per slice, wavefront w walking
+// the slots [w c, (w+1) c) of every row of the slice (c = ceil(width / P)); wavefront 0
+// adds the P partial sums in order through LDS and finishes the update.  P is at most
+// split_max<KP>() so that the partial sums fit in 64 KB of LDS.
+template <int KP>
+constexpr int split_max() {
+  return 1 + 65536 / (KP * kSlice * 8) < 16 ? 1 + 65536 / (KP * kSlice * 8) : 16;
+}
+
+template <int KP, bool PACKED, bool VAR>
+__device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev* __restrict__ mats, int k,
+                                                  const StepScalars& sc, int64_t s, int P, int* flag) {
+  using C = Codec<KP, PACKED>;
+  using DT = typename C::T;
+  constexpr int PM = split_max<KP>();
+  __shared__ double part[(PM > 1 ? PM - 1 : 1) * KP * kSlice];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int64_t r = s * kSlice + lane;
+  const int len = ld_stream(S.len + r);
+  int32_t li = 0, mi = 0;
+  double x_old = 0.0, xbar_old = 0.0, tgt_r = 0.0;
+  if (w == 0) {
+    li = ld_stream(S.orig + r);
+    x_old = ld_stream(S.x + r);
+    if (!VAR || !S.zout) xbar_old = ld_stream(S.xbar + r);
+    mi = S.slice_mat[s];
+    if constexpr (VAR) {
+      if (S.tgt) tgt_r = ld_stream(S.tgt + r);
+    }
+  }
+  const int64_t base = S.slice_off[s];
+  const int width = (int)((S.slice_off[s + 1] - base) / kSlice);
+  const int chunk = (width + P - 1) / P;
+  const int q0 = min(len, w * chunk), q1 = min(len, w * chunk + chunk);
+  const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + base + lane);
+  const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
+  double acc[KP];
+#pragma unroll
+  for (int p = 0; p < KP; ++p) acc[p] = 0.0;
+  gather_rows<KP, PACKED, 8>(e, gather, q0, q1, acc);
+  if (w > 0) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p)
+      if (p < k) part[((w - 1) * KP + p) * kSlice + lane] = acc[p];
+  }
+  __syncthreads();
+  if (w != 0) return;
+  for (int i = 1; i < P; ++i) {
+#pragma unroll
+    for (int p = 0; p < KP; ++p)
+      if (p < k) acc[p] += part[((i - 1) * KP + p) * kSlice + lane];
+  }
+  if (li < 0) return;
+  finish_update<KP, PACKED, VAR>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
+}
+
+__device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk, int64_t bsize = kBlock) {
+  const int64_t c = gblk * bsize + threadIdx.x;
   if (c >= g.nblocks) return;
   int lo = 0, hi = g.nseg - 1;
   while (lo < hi) {
@@ -249,6 +325,15 @@ __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
+
+// One slice per workgroup of 64 P threads (side_update_split); workgroups past
+// side_blocks (= slices) draw the sign words of step t+2, 64 P Philox blocks each.
+template <int KP, bool PACKED, bool VAR>
+__global__ __launch_bounds__(kSlice * split_max<KP>()) void k_phase_split(PhaseArgs a, int P) {
+  const int64_t b = blockIdx.x;
+  if (b < a.side_blocks) side_update_split<KP, PACKED, VAR>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
+  else signgen_block(a.gen, b - a.side_blocks, (int64_t)blockDim.x);
+}
 
 // Lane groups of the block kernels: G lanes (a power of two, 1..64, chosen from the
 // mean block size) share one block; the wavefront holds 64 / G blocks.  group_sum adds
@@ -509,7 +594,16 @@ void dispatch(int k, bool packed, Args&&... args) {
 template <int KP, bool PACKED>
 struct PhaseLauncher {
   static void run(const PhaseArgs& a, int nb, hipStream_t st) {
-    if (a.side.tgt || a.side.zout) {
+    const int P = std::min(a.split, split_max<KP>());
+    if (a.side.part_mode == 0 && P > 1) {
+      // few slices: one workgroup of P wavefronts per slice (grid in slices, not rows)
+      PhaseArgs b = a;
+      b.side_blocks = a.side.nint / kSlice;
+      b.gen_blocks = a.gen_blocks > 0 ? ceil_div(a.gen.nblocks, (int64_t)kSlice * P) : 0;
+      const dim3 grid((unsigned)(b.side_blocks + b.gen_blocks)), block((unsigned)(kSlice * P));
+      if (a.side.tgt || a.side.zout) k_phase_split<KP, PACKED, true><<<grid, block, 0, st>>>(b, P);
+      else k_phase_split<KP, PACKED, false><<<grid, block, 0, st>>>(b, P);
+    } else if (a.side.tgt || a.side.zout) {
       k_phase_var<KP, PACKED><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
     } else if (nb <= 4) {
       launch_phase<KP, PACKED, 4>(a, st);
@@ -707,6 +801,10 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     a.side_blocks = ceil_div(rows ? nr : nc, kBlock);
     a.gen_blocks = gen ? ceil_div(p->sign_blocks, kBlock) : 0;
     a.flag = p->flag;
+    // few slices (rows of a small matrix, or long rows): several wavefronts per slice,
+    // so that about 2048 slices' worth of wavefronts are in flight
+    const int64_t ns = (rows ? p->rows.nslices : p->cols.nslices);
+    a.split = mode == 0 ? (int)std::max<int64_t>(1, std::min<int64_t>(16, 2048 / std::max<int64_t>(ns, 1))) : 1;
     return a;
   };
   // A block side adds one launch after its direction: the block sums, steps and the
