@@ -49,7 +49,7 @@ typedef enum {
   MFE_ENONFINITE = -3,   /* a gradient estimate or iterate became NaN/Inf (e.g. NaN in A) */
   MFE_EDEVICE = -4,      /* a HIP runtime call failed */
   MFE_ENOMEM = -5,       /* device allocation failed */
-  MFE_EUNSUPPORTED = -6  /* valid request this build does not implement */
+  MFE_EUNSUPPORTED = -6  /* valid request the library does not implement */
 } mfe_status;
 
 typedef enum {
