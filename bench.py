@@ -452,6 +452,43 @@ def profile_c4():
     print(json.dumps({"profile": "c4 done"}), flush=True)
 
 
+def profile_c2():
+    """Counter / timing run for the batched workload: 512 matrices in one plan, 16 loads
+    in flight (the autotuner's choice), 20 eager steps, then the calibration copy."""
+    import torch
+
+    from workloads import batched_sparse
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    mats = batched_sparse(512, 1002)
+    G = [mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0") for c in mats]
+    del mats
+    with mfe.Plan(G, max_probes=8) as plan:
+        plan.set_tuning(16, 0, 0)
+        plan.equilibrate(None, None, GAMMA, BOX_M, 20, 8, 2002)
+        torch.cuda.synchronize()
+    calibration_copy()
+    print(json.dumps({"profile": "c2 done", "copy_bytes": 512 * 1024 * 1024}), flush=True)
+
+
+def profile_c0():
+    """Timing run for the dense FP64 200 x 100 workload: three runs of 300 steps."""
+    import torch
+
+    from workloads import scaled_dense
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    A = scaled_dense(200, 100, 1.5, 1000)
+    D = mfe.Dense(torch.tensor(A, device="cuda:0"))
+    al, be = mfe.default_alpha_beta(200, 100)
+    for _ in range(3):
+        mfe.equilibrate(D, al, be, GAMMA, BOX_M, 300, 1, 2000)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "c0 done"}), flush=True)
+
+
 def profile_var():
     """Timing run for the Section 6 variants: 20 eager steps each of per-index targets and
     of blocks (16 rows / 8 columns) on the headline matrix, then of Algorithm 2 on the
@@ -550,11 +587,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
-    ap.add_argument("--profile", nargs="?", const="c1", default=None, choices=["c1", "c3", "c4", "var", "ccp"],
+    ap.add_argument("--profile", nargs="?", const="c1", default=None,
+                    choices=["c1", "c0", "c2", "c3", "c4", "var", "ccp"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
                          "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls; var: 20 steps "
-                         "of each Section 6 variant; ccp: 200 CCP iterations plain and equilibrated")
+                         "of each Section 6 variant; ccp: 200 CCP iterations plain and equilibrated; "
+                         "c2: 20 batched steps and the calibration copy; c0: three dense runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -563,8 +602,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     work = set(args.workloads.split(","))
     if args.profile:
-        {"c1": profile_run, "c3": profile_c3, "c4": profile_c4, "var": profile_var,
-         "ccp": profile_ccp}[args.profile]()
+        {"c1": profile_run, "c0": profile_c0, "c2": profile_c2, "c3": profile_c3, "c4": profile_c4,
+         "var": profile_var, "ccp": profile_ccp}[args.profile]()
         return
 
     import numpy as np
