@@ -48,11 +48,16 @@ def scaled(A, d, e):
 
 
 def op_norm(A, d=None, e=None):
-    """||D A E||_2: the largest singular value, by a dense SVD (small matrices)."""
+    """||D A E||_2: the largest singular value, by a dense SVD for small matrices and by
+    scipy's sparse partial SVD (ARPACK) for large sparse ones."""
     m, n = A.shape
     d = np.ones(m) if d is None else np.asarray(d, dtype=np.float64)
     e = np.ones(n) if e is None else np.asarray(e, dtype=np.float64)
     B = scaled(A, d, e)
+    if sp.issparse(B) and min(m, n) > 2000:
+        from scipy.sparse.linalg import svds
+
+        return float(svds(B, k=1, tol=1e-14, return_singular_vectors=False, random_state=0)[0])
     B = B.toarray() if sp.issparse(B) else B
     return float(np.linalg.svd(B, compute_uv=False)[0])
 

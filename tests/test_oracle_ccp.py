@@ -78,3 +78,11 @@ def test_equilibration_does_not_change_the_problem():
     r1 = ccp.ccp_lasso(A, b, lam, 50)
     r2 = ccp.ccp_lasso(A, b, lam, 50, d=np.ones(40), e=np.ones(70))
     assert np.array_equal(r1["x"], r2["x"])
+
+
+def test_sparse_norm_path_equals_dense_svd():
+    """The operator norm of large sparse inputs (ARPACK partial SVD) is the dense SVD's."""
+    A = paper_sparse(2100, 2200, 0.01, 9).to_scipy()
+    d = np.exp(np.random.default_rng(1).normal(0, 0.5, 2100))
+    ref = np.linalg.svd(d[:, None] * A.toarray(), compute_uv=False)[0]
+    assert abs(ccp.op_norm(A, d=d) - ref) <= 1e-12 * ref
