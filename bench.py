@@ -452,6 +452,23 @@ def profile_c4():
     print(json.dumps({"profile": "c4 done"}), flush=True)
 
 
+def profile_lsqr():
+    """Timing run for LSQR on the headline matrix: 200 iterations without scaling."""
+    import torch
+
+    from workloads import rhs_noisy, scaled_sparse
+
+    mfe = load_lib()
+    torch.cuda.set_device(0)
+    csr = scaled_sparse(M_ROWS, N_COLS, NNZ_ROW, SIGMA, GEN_SEED)
+    b, _ = rhs_noisy(csr.to_scipy(), 1002, noise=1e-3)
+    with mfe.Plan([mfe.Csr.from_arrays(csr.m, csr.n, csr.row_ptr, csr.col_idx, csr.val, device="cuda:0")],
+                  max_probes=K_PROBES) as plan:
+        plan.lsqr(torch.tensor(b, device="cuda:0"), None, None, tol=1e-12, max_iter=200, check_every=25)
+        torch.cuda.synchronize()
+    print(json.dumps({"profile": "lsqr done"}), flush=True)
+
+
 def profile_c2():
     """Counter / timing run for the batched workload: 512 matrices in one plan, 16 loads
     in flight (the autotuner's choice), 20 eager steps, then the calibration copy."""
@@ -588,12 +605,13 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--profile", nargs="?", const="c1", default=None,
-                    choices=["c1", "c0", "c2", "c3", "c4", "var", "ccp"],
+                    choices=["c1", "c0", "c2", "c3", "c4", "var", "ccp", "lsqr"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
                          "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls; var: 20 steps "
                          "of each Section 6 variant; ccp: 200 CCP iterations plain and equilibrated; "
-                         "c2: 20 batched steps and the calibration copy; c0: three dense runs")
+                         "c2: 20 batched steps and the calibration copy; c0: three dense runs; "
+                         "lsqr: 200 LSQR iterations on the headline matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -603,7 +621,7 @@ def main():
     work = set(args.workloads.split(","))
     if args.profile:
         {"c1": profile_run, "c0": profile_c0, "c2": profile_c2, "c3": profile_c3, "c4": profile_c4,
-         "var": profile_var, "ccp": profile_ccp}[args.profile]()
+         "var": profile_var, "ccp": profile_ccp, "lsqr": profile_lsqr}[args.profile]()
         return
 
     import numpy as np

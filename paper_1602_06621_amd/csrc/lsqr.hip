@@ -48,70 +48,94 @@ __device__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- sliced products
 //
-// A workgroup of P wavefronts takes one slice (64 rows): wavefront w walks the slots
-// [w c, (w+1) c) of every row of the slice (c = ceil(width / P)), and wavefront 0 adds
-// the P partial sums in order.  P = 1 (plans with many slices) is one sequential sum per
-// row; long rows in few slices (the Lasso of Section 5.2: 10,000 rows of ~200 entries)
+// A workgroup holds G groups of P wavefronts; group j takes slice G blockIdx + j (64
+// rows), its wavefront w walking the slots [w c, (w+1) c) of every row of the slice
+// (c = ceil(width / P)), and the group's first wavefront adding the P partial sums in
+// order.  Plans with many slices run P = 1, G = 4 (one sequential sum per row); long rows
+// in few slices (the Lasso of Section 5.2: 10,000 rows of ~200 entries are 157 slices)
 // get P up to 16, so that thousands of wavefronts share the work instead of 157.
 constexpr int kMaxSplit = 16;
 
-// Row sums sum_q a_q g[idx_q] of slice s, returned in wavefront 0 (0 elsewhere).  Every
-// thread of the workgroup must call it (it has a barrier when P > 1).
-__device__ double slice_row_sum(const SideDev& S, const double* __restrict__ g, int64_t s, int P) {
-  __shared__ double part[kMaxSplit][kSlice];
-  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int64_t base = S.slice_off[s];
-  const int len = S.len[s * kSlice + lane];
-  const int width = (int)((S.slice_off[s + 1] - base) / kSlice);
-  const int chunk = (width + P - 1) / P;
-  const int q0 = w * chunk, q1 = min(len, q0 + chunk);
-  const int2* e = S.ent + base + lane;
-  double acc = 0.0;
-  for (int q = q0; q < q1; ++q) {
-    const int2 en = e[(int64_t)q * kSlice];
-    acc += (double)__int_as_float(en.y) * g[en.x];
-  }
-  if (P == 1) return acc;
-  part[w][lane] = acc;
-  __syncthreads();
-  double tot = 0.0;
-  if (w == 0)
-    for (int i = 0; i < P; ++i) tot += part[i][lane];
-  return tot;
+struct SliceMap {
+  int P, G;  // wavefronts per slice, slices per workgroup
+};
+
+// Wavefronts per slice for a direction with `nslices` slices: enough to give the device
+// about 4096 wavefronts, at most kMaxSplit per slice; four slices per workgroup when one
+// wavefront per slice suffices.
+inline SliceMap slice_map(int64_t nslices) {
+  const int64_t p = nslices > 0 ? ceil_div(4096, nslices) : 1;
+  SliceMap m;
+  m.P = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, p));
+  m.G = std::max(1, 4 / m.P);
+  return m;
 }
 
-// Wavefronts per slice for a direction with `nslices` slices: enough workgroups to
-// give the device about 4096 wavefronts, at most kMaxSplit per slice.
-inline int slice_split(int64_t nslices) {
-  const int64_t p = nslices > 0 ? ceil_div(4096, nslices) : 1;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, p));
+// Row sums sum_q a_q g[idx_q] of slice s for lane `lane`, returned in the group's first
+// wavefront (wsub = 0; 0 elsewhere and for s >= nslices).  Every thread of the workgroup
+// must call it (it has a barrier when P > 1).
+__device__ double slice_row_sum(const SideDev& S, const double* __restrict__ g, int64_t s, int64_t nslices, int P,
+                                int wave, int wsub, int lane) {
+  __shared__ double part[kMaxSplit][kSlice];
+  double acc = 0.0;
+  if (s < nslices) {
+    const int64_t base = S.slice_off[s];
+    const int len = S.len[s * kSlice + lane];
+    const int width = (int)((S.slice_off[s + 1] - base) / kSlice);
+    const int chunk = (width + P - 1) / P;
+    const int q0 = wsub * chunk, q1 = min(len, q0 + chunk);
+    const int2* e = S.ent + base + lane;
+    for (int q = q0; q < q1; ++q) {
+      const int2 en = e[(int64_t)q * kSlice];
+      acc += (double)__int_as_float(en.y) * g[en.x];
+    }
+  }
+  if (P == 1) return acc;
+  part[wave][lane] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  if (wsub == 0)
+    for (int i = 0; i < P; ++i) tot += part[wave + i][lane];
+  return tot;
 }
 
 // y_r = sout_r * inv * sum_q a_q g[idx_q] + coef * yprev_r  over the rows r of one
 // direction of a plan (internal order); gout_r = sout_r * y_r when requested; one
-// partial of sum y_r^2 per slice.  inv and coef are read from device memory (nullable =
-// 1, 0).  Grid: one workgroup of 64 P threads per slice.
-__global__ __launch_bounds__(kSlice * kMaxSplit) void k_sell_product(SideDev S, int P, const double* __restrict__ sout,
+// partial of sum y_r^2 per workgroup.  inv and coef are read from device memory
+// (nullable = 1, 0).  Grid: ceil(nslices / G) workgroups of 64 G P threads.
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_sell_product(SideDev S, SliceMap sm,
+                                                                     const double* __restrict__ sout,
                                                                      const double* __restrict__ g, const double* inv,
                                                                      const double* coef,
                                                                      const double* __restrict__ yprev,
                                                                      double* __restrict__ y, double* __restrict__ gout,
                                                                      double* __restrict__ partial) {
-  const int64_t s = blockIdx.x;
-  const double acc = slice_row_sum(S, g, s, P);
-  if (threadIdx.x >= kSlice) return;
-  const int64_t r = s * kSlice + threadIdx.x;
+  __shared__ double gsum[kMaxSplit];
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int wsub = wave % sm.P;
+  const int64_t nslices = S.nint / kSlice;
+  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const double acc = slice_row_sum(S, g, s, nslices, sm.P, wave, wsub, lane);
   double contrib = 0.0;
-  if (S.orig[r] >= 0) {
-    const double so = sout ? sout[r] : 1.0;
-    double v = so * (acc * (inv ? *inv : 1.0));
-    if (coef) v += *coef * yprev[r];
-    y[r] = v;
-    if (gout) gout[r] = so * v;
-    contrib = v * v;
+  if (wsub == 0 && s < nslices) {
+    const int64_t r = s * kSlice + lane;
+    if (S.orig[r] >= 0) {
+      const double so = sout ? sout[r] : 1.0;
+      double v = so * (acc * (inv ? *inv : 1.0));
+      if (coef) v += *coef * yprev[r];
+      y[r] = v;
+      if (gout) gout[r] = so * v;
+      contrib = v * v;
+    }
   }
   const double ws = wave_sum(contrib);
-  if (threadIdx.x == 0) partial[s] = ws;
+  if (lane == 0) gsum[wave] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < sm.G; ++i) t += gsum[i * sm.P];
+    partial[blockIdx.x] = t;
+  }
 }
 
 // RMS-residual pass over one direction: s_r = sum_q a_q^2 g2[idx_q] (g2 = squared scales
@@ -264,9 +288,26 @@ __global__ __launch_bounds__(kRed) void k_reduce(const double* __restrict__ part
   if (threadIdx.x == 0) *out = t;
 }
 
+// First stage of a long sum: one partial per block of kRed values.
+__global__ __launch_bounds__(kRed) void k_block_partials(const double* __restrict__ v, int64_t n,
+                                                         double* __restrict__ partial) {
+  const int64_t i = (int64_t)blockIdx.x * kRed + threadIdx.x;
+  const double t = block_sum(i < n ? v[i] : 0.0);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// out = sum of v[0..n) in a fixed order, in two stages (scratch: ceil(n / kRed) values).
+void reduce_long(const double* v, int64_t n, double* scratch, double* out, hipStream_t st) {
+  const int64_t nb = ceil_div(n, kRed);
+  k_block_partials<<<dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kRed), 0, st>>>(v, n, scratch);
+  k_reduce<<<1, kRed, 0, st>>>(scratch, nb, out);
+}
+
 // After the forward product: beta = ||p||, coefficients for the transposed product.
 // The partial sums of the forward pass are reduced here.
-__global__ __launch_bounds__(kRed) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc) {
+__global__ __launch_bounds__(kRed) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
+                                                    int it = 0) {
+  if (it > 0 && threadIdx.x == 0) sc->iter = it;  // before any use below (same thread)
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
   const double t = block_sum(s);
@@ -360,7 +401,6 @@ __global__ void k_scal_init(LsqrScal* sc) {
   *sc = z;
 }
 
-__global__ void k_scal_iter(LsqrScal* sc, int it) { sc->iter = it; }
 
 __global__ void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -422,23 +462,23 @@ struct SellOps : Ops {
     C.ent = p->cols.ent;
     C.nint = p->cols.nint;
     C.is_row = 0;
-    PR = slice_split(p->rows.nslices);
-    PC = slice_split(p->cols.nslices);
+    MR = slice_map(p->rows.nslices);
+    MC = slice_map(p->cols.nslices);
   }
   int64_t rows() const override { return p->rows.nint; }
   int64_t cols() const override { return p->cols.nint; }
-  int PR = 1, PC = 1;  // wavefronts per slice of each direction
-  int64_t fwd_blocks() const override { return p->rows.nslices; }
-  int64_t bwd_blocks() const override { return p->cols.nslices; }
+  SliceMap MR{1, 4}, MC{1, 4};  // slice maps of the two directions
+  int64_t fwd_blocks() const override { return ceil_div(p->rows.nslices, MR.G); }
+  int64_t bwd_blocks() const override { return ceil_div(p->cols.nslices, MC.G); }
   void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
            double* gout, double* partial, hipStream_t st) const override {
-    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kSlice * PR), 0, st>>>(R, PR, sout, g, inv, coef, yprev, y,
-                                                                                gout, partial);
+    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kSlice * MR.P * MR.G), 0, st>>>(R, MR, sout, g, inv, coef,
+                                                                                          yprev, y, gout, partial);
   }
   void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
            double* gout, double* partial, hipStream_t st) const override {
-    k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kSlice * PC), 0, st>>>(C, PC, sout, g, inv, coef, yprev, y,
-                                                                                gout, partial);
+    k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kSlice * MC.P * MC.G), 0, st>>>(C, MC, sout, g, inv, coef,
+                                                                                          yprev, y, gout, partial);
   }
   void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const override {
     const SideDev& S = row ? R : C;
@@ -496,7 +536,7 @@ struct DenseOps : Ops {
 int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
              int32_t check_every, double* x_out, mfe_lsqr_info* info, hipStream_t st) {
   const int64_t nr = ops.rows(), nc = ops.cols();
-  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks());
+  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks()) + ceil_div(nr, kRed) + 1;
   Work W;
   double *bb, *dd, *ee, *u, *du, *v, *w, *x, *ev, *res, *part, *w_tmp;
   LsqrScal* sc;
@@ -523,12 +563,12 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
   const unsigned row_grid = (unsigned)ceil_div(nr, 256);
   // ||b||^2 for the relative residual of the original system
   k_mul<<<row_grid, 256, 0, st>>>(nr, bb, bb, res);
-  k_reduce<<<1, kRed, 0, st>>>(res, nr, &sc->bnorm2);
+  reduce_long(res, nr, part, &sc->bnorm2, st);
   // start: beta_1 u_1 = D b, alpha_1 v_1 = Abar' u_1
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);   // u = D b (normalised by k_lsqr_update)
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);   // du = D u, gathered by the transposed product
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
-  k_reduce<<<1, kRed, 0, st>>>(res, nr, part);
+  reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
   k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
   // v = E A' D u / beta_1 (previous v is zero)
   ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);
@@ -551,10 +591,9 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
     max_iter = 0;
   }
   for (int it = 1; it <= max_iter; ++it) {
-    k_scal_iter<<<1, 1, 0, st>>>(sc, it);
     // p = D A E v - alpha u  (u normalised), du = D p, partial ||p||^2
     ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);
-    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc);
+    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
     // q = E A' D p / beta - beta v, partial ||q||^2
     ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);
     k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
@@ -750,16 +789,20 @@ int dense_f64_residual(const mfe_matrix* A, const double* d, const double* e, do
 
 // Dual step over the rows: y <- (y + sigma D A gx - sigma d b) / (1 + sigma d^2 sqrt(lam)/2),
 // gy = d y (gathered by the primal step); gx = e xt in the columns' internal order.
-// One workgroup of 64 P threads per slice (see slice_row_sum).
-__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_dual(SideDev S, int P, const double* __restrict__ gx,
+// Workgroups as for k_sell_product.
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_dual(SideDev S, SliceMap sm,
+                                                                 const double* __restrict__ gx,
                                                                  const double* __restrict__ d,
                                                                  const double* __restrict__ b, double sigma,
                                                                  double half_sqrt_lam, double* __restrict__ y,
                                                                  double* __restrict__ gy) {
-  const int64_t s = blockIdx.x;
-  const double acc = slice_row_sum(S, gx, s, P);
-  if (threadIdx.x >= kSlice) return;
-  const int64_t r = s * kSlice + threadIdx.x;
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int wsub = wave % sm.P;
+  const int64_t nslices = S.nint / kSlice;
+  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const double acc = slice_row_sum(S, gx, s, nslices, sm.P, wave, wsub, lane);
+  if (wsub != 0 || s >= nslices) return;
+  const int64_t r = s * kSlice + lane;
   if (S.orig[r] < 0) return;
   const double dr = d[r];
   const double yn = (y[r] + sigma * (dr * acc) - sigma * dr * b[r]) / (1.0 + sigma * dr * dr * half_sqrt_lam);
@@ -769,14 +812,18 @@ __global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_dual(SideDev S, int 
 
 // Primal step over the columns: u = x - tau e A' gy, x' = soft(u, tau sqrt(lam) e),
 // xt = x' + theta (x' - x), gx = e xt.
-__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_primal(SideDev S, int P, const double* __restrict__ gy,
+__global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_primal(SideDev S, SliceMap sm,
+                                                                   const double* __restrict__ gy,
                                                                    const double* __restrict__ e_sc, double tau,
                                                                    double thr, double theta, double* __restrict__ x,
                                                                    double* __restrict__ gx) {
-  const int64_t s = blockIdx.x;
-  const double acc = slice_row_sum(S, gy, s, P);
-  if (threadIdx.x >= kSlice) return;
-  const int64_t c = s * kSlice + threadIdx.x;
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int wsub = wave % sm.P;
+  const int64_t nslices = S.nint / kSlice;
+  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const double acc = slice_row_sum(S, gy, s, nslices, sm.P, wave, wsub, lane);
+  if (wsub != 0 || s >= nslices) return;
+  const int64_t c = s * kSlice + lane;
   if (S.orig[c] < 0) return;
   const double ec = e_sc[c];
   const double u = x[c] - tau * (ec * acc);
@@ -847,7 +894,7 @@ double tridiag_max_eig(const std::vector<double>& dg, const std::vector<double>&
 int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t max_iter, double tol, double* norm,
                 int32_t* iters, hipStream_t st) {
   const int64_t nr = ops.rows(), nc = ops.cols();
-  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks());
+  const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks()) + ceil_div(nr, kRed) + 1;
   Work W;
   double *bb, *u, *du, *v, *w, *x, *ev, *res, *part, *hist;
   LsqrScal* sc;
@@ -869,7 +916,7 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);  // beta_1 u_1 = D 1
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
-  k_reduce<<<1, kRed, 0, st>>>(res, nr, part);
+  reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
   k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
   ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);  // alpha_1 v_1 = Abar' u_1
   k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
@@ -880,9 +927,8 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   double est = 0.0, prev = -1.0;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    k_scal_iter<<<1, 1, 0, st>>>(sc, it);
     ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);  // beta u = Abar v - alpha u
-    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc);
+    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
     ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);  // alpha v = Abar' u - beta v
     k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
     k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
@@ -983,10 +1029,10 @@ int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* 
   };
   int tr = 0;
   for (int it = 1; it <= iters; ++it) {
-    k_ccp_dual<<<dim3((unsigned)ops.fwd_blocks()), dim3(kSlice * ops.PR), 0, st>>>(ops.R, ops.PR, gx, dd, bb, sigma,
-                                                                                   0.5 * sl, y, gy);
-    k_ccp_primal<<<dim3((unsigned)ops.bwd_blocks()), dim3(kSlice * ops.PC), 0, st>>>(ops.C, ops.PC, gy, ee, tau,
-                                                                                     tau * sl, 1.0, x, gx);
+    k_ccp_dual<<<dim3((unsigned)ops.fwd_blocks()), dim3(kSlice * ops.MR.P * ops.MR.G), 0, st>>>(
+        ops.R, ops.MR, gx, dd, bb, sigma, 0.5 * sl, y, gy);
+    k_ccp_primal<<<dim3((unsigned)ops.bwd_blocks()), dim3(kSlice * ops.MC.P * ops.MC.G), 0, st>>>(
+        ops.C, ops.MC, gy, ee, tau, tau * sl, 1.0, x, gx);
     MFE_HIP(hipGetLastError());
     if (trace && trace_every > 0 && it % trace_every == 0) MFE_CHECK(objective(&trace[tr++]));
   }
