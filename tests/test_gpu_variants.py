@@ -318,3 +318,52 @@ def test_variant_settings_rejected():
         plan.set_targets(None, None)
         out = plan.equilibrate(None, None, 0.1, 10.0, 10, 4, 1)
         assert out["u_bar"].numel() == 300
+
+
+def test_targets_on_a_batched_plan():
+    """Per-index targets on a plan of three matrices (targets concatenated in plan order,
+    matrix b on sign batch b): each matrix against its own oracle run, t0 = 30 (oracle
+    spread 4.4e-13)."""
+    from paper_1602_06621_amd import Plan
+
+    mats = [scaled_sparse(240, 130, 6, 1.0, 300 + i) for i in range(3)]
+    g = np.random.default_rng(12)
+    rts, cts = [], []
+    for c in mats:
+        al, be = A1.default_alpha_beta(c.m, c.n)
+        rts.append(al**2 * g.uniform(0.5, 2.0, c.m))
+        cts.append(be**2 * g.uniform(0.5, 2.0, c.n))
+    _say("batched targets")
+    with Plan([_gpu(c) for c in mats], max_probes=16) as plan:
+        plan.set_targets(torch.tensor(np.concatenate(rts), device="cuda"),
+                         torch.tensor(np.concatenate(cts), device="cuda"))
+        out = _np(plan.equilibrate(None, None, 0.1, 10.0, 40, 16, 61, t0=30))
+    r0 = np.concatenate([[0], np.cumsum([c.m for c in mats])])
+    c0 = np.concatenate([[0], np.cumsum([c.n for c in mats])])
+    worst = 0.0
+    for b, c in enumerate(mats):
+        o = V.equilibrate_general(c.to_scipy(), 0.1, 10.0, 40, k=16, seed=61, t0=30, row_target=rts[b],
+                                  col_target=cts[b], batch=b)
+        worst = max(worst, np.abs(out["u_bar"][r0[b]:r0[b + 1]] - o["u_bar"]).max(),
+                    np.abs(out["v_bar"][c0[b]:c0[b + 1]] - o["v_bar"]).max())
+    _say("max err", worst)
+    assert worst <= TOL
+
+
+def test_symmetric_wide_descriptors_one_step():
+    """Algorithm 2 with k = 64 (16-byte descriptors, the widest probe bucket), one step
+    from random in-box states: relative 1e-11."""
+    from paper_1602_06621_amd import Plan
+
+    csr = symmetric_sparse(500, 3, 1.5, 98)
+    A = csr.to_scipy()
+    g = np.random.default_rng(64)
+    worst = 0.0
+    with Plan.symmetric_plan(_gpu(csr), max_probes=64) as plan:
+        for t0 in (0, 50):
+            u = np.clip(g.normal(0, 1.5, csr.n), -10, 10)
+            out = _np(plan.equilibrate(1.0, 1.0, 0.1, 10.0, 1, 64, 29, t0=t0, u0=torch.tensor(u, device="cuda")))
+            o = V.equilibrate_symmetric(A, 1.0, 0.1, 10.0, 1, k=64, seed=29, t0=t0, u0=u)
+            worst = max(worst, (np.abs(out["u_bar"] - o["u_bar"]) / np.maximum(1.0, np.abs(o["u_bar"]))).max())
+    _say("worst", worst)
+    assert worst <= 1e-11
