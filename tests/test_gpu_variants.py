@@ -367,3 +367,34 @@ def test_symmetric_wide_descriptors_one_step():
             worst = max(worst, (np.abs(out["u_bar"] - o["u_bar"]) / np.maximum(1.0, np.abs(o["u_bar"]))).max())
     _say("worst", worst)
     assert worst <= 1e-11
+
+
+def test_graph_recaptured_after_variant_settings():
+    """A plan's cached HIP graph is rebuilt when the variant settings change: graph runs
+    before and after set_blocks / set_targets equal the eager runs with the same settings."""
+    from paper_1602_06621_amd import Plan
+
+    csr = scaled_sparse(500, 300, 6, 1.0, 44)
+    al, be = A1.default_alpha_beta(csr.m, csr.n)
+    rp = _random_blocks(csr.m, 9, 3)
+    g = np.random.default_rng(4)
+    rt = torch.tensor(al**2 * g.uniform(0.5, 2.0, csr.m), device="cuda")
+    _say("graph recapture")
+    with Plan([_gpu(csr)], max_probes=8) as plan:
+        res = {}
+        for label in ("plain", "blocks", "targets", "plain2"):
+            if label == "blocks":
+                plan.set_blocks(rp, None)
+            elif label == "targets":
+                plan.set_blocks(None, None)
+                plan.set_targets(rt, None)
+            elif label == "plain2":
+                plan.set_targets(None, None)
+            gr = _np(plan.equilibrate(al, be, 0.1, 10.0, 20, 8, 5, use_graph=True))
+            ea = _np(plan.equilibrate(al, be, 0.1, 10.0, 20, 8, 5, use_graph=False))
+            for key in ("u_bar", "v_bar", "d", "e"):
+                assert np.array_equal(gr[key], ea[key]), (label, key)
+            res[label] = gr
+    assert np.array_equal(res["plain"]["d"], res["plain2"]["d"])
+    assert not np.array_equal(res["plain"]["d"], res["blocks"]["d"])
+    assert not np.array_equal(res["plain"]["d"], res["targets"]["d"])
