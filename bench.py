@@ -41,10 +41,11 @@ BF16_PEAK_TFLOPS = 2500.0
 M_ROWS, N_COLS, NNZ_ROW, SIGMA = 1_000_000, 500_000, 10, 2.0
 T_STEPS, K_PROBES, GAMMA, BOX_M = 2000, 16, 0.1, 10.0
 GEN_SEED, PROBE_SEED = 1001, 2001
-# HBM-side bytes per step of k_phase<16, true, 8> on the headline workload, from rocprofv3
-# FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) per launch, calibrated against a plain
-# 512 MiB copy (profiles/k_phase_csr_1e6x5e5_k16.md).  Set to None when the kernel changes.
-TRAFFIC_BYTES_PER_STEP = (175.0 + 665.1 + 27.0 + 12.0) * 1e6
+# HBM-side bytes per step of k_phase_both<16, true, 8> on the headline workload, from
+# rocprofv3 FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) per launch, calibrated against a
+# plain 512 MiB copy (profiles/k_phase_csr_1e6x5e5_k16.md).  None when the kernel has
+# changed since the counters were taken.
+TRAFFIC_BYTES_PER_STEP = (909.5 + 39.1) * 1e6
 
 
 def sparse_algorithmic_bytes(m, n, nnz, k):
@@ -482,7 +483,7 @@ def profile_c2():
     G = [mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0") for c in mats]
     del mats
     with mfe.Plan(G, max_probes=8) as plan:
-        plan.set_tuning(16, 0, 0)
+        plan.set_tuning(16, 2, 2)
         plan.equilibrate(None, None, GAMMA, BOX_M, 20, 8, 2002)
         torch.cuda.synchronize()
     calibration_copy()
@@ -709,7 +710,7 @@ def main():
                    "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES_PER_STEP,
-                     "kernel": "k_phase<16,true,8> (row launch + column launch of one step)",
+                     "kernel": "k_phase_both<16,true,8> (both directions of one step in one launch)",
                      "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch},
         "cpu_baseline": cpu,
         "extra": extra,

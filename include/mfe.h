@@ -262,11 +262,13 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
  * every launch configuration with the run parameters p (probes, targets, seed) and keeps
  * the fastest in the plan for its later runs (the default configuration is timed first and
  * kept unless another is more than 1% faster).  Configurations: 4, 8 or 16 entry loads in
- * flight per lane (16 only for p->probes <= 16); and, for a single-matrix plan whose
- * gathered table exceeds 6 MB, each such direction in mode 0 (one launch) or 1 (two
- * launches over the halves of the table, FP64 partial sums in between).  Every
+ * flight per lane (16 only for p->probes <= 16); both directions of a step in one launch
+ * (modes 2, 2: the default) or one launch per direction (mode 0); and, for a
+ * single-matrix plan whose gathered table exceeds 6 MB, each such direction also in mode
+ * 1 (two launches over the halves of the table, FP64 partial sums in between).  Every
  * configuration adds the same terms in the same order, so tuning never changes a result
- * bit.
+ * bit.  (Plans whose directions have few slices, and plans with Section 6 settings, run
+ * their own launch forms whatever the modes.)
  * chosen (host int32[3], nullable): loads in flight, mode of the rows, mode of the columns;
  * best_step_ms, n_candidates: nullable.  Allocates two temporary device arrays.
  * EINVAL: plan NULL, invalid p (as mfe_plan_equilibrate), trial_steps out of range. */
@@ -274,8 +276,9 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
                       int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates);
 
 /* Sets a plan's launch configuration directly (the values mfe_plan_autotune chooses):
- * loads_in_flight 4, 8 or 16; rows_mode / cols_mode 0 or 1 (1 only for a direction with
- * a two-part layout, see mfe_plan_autotune).
+ * loads_in_flight 4, 8 or 16; rows_mode / cols_mode both 2 (one launch per step, the
+ * default), or each 0 or 1 (1 only for a direction with a two-part layout, see
+ * mfe_plan_autotune).
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
  * direction without the layout. */
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode);

@@ -399,8 +399,9 @@ class Plan:
         return dict(loads_in_flight=chosen[0], rows_mode=chosen[1], cols_mode=chosen[2], step_ms=best.value,
                     candidates=n.value)
 
-    def set_tuning(self, loads_in_flight=8, rows_mode=0, cols_mode=0):
-        """Launch configuration of the step kernels (see mfe_plan_set_tuning)."""
+    def set_tuning(self, loads_in_flight=8, rows_mode=2, cols_mode=2):
+        """Launch configuration of the step kernels (see mfe_plan_set_tuning); the defaults
+        are the library's (8 loads in flight, both directions in one launch)."""
         _check(_lib().mfe_plan_set_tuning(self._h, int(loads_in_flight), int(rows_mode), int(cols_mode)))
 
     def last_timing(self):

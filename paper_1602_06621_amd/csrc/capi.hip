@@ -304,9 +304,10 @@ int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mo
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   if (loads_in_flight != 4 && loads_in_flight != 8 && loads_in_flight != 16)
     return set_error(MFE_EINVAL, "loads_in_flight must be 4, 8 or 16");
-  if (rows_mode < 0 || rows_mode > 1 || cols_mode < 0 || cols_mode > 1)
-    return set_error(MFE_EINVAL, "direction modes must be 0 or 1");
-  if ((rows_mode && !plan->rows.len_lo) || (cols_mode && !plan->cols.len_lo))
+  const bool both = rows_mode == 2 && cols_mode == 2;
+  if (!both && (rows_mode < 0 || rows_mode > 1 || cols_mode < 0 || cols_mode > 1))
+    return set_error(MFE_EINVAL, "direction modes must be 0 or 1 each, or 2 for both (one launch per step)");
+  if ((rows_mode == 1 && !plan->rows.len_lo) || (cols_mode == 1 && !plan->cols.len_lo))
     return set_error(MFE_EUNSUPPORTED, "two-part mode requested for a direction without the two-part layout");
   plan->tune_batch = loads_in_flight;
   plan->tune_split[0] = rows_mode;

@@ -150,11 +150,12 @@ struct mfe_plan {
   uint64_t* signs[2] = {nullptr, nullptr};
   double* part[2] = {nullptr, nullptr};  // partial sums of the two-part mode (rows, columns)
   // Launch configuration of the step kernels, chosen by plan_autotune (results are the
-  // same bit for bit under every configuration): loads in flight per lane, and whether
-  // each direction (rows, columns) with a two-part layout runs as one launch (0) or as
-  // two launches over the halves of its table (1).
+  // same bit for bit under every configuration): loads in flight per lane, and how the
+  // directions (rows, columns) are launched: {2, 2} both directions of a step in one
+  // launch (the default); otherwise one launch per direction (0), or two launches over
+  // the halves of its table for a direction with a two-part layout (1).
   int32_t tune_batch = mfe::kBatch;
-  int32_t tune_split[2] = {0, 0};
+  int32_t tune_split[2] = {2, 2};
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;

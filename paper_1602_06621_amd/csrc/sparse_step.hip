@@ -316,6 +316,18 @@ __global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
   else signgen_block(a.gen, b - a.side_blocks);
 }
 
+// Both directions of one step in one launch (row workgroups, then column workgroups,
+// then the sign words): for plans too small to fill the device with one direction.  The
+// directions read the other's descriptors of step t-1 and write their own of step t, so
+// they are independent within a step.
+template <int KP, bool PACKED, int NB>
+__global__ __launch_bounds__(kBlock) void k_phase_both(PhaseArgs a, SideDev C, int64_t col_blocks) {
+  const int64_t b = blockIdx.x;
+  if (b < a.side_blocks) side_update<KP, PACKED, NB>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, NB>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
+  else signgen_block(a.gen, b - a.side_blocks - col_blocks);
+}
+
 // The same for the Section 6 variants (per-index targets, block sides, symmetric plans).
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
@@ -617,6 +629,21 @@ struct PhaseLauncher {
 };
 
 template <int KP, bool PACKED>
+struct BothLauncher {
+  static void run(const PhaseArgs& a, const SideDev& C, int64_t col_blocks, int nb, hipStream_t st) {
+    const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block(kBlock);
+    if (nb <= 4) {
+      k_phase_both<KP, PACKED, 4><<<grid, block, 0, st>>>(a, C, col_blocks);
+    } else if constexpr (KP <= 16) {
+      if (nb >= 16) k_phase_both<KP, PACKED, 16><<<grid, block, 0, st>>>(a, C, col_blocks);
+      else k_phase_both<KP, PACKED, 8><<<grid, block, 0, st>>>(a, C, col_blocks);
+    } else {
+      k_phase_both<KP, PACKED, 8><<<grid, block, 0, st>>>(a, C, col_blocks);
+    }
+  }
+};
+
+template <int KP, bool PACKED>
 struct BlockLauncher {
   static void run(const SideDev& S, const BlockDev& B, int k, const StepScalars& sc, int64_t wbase,
                   const double* x0, int init, int* flag, hipStream_t st) {
@@ -752,14 +779,14 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     MFE_HIP(hipGetLastError());
   }
 
-  // Step t = two launches (Jacobi order: both read the descriptors of step t-1):
-  // the row direction (plus the sign words of step t+2), then the column direction.
-  // Keeping the directions apart lets each launch's L2 hold only the table it gathers.
-  // A direction with a two-part layout runs as two launches, each gathering from one
-  // half of the table, when the plan's tuning says so.
+  // Step t (Jacobi order: both directions read the descriptors of step t-1): by default
+  // one launch holding the row direction (plus the sign words of step t+2) and the
+  // column direction; otherwise, as the plan's tuning says, one launch per direction, and
+  // a direction with a two-part layout as two launches, each gathering from one half of
+  // its table.
   // (Symmetric plans gather with their own entries, which have no two-part layout.)
-  const int split_rows = p->rows.len_lo && !p->symmetric ? p->tune_split[0] : 0;  // 0 one launch, 1 two
-  const int split_cols = p->cols.len_lo ? p->tune_split[1] : 0;
+  const int split_rows = p->rows.len_lo && !p->symmetric && p->tune_split[0] == 1 ? 1 : 0;  // 1: two launches
+  const int split_cols = p->cols.len_lo && p->tune_split[1] == 1 ? 1 : 0;
   const int nb = p->tune_batch;
   for (int i = 0; i < 2; ++i) {
     const bool need = (i == 0 ? split_rows : split_cols) != 0;
@@ -809,7 +836,17 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   };
   // A block side adds one launch after its direction: the block sums, steps and the
   // descriptors of the block's indices (which the other direction reads at step t+1).
+  // Both directions in one launch (tuning modes 2 / 2) where neither needs another form.
+  const bool fused = p->tune_split[0] == 2 && p->tune_split[1] == 2 && !p->symmetric && !blocked[0] &&
+                     !blocked[1] && !p->tgt_int[0] && !p->tgt_int[1];
   auto launch_step = [&](int t, hipStream_t s) {
+    if (fused) {
+      const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
+      if (a.split <= 1 && c.split <= 1) {
+        dispatch<BothLauncher>(k, packed, a, c.side, c.side_blocks, nb, s);
+        return;
+      }
+    }
     for (const bool rows : {true, false}) {
       if (!rows && p->symmetric) break;
       if (rows ? split_rows : split_cols) {
@@ -835,7 +872,8 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   if (use_graph && T > 0) {
     const double key[12] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
                             (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
-                            (double)nb, (double)split_rows, (double)split_cols, (double)p->variant_epoch};
+                            (double)nb, (double)p->tune_split[0], (double)p->tune_split[1],
+                            (double)p->variant_epoch};
     bool hit = p->graph_exec != nullptr;
     for (int i = 0; i < 12 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -924,6 +962,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   std::vector<Cand> cands;
   for (int nb : {8, 4, 16}) {
     if (nb == 16 && k > 16) continue;
+    cands.push_back({nb, 2, 2});  // both directions in one launch
     for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
       for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc});
   }
