@@ -328,6 +328,15 @@ __global__ __launch_bounds__(kBlock) void k_phase_both(PhaseArgs a, SideDev C, i
   else signgen_block(a.gen, b - a.side_blocks - col_blocks);
 }
 
+// The same with the Section 6 variant update (per-index targets, block sides).
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev C, int64_t col_blocks) {
+  const int64_t b = blockIdx.x;
+  if (b < a.side_blocks) side_update<KP, PACKED, 8, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, 8, true>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
+  else signgen_block(a.gen, b - a.side_blocks - col_blocks);
+}
+
 // The same for the Section 6 variants (per-index targets, block sides, symmetric plans).
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
@@ -632,7 +641,9 @@ template <int KP, bool PACKED>
 struct BothLauncher {
   static void run(const PhaseArgs& a, const SideDev& C, int64_t col_blocks, int nb, hipStream_t st) {
     const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block(kBlock);
-    if (nb <= 4) {
+    if (a.side.tgt || a.side.zout || C.tgt || C.zout) {
+      k_phase_both_var<KP, PACKED><<<grid, block, 0, st>>>(a, C, col_blocks);
+    } else if (nb <= 4) {
       k_phase_both<KP, PACKED, 4><<<grid, block, 0, st>>>(a, C, col_blocks);
     } else if constexpr (KP <= 16) {
       if (nb >= 16) k_phase_both<KP, PACKED, 16><<<grid, block, 0, st>>>(a, C, col_blocks);
@@ -836,14 +847,19 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   };
   // A block side adds one launch after its direction: the block sums, steps and the
   // descriptors of the block's indices (which the other direction reads at step t+1).
-  // Both directions in one launch (tuning modes 2 / 2) where neither needs another form.
-  const bool fused = p->tune_split[0] == 2 && p->tune_split[1] == 2 && !p->symmetric && !blocked[0] &&
-                     !blocked[1] && !p->tgt_int[0] && !p->tgt_int[1];
+  // Both directions in one launch (tuning modes 2 / 2) where neither needs another form;
+  // block sides then run their block launches after it.
+  const bool fused = p->tune_split[0] == 2 && p->tune_split[1] == 2 && !p->symmetric;
   auto launch_step = [&](int t, hipStream_t s) {
     if (fused) {
       const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
       if (a.split <= 1 && c.split <= 1) {
         dispatch<BothLauncher>(k, packed, a, c.side, c.side_blocks, nb, s);
+        for (int si = 0; si < 2; ++si)
+          if (blocked[si]) {
+            const PhaseArgs& x = si == 0 ? a : c;
+            dispatch<BlockLauncher>(k, packed, x.side, bd[si], k, x.sc, wbase[si], nullptr, 0, p->flag, s);
+          }
         return;
       }
     }
