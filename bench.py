@@ -711,7 +711,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES_PER_STEP,
                      "kernel": "k_phase_both<16,true,8> (both directions of one step in one launch)",
-                     "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch},
+                     "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch,
+                     # HBM bytes the counters saw per step, over the same kernel time
+                     "traffic_gbs": (TRAFFIC_BYTES_PER_STEP / (kern_ms / 1e3) / 1e9
+                                     if TRAFFIC_BYTES_PER_STEP else None)},
         "cpu_baseline": cpu,
         "extra": extra,
     }
