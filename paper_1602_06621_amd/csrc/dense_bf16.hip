@@ -3,24 +3,26 @@
 // Per step the two products are GEMMs against the probe block: Y = A (E S) (m x k) and
 // X = A' (D W) (n x k), k <= 64.  Probe operands are exact signs times bf16(e^x);
 // products accumulate in FP32 on v_mfma_f32_32x32x16_bf16; the square / step /
-// project / average epilogue runs in FP64 inside the same kernel.
+// project / average update runs in FP64.
 //
 // Layout.  The library keeps two copies of A in an MFMA-native tiled layout: tile
 // (row block rb of 32 rows, k chunk kc of 16 columns) is 1 KiB, lane l holding the 8
 // values A[32 rb + l%32][16 kc + 8 (l/32) + j], j < 8, in 16 consecutive bytes, so a
 // wavefront reads each tile with one fully coalesced 16-byte load per lane.  The second
 // copy is A' in the same layout, which turns the transposed product into the same
-// kernel.  Probe blocks use the matching operand layout (per k chunk, lane l holds probe
-// 32 nb + l%32 at the same 8 k values).  Both are padded with zeros to whole tiles.
+// kernel.  Tiles are padded with zeros.  The probe operand of a chunk has the matching
+// layout (lane l holds probe 32 nb + l%32 at the same 8 k values), but is not stored as
+// a tile: per k chunk the pass loads the 16 bf16
+// scales and one sign byte per (probe, half chunk), 32 + 64 NB bytes, and assembles the
+// MFMA operand in registers (sign bit XORed into each scale).  A step is three
+// launches: the probe build (Philox signs and bf16 scales of both sides), both passes
+// (rows over A, then columns over A'), and the update of both sides.
 //
-// Work split: a workgroup of 4 wavefronts covers 4 consecutive 32-row blocks over one k
-// range (the k chunks are split into `splits` ranges so that a pass launches ~512
-// workgroups).  The four wavefronts walk the same chunks, so each probe tile is fetched
-// from L2 once per workgroup and read by the other wavefronts from L1 (probe loads were
-// two thirds of the L2 requests when every wavefront walked its own chunks; the pass is
-// bound by L2 requests in flight per CU).  Each wavefront stores its 32 x 32 NB FP32
-// accumulator as the partial of its block and range; a second launch adds the ranges in
-// FP64 and runs the square / step / project / average update.
+// Work split: a workgroup of 4 wavefronts covers 4 RW consecutive 32-row blocks over one
+// k range (the k chunks are split into `splits` ranges so that a pass launches about
+// MFE_BF16_WG workgroups).  Each wavefront keeps two groups of F chunks in flight and
+// stores its 32 RW x 32 NB FP32 accumulator as the partial of its blocks and range; the
+// update adds the ranges in FP64 and runs the square / step / project / average update.
 #include <cmath>
 #include <vector>
 
@@ -36,7 +38,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 32;   // rows per tile / workgroup
 constexpr int kChunk = 16;  // k per MFMA
-constexpr int kWaves = 4;
+#ifndef MFE_BF16_WAVES
+#define MFE_BF16_WAVES 4
+#endif
+constexpr int kWaves = MFE_BF16_WAVES;
 
 // FP64 -> bfloat16 bits, round to nearest even, for finite normal values in range.
 __device__ inline uint16_t bf16_rne(double x) {
@@ -89,42 +94,76 @@ __global__ void k_tile(const uint16_t* __restrict__ A, int64_t m, int64_t n, int
   tiles[gid] = w;
 }
 
-// Probe operand tiles: per k chunk kc and probe block nb (32 probes), lane l holds
-// probe p = 32 nb + l%32 at k = 16 kc + 8 (l/32) + j:  +-bf16(scale[k]), sign bit k*K + p.
-__global__ void k_probe_tiles(const double* __restrict__ scale, const uint64_t* __restrict__ sw, int64_t C, int K,
-                              int64_t KC, int NB, u32x4* __restrict__ out) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (kc, nb, lane)
-  if (gid >= KC * NB * 64) return;
-  const int lane = (int)(gid & 63);
-  const int64_t t = gid >> 6;
-  const int nb = (int)(t % NB);
-  const int64_t kc = t / NB;
-  const int p = nb * 32 + (lane & 31);
-  const int64_t k0 = kc * kChunk + (lane >> 5) * 8;
-  uint16_t v[8];
-  for (int j = 0; j < 8; ++j) {
-    const int64_t kk = k0 + j;
-    uint16_t x = 0;
-    if (kk < C && p < K) {
-      x = bf16_rne(scale[kk]);
-      const uint64_t g = (uint64_t)kk * (uint64_t)K + (uint64_t)p;
-      if ((sw[g >> 6] >> (g & 63)) & 1ull) x ^= 0x8000;
-    }
-    v[j] = x;
+// Probe operands, kept compressed in memory and expanded into MFMA operands in
+// registers by the pass: per k chunk kc, the bf16 scales of its 16 indices
+// (scl[16 kc + i]; zero past the end) and one sign byte per (half h, probe p):
+// sgn[((2 kc + h) 32 + p % 32) NB + p / 32] holds in bit j the sign of probe p at
+// index 16 kc + 8 h + j, which is bit k*K + p of the side's Philox stream (the layout
+// of the library's sign words); zero for p >= K or past the end.  Per chunk that is
+// 32 + 64 NB bytes instead of the 1 KiB operand tile per 32 probes.
+struct ProbeSide {
+  const double* scale;  // e^x of the indices of this side, step t-1
+  int64_t C, KC;        // indices, k chunks
+  uint64_t ctrl;        // Philox key word: (batch << 34) | (t << 2) | side
+  uint16_t* scl;        // [KC * 16]
+  uint8_t* sgn;         // [KC][2][32][NB]
+  int64_t groups;       // workgroups of kProbeChunks chunks
+};
+
+constexpr int kProbeChunks = 4;                                       // k chunks per workgroup
+constexpr int kProbeBlocks = kProbeChunks * kChunk * 64 / 256 + 2;  // Philox blocks per workgroup (K <= 64)
+
+// One launch for both sides: the workgroup draws the Philox blocks that hold the sign
+// bits of its 64 indices into LDS, then writes its chunks' scales and sign bytes.
+__global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1, int K, int NB, uint64_t seed) {
+  __shared__ uint64_t words[4 * kProbeBlocks];
+  const bool first = blockIdx.x < P0.groups;
+  const ProbeSide& P = first ? P0 : P1;
+  const int64_t grp = first ? blockIdx.x : blockIdx.x - P0.groups;
+  const int64_t kk0 = grp * kProbeChunks * kChunk;
+  const int64_t kk1 = kk0 + kProbeChunks * kChunk < P.C ? kk0 + kProbeChunks * kChunk : P.C;
+  const int64_t c0 = (kk0 * K) >> 8;  // first Philox block
+  const int64_t nblk = kk1 > kk0 ? (((kk1 * K + 255) >> 8) - c0) : 0;
+  for (int64_t i = threadIdx.x; i < nblk; i += 256) {
+    const U64x4 w = philox4x64_10((uint64_t)(c0 + i) + 1, 0, 0, 0, seed, P.ctrl);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) words[4 * i + q] = w.x[q];
   }
-  u32x4 w;
-  w.x = v[0] | ((uint32_t)v[1] << 16);
-  w.y = v[2] | ((uint32_t)v[3] << 16);
-  w.z = v[4] | ((uint32_t)v[5] << 16);
-  w.w = v[6] | ((uint32_t)v[7] << 16);
-  out[gid] = w;
+  if (threadIdx.x < kProbeChunks * kChunk) {
+    const int64_t kk = kk0 + threadIdx.x;
+    if (kk < P.KC * kChunk) P.scl[kk] = kk < P.C ? bf16_rne(P.scale[kk]) : (uint16_t)0;
+  }
+  __syncthreads();
+  const int nout = kProbeChunks * 64 * NB;
+  for (int o = threadIdx.x; o < nout; o += 256) {
+    const int nb = o % NB;
+    const int hq = (o / NB) & 63;  // 32 h + p % 32
+    const int64_t kc = grp * kProbeChunks + o / (64 * NB);
+    if (kc >= P.KC) continue;
+    const int p = nb * 32 + (hq & 31);
+    const int64_t k0 = kc * kChunk + (hq >> 5) * 8;
+    uint32_t byte = 0;
+    if (p < K) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t kk = k0 + j;
+        if (kk < P.C) {
+          const int64_t g = kk * K + p - c0 * 256;
+          byte |= (uint32_t)((words[g >> 6] >> (g & 63)) & 1ull) << j;
+        }
+      }
+    }
+    P.sgn[kc * 64 * NB + o % (64 * NB)] = (uint8_t)byte;
+  }
 }
 
 struct Bf16Side {
   const u32x4* tiles;   // [RB][KC][64]
-  const u32x4* probes;  // [KC][NB][64]
+  const uint16_t* scl;  // probe operands, compressed (see ProbeSide)
+  const uint8_t* sgn;
   int64_t R, RB, KC;
   int splits;           // k ranges per row block
+  int64_t groups;       // workgroups per k range (kWaves * RW row blocks each)
   float* part;          // [splits][RB * 32][32 NB] partial products
   double* x;
   double* xbar;
@@ -138,91 +177,138 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) {
   return r;
 }
 
-// Wavefront w of workgroup (g, split): row block 4 g + w, chunks of range `split`;
-// partial Y (32 x 32 NB) = tiles . probes.
+// Probe operands of one chunk for lane l from its 8 scales (16 bytes) and sign bytes:
+// the sign of index j goes to bit 15 of slot j (slots 2i and 2i+1 share 32-bit word i).
 template <int NB>
+__device__ __forceinline__ void expand_probes(const u32x4& sc, uint32_t sg, u32x4 (&op)[NB]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const uint32_t y = sg >> (8 * b);
+    op[b].x = sc.x ^ ((y << 15) & 0x8000u) ^ ((y << 30) & 0x80000000u);
+    op[b].y = sc.y ^ ((y << 13) & 0x8000u) ^ ((y << 28) & 0x80000000u);
+    op[b].z = sc.z ^ ((y << 11) & 0x8000u) ^ ((y << 26) & 0x80000000u);
+    op[b].w = sc.w ^ ((y << 9) & 0x8000u) ^ ((y << 24) & 0x80000000u);
+  }
+}
+
+// Wavefront w of workgroup (g, split): row blocks RW (4 g + w) .. + RW - 1, chunks of
+// range `split`; partial Y (32 RW x 32 NB) = tiles . probes.  The probe operands of a
+// chunk are expanded once per wavefront and used for all RW row blocks.
+template <int NB, int RW, int F>
 struct ChunkGroup {
-  static constexpr int F = 4;  // chunks per group; two groups are in flight
-  u32x4 a[F];
-  u32x4 p[F][NB];
-  __device__ __forceinline__ void load(const u32x4* __restrict__ at, const u32x4* __restrict__ pt, int64_t kc) {
+  u32x4 a[F][RW];
+  u32x4 sc[F];    // bf16 scales of the lane's 8 indices
+  uint32_t sg[F]; // sign bytes of the lane's NB probes
+  // ps: scales as 16-byte groups, offset by the lane's half; pg: sign bytes (NB per
+  // lane), offset by the lane
+  __device__ __forceinline__ void load(const u32x4* const (&at)[RW], const u32x4* __restrict__ ps,
+                                       const uint8_t* __restrict__ pg, int64_t kc) {
 #pragma unroll
     for (int u = 0; u < F; ++u) {
-      a[u] = __builtin_nontemporal_load(at + (kc + u) * 64);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) p[u][b] = pt[((kc + u) * NB + b) * 64];
+      for (int r = 0; r < RW; ++r) a[u][r] = __builtin_nontemporal_load(at[r] + (kc + u) * 64);
+      sc[u] = ps[(kc + u) * 2];
+      if (NB == 2) sg[u] = *(const uint16_t*)(pg + (kc + u) * 128);
+      else sg[u] = pg[(kc + u) * 64];
     }
   }
-  __device__ __forceinline__ void mma(f32x16 (&acc)[NB]) const {
+  __device__ __forceinline__ void mma(f32x16 (&acc)[RW][NB]) const {
 #pragma unroll
-    for (int u = 0; u < F; ++u)
+    for (int u = 0; u < F; ++u) {
+      u32x4 op[NB];
+      expand_probes<NB>(sc[u], sg[u], op);
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u]), as_bf16x8(p[u][b]), acc[b], 0, 0, 0);
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u][r]), as_bf16x8(op[b]), acc[r][b], 0, 0,
+                                                              0);
+    }
   }
 };
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_bf16_pass(Bf16Side S) {
-  constexpr int F = ChunkGroup<NB>::F;
+template <int NB, int RW, int F>
+__device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int split) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t rb = (int64_t)blockIdx.x * kWaves + wave;
-  if (rb >= S.RB) return;
-  const int split = blockIdx.y;
+  const int64_t rb0 = (grp * kWaves + wave) * RW;
+  if (rb0 >= S.RB) return;
   const int64_t per = (S.KC + S.splits - 1) / S.splits;
   const int64_t kbeg = (int64_t)split * per, kend = kbeg + per < S.KC ? kbeg + per : S.KC;
-  f32x16 acc[NB];
+  f32x16 acc[RW][NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+  for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
-  const u32x4* __restrict__ at = S.tiles + rb * S.KC * 64 + lane;
-  const u32x4* __restrict__ pt = S.probes + lane;
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][b][v] = 0.f;
+  // row blocks past the end re-read the last one; their results are not stored
+  const u32x4* at[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) at[r] = S.tiles + (rb0 + r < S.RB ? rb0 + r : S.RB - 1) * S.KC * 64 + lane;
+  const u32x4* __restrict__ ps = (const u32x4*)S.scl + (lane >> 5);
+  const uint8_t* __restrict__ pg = S.sgn + lane * NB;
   // double-buffered groups: the loads of group g + 1 are issued before the products of g
   const int64_t ngroups = (kend - kbeg) / F;
-  ChunkGroup<NB> g0, g1;
+  ChunkGroup<NB, RW, F> g0, g1;
   int64_t kc = kbeg;
-  if (ngroups > 0) g0.load(at, pt, kc);
+  if (ngroups > 0) g0.load(at, ps, pg, kc);
   for (int64_t g = 0; g < ngroups; g += 2) {
-    if (g + 1 < ngroups) g1.load(at, pt, kc + F);
+    if (g + 1 < ngroups) g1.load(at, ps, pg, kc + F);
     g0.mma(acc);
     if (g + 1 >= ngroups) {
       kc += F;
       break;
     }
-    if (g + 2 < ngroups) g0.load(at, pt, kc + 2 * F);
+    if (g + 2 < ngroups) g0.load(at, ps, pg, kc + 2 * F);
     g1.mma(acc);
     kc += 2 * F;
   }
   for (; kc < kend; ++kc) {
-    const u32x4 a = __builtin_nontemporal_load(at + kc * 64);
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a), as_bf16x8(pt[(kc * NB + b) * 64]), acc[b], 0,
-                                                       0, 0);
+    ChunkGroup<NB, RW, 1> one;
+    one.load(at, ps, pg, kc);
+    one.mma(acc);
   }
   // accumulator layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + v%4, column l%32
-  float* __restrict__ out = S.part + ((int64_t)split * S.RB + rb) * kRows * 32 * NB;
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+  for (int r = 0; r < RW; ++r) {
+    if (rb0 + r >= S.RB) break;
+    float* __restrict__ out = S.part + ((int64_t)split * S.RB + rb0 + r) * kRows * 32 * NB;
 #pragma unroll
-    for (int v = 0; v < 16; ++v)
-      out[((v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)) * 32 * NB + b * 32 + (lane & 31)] = acc[b][v];
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        out[((v >> 2) * 8 + (lane >> 5) * 4 + (v & 3)) * 32 * NB + b * 32 + (lane & 31)] = acc[r][b][v];
+  }
 }
 
-// Update of every index from the FP32 partials: one wavefront per row, lane p adds the
-// ranges of probe p in FP64 (coalesced over the probes), the squares are summed across
-// the wavefront, and lane 0 updates the iterate.
+// Both products of one step in one launch: the row pass over the tiles of A, then the
+// column pass over the tiles of A' (Jacobi order: each reads the operands of step t-1).
+// Workgroup b < R.groups * R.splits belongs to the row pass.
+template <int NB, int RW, int F>
+__global__ __launch_bounds__(kWaves * 64) void k_bf16_pass(Bf16Side R, Bf16Side C) {
+  const int64_t nr = R.groups * R.splits;
+  const int64_t b = blockIdx.x;
+  if (b < nr) bf16_pass<NB, RW, F>(R, b % R.groups, (int)(b / R.groups));
+  else bf16_pass<NB, RW, F>(C, (b - nr) % C.groups, (int)((b - nr) / C.groups));
+}
+
 template <int NB>
-__global__ __launch_bounds__(256) void k_bf16_update(Bf16Side S, int k, StepScalars sc, int* flag) {
+__device__ __forceinline__ void bf16_update(const Bf16Side& S, int64_t r, int k, const StepScalars& sc, int* flag) {
   const int lane = threadIdx.x & 63;
-  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   if (r >= S.R) return;  // whole wavefronts leave together
   const int64_t stride = S.RB * kRows * 32 * NB;
   double y = 0.0;
   if (lane < 32 * NB && lane < k) {
+    // eight ranges' loads in flight at a time, added in range order
     const float* __restrict__ base = S.part + r * 32 * NB + lane;
-    for (int sp = 0; sp < S.splits; ++sp) y += (double)base[sp * stride];
+    for (int s0 = 0; s0 < S.splits; s0 += 8) {
+      float q[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) q[j] = s0 + j < S.splits ? base[(int64_t)(s0 + j) * stride] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (s0 + j < S.splits) y += (double)q[j];
+    }
   }
   const double ss = wave_sum(y * y);
   if (lane == 0) {
@@ -232,6 +318,19 @@ __global__ __launch_bounds__(256) void k_bf16_update(Bf16Side S, int k, StepScal
     S.xbar[r] = xb;
     S.scale_out[r] = exp(x);
   }
+}
+
+// Update of every index of both sides from the FP32 partials: one wavefront per index,
+// lane p adds the ranges of probe p in FP64 (coalesced over the probes), the squares are
+// summed across the wavefront, and lane 0 updates the iterate.  Workgroups
+// b < ceil(R.R / 4) take the rows.
+template <int NB>
+__global__ __launch_bounds__(256) void k_bf16_update(Bf16Side R, Bf16Side C, int k, StepScalars sc, int* flag) {
+  const int64_t rw = (R.R + 3) / 4;
+  const int64_t b = blockIdx.x;
+  const int64_t w = threadIdx.x >> 6;
+  if (b < rw) bf16_update<NB>(R, b * 4 + w, k, sc, flag);
+  else bf16_update<NB>(C, (b - rw) * 4 + w, k, sc, flag);
 }
 
 __global__ void k_bf_init(int64_t cnt, const double* __restrict__ x0, double M, double* __restrict__ x,
@@ -272,17 +371,34 @@ struct Bufs {
   }
 };
 
+// Launch shape (compile-time; measured on the 16384 x 8192, k = 64 workload: one row
+// block per wavefront, eight chunks per load group and about 128 workgroups per pass
+// gave the shortest step).
+#ifndef MFE_BF16_RW
+#define MFE_BF16_RW 1
+#endif
+#ifndef MFE_BF16_F
+#define MFE_BF16_F 8
+#endif
+#ifndef MFE_BF16_WG
+#define MFE_BF16_WG 128
+#endif
+constexpr int kRW = MFE_BF16_RW;   // row blocks per wavefront
+constexpr int kF = MFE_BF16_F;     // chunks per load group (two groups in flight)
+
 template <int NB>
-void launch_pass(const Bf16Side& S, int k, const StepScalars& sc, int* flag, hipStream_t st) {
-  k_bf16_pass<NB><<<dim3((unsigned)ceil_div(S.RB, kWaves), (unsigned)S.splits), dim3(256), 0, st>>>(S);
-  k_bf16_update<NB><<<dim3((unsigned)ceil_div(S.R * 64, 256)), dim3(256), 0, st>>>(S, k, sc, flag);
+void launch_step(const Bf16Side& R, const Bf16Side& C, int k, const StepScalars& sc, int* flag, hipStream_t st) {
+  const int64_t wgs = R.groups * R.splits + C.groups * C.splits;
+  k_bf16_pass<NB, kRW, kF><<<dim3((unsigned)wgs), dim3(kWaves * 64), 0, st>>>(R, C);
+  const int64_t ub = ceil_div(R.R, 4) + ceil_div(C.R, 4);
+  k_bf16_update<NB><<<dim3((unsigned)ub), dim3(256), 0, st>>>(R, C, k, sc, flag);
 }
 
-// k ranges per row block: about 512 workgroups (of 4 row blocks) per pass, at least 32
-// chunks per range.
+// k ranges per row block: about MFE_BF16_WG workgroups (of kWaves * kRW row blocks) per
+// pass, at least 32 chunks per range.
 int bf16_splits(int64_t RB, int64_t KC) {
   int64_t s = 1;
-  while (ceil_div(RB, kWaves) * s < 512 && KC / (2 * s) >= 32) s *= 2;
+  while (ceil_div(RB, kWaves * kRW) * s < MFE_BF16_WG && KC / (2 * s) >= 32) s *= 2;
   return (int)s;
 }
 
@@ -301,13 +417,18 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   const int64_t RBu = ceil_div(m, kRows), KCu = ceil_div(n, kChunk);  // tiles of A
   const int64_t RBv = ceil_div(n, kRows), KCv = ceil_div(m, kChunk);  // tiles of A'
   Bufs B;
-  u32x4 *tu, *tv, *pu, *pv;
+  u32x4 *tu, *tv;
+  uint16_t *scu, *scv;
+  uint8_t *sgu, *sgv;
   double *u, *ub, *v, *vb, *su[2], *sv[2];
   int* flag;
   MFE_CHECK(B.alloc(&tu, RBu * KCu * 64));
   MFE_CHECK(B.alloc(&tv, RBv * KCv * 64));
-  MFE_CHECK(B.alloc(&pu, KCu * NB * 64));  // probes for the row pass: columns, side 0
-  MFE_CHECK(B.alloc(&pv, KCv * NB * 64));  // probes for the column pass: rows, side 1
+  // probe operands for the row pass (columns, side 0) and the column pass (rows, side 1)
+  MFE_CHECK(B.alloc(&scu, KCu * kChunk));
+  MFE_CHECK(B.alloc(&sgu, KCu * 64 * NB));
+  MFE_CHECK(B.alloc(&scv, KCv * kChunk));
+  MFE_CHECK(B.alloc(&sgv, KCv * 64 * NB));
   MFE_CHECK(B.alloc(&u, m));
   MFE_CHECK(B.alloc(&ub, m));
   MFE_CHECK(B.alloc(&v, n));
@@ -321,25 +442,6 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   float *partu, *partv;
   MFE_CHECK(B.alloc(&partu, (int64_t)Su * RBu * kRows * 32 * NB));
   MFE_CHECK(B.alloc(&partv, (int64_t)Sv * RBv * kRows * 32 * NB));
-  // sign words: side 0 (n * k bits) then side 1 (m * k bits), one slot refilled per step
-  SignSeg segs_h[2];
-  segs_h[0].ctrl_lo = ((uint64_t)p->batch << 34) | 0ull;
-  segs_h[0].nblocks = ceil_div(n * k, 256);
-  segs_h[0].word_off = 0;
-  segs_h[1].ctrl_lo = ((uint64_t)p->batch << 34) | 1ull;
-  segs_h[1].nblocks = ceil_div(m * k, 256);
-  segs_h[1].word_off = 4 * segs_h[0].nblocks + 4;
-  const int64_t words = segs_h[1].word_off + 4 * segs_h[1].nblocks + 4;
-  const int64_t pre[3] = {0, segs_h[0].nblocks, segs_h[0].nblocks + segs_h[1].nblocks};
-  SignSeg* segs;
-  int64_t* prefix;
-  uint64_t* sw;
-  MFE_CHECK(B.alloc(&segs, 2));
-  MFE_CHECK(B.alloc(&prefix, 3));
-  MFE_CHECK(B.alloc(&sw, words));
-  MFE_HIP(hipMemcpyAsync(segs, segs_h, sizeof segs_h, hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemcpyAsync(prefix, pre, sizeof pre, hipMemcpyHostToDevice, st));
-  MFE_HIP(hipMemsetAsync(sw, 0, sizeof(uint64_t) * words, st));
   MFE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
 
   const uint16_t* Ad = (const uint16_t*)A->data;
@@ -353,35 +455,24 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   MFE_HIP(hipEventCreate(&e0));
   MFE_HIP(hipEventCreate(&e1));
   MFE_HIP(hipEventRecord(e0, st));
+  const int64_t groups_u = ceil_div(RBu, kWaves * kRW), groups_v = ceil_div(RBv, kWaves * kRW);
+  const int64_t probe_wgs = ceil_div(KCv, kProbeChunks) + ceil_div(KCu, kProbeChunks);
   for (int t = 1; t <= p->steps; ++t) {
-    SignGenDev g;
-    g.segs = segs;
-    g.seg_prefix = prefix;
-    g.nseg = 2;
-    g.nblocks = pre[2];
-    g.seed = p->seed;
-    g.step = (uint64_t)t;
-    g.out = sw;
-    MFE_CHECK(launch_signgen(g, st));
     const int cur = t & 1, prev = cur ^ 1;
-    // probe operands from the scales of step t-1 (Jacobi order)
-    k_probe_tiles<<<dim3((unsigned)ceil_div(KCu * NB * 64, 256)), dim3(256), 0, st>>>(sv[prev], sw, n, k, KCu, NB, pu);
-    k_probe_tiles<<<dim3((unsigned)ceil_div(KCv * NB * 64, 256)), dim3(256), 0, st>>>(
-        su[prev], sw + segs_h[1].word_off, m, k, KCv, NB, pv);
+    // probe operands from the scales of step t-1 (Jacobi order): the row pass takes the
+    // column scales and side-0 signs, the column pass the row scales and side-1 signs
+    ProbeSide P0{sv[prev], n, KCu, stream_ctrl((uint64_t)p->batch, (uint64_t)t, 0), scu, sgu, ceil_div(KCu, kProbeChunks)};
+    ProbeSide P1{su[prev], m, KCv, stream_ctrl((uint64_t)p->batch, (uint64_t)t, 1), scv, sgv, ceil_div(KCv, kProbeChunks)};
+    k_probe_build<<<dim3((unsigned)probe_wgs), dim3(256), 0, st>>>(P0, P1, k, NB, p->seed);
     StepScalars sc;
     sc.tau = (double)t + (double)p->t0;
     sc.eta = 2.0 / (p->gamma * (sc.tau + 1.0));
     sc.gamma = p->gamma;
     sc.M = p->box_M;
-    Bf16Side R{tu, pu, m, RBu, KCu, Su, partu, u, ub, su[cur], p->alpha * p->alpha};
-    Bf16Side Cc{tv, pv, n, RBv, KCv, Sv, partv, v, vb, sv[cur], p->beta * p->beta};
-    if (NB == 1) {
-      launch_pass<1>(R, k, sc, flag, st);
-      launch_pass<1>(Cc, k, sc, flag, st);
-    } else {
-      launch_pass<2>(R, k, sc, flag, st);
-      launch_pass<2>(Cc, k, sc, flag, st);
-    }
+    Bf16Side R{tu, scu, sgu, m, RBu, KCu, Su, groups_u, partu, u, ub, su[cur], p->alpha * p->alpha};
+    Bf16Side Cc{tv, scv, sgv, n, RBv, KCv, Sv, groups_v, partv, v, vb, sv[cur], p->beta * p->beta};
+    if (NB == 1) launch_step<1>(R, Cc, k, sc, flag, st);
+    else launch_step<2>(R, Cc, k, sc, flag, st);
   }
   MFE_HIP(hipGetLastError());
   MFE_HIP(hipEventRecord(e1, st));
