@@ -14,9 +14,10 @@
 // layout (lane l holds probe 32 nb + l%32 at the same 8 k values), but is not stored as
 // a tile: per k chunk the pass loads the 16 bf16
 // scales and one sign byte per (probe, half chunk), 32 + 64 NB bytes, and assembles the
-// MFMA operand in registers (sign bit XORed into each scale).  A step is three
-// launches: the probe build (Philox signs and bf16 scales of both sides), both passes
-// (rows over A, then columns over A'), and the update of both sides.
+// MFMA operand in registers (sign bit XORed into each scale).  A step is two launches:
+// both passes (rows over A, then columns over A'), and the update of both sides, which
+// also writes the bf16 scales and (extra workgroups) the Philox sign bytes of the next
+// step.  A separate probe build makes the operands of the first step.
 //
 // Work split: a workgroup of 4 wavefronts covers 4 RW consecutive 32-row blocks over one
 // k range (the k chunks are split into `splits` ranges so that a pass launches about
@@ -113,13 +114,11 @@ struct ProbeSide {
 constexpr int kProbeChunks = 4;                                       // k chunks per workgroup
 constexpr int kProbeBlocks = kProbeChunks * kChunk * 64 / 256 + 2;  // Philox blocks per workgroup (K <= 64)
 
-// One launch for both sides: the workgroup draws the Philox blocks that hold the sign
-// bits of its 64 indices into LDS, then writes its chunks' scales and sign bytes.
-__global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1, int K, int NB, uint64_t seed) {
-  __shared__ uint64_t words[4 * kProbeBlocks];
-  const bool first = blockIdx.x < P0.groups;
-  const ProbeSide& P = first ? P0 : P1;
-  const int64_t grp = first ? blockIdx.x : blockIdx.x - P0.groups;
+// One workgroup of the probe build: draws the Philox blocks that hold the sign bits of
+// its 64 indices into LDS, then writes its chunks' sign bytes and, when P.scale is set,
+// their bf16 scales.  Called by every thread of the workgroup.
+__device__ __forceinline__ void probe_group(const ProbeSide& P, int64_t grp, int K, int NB, uint64_t seed,
+                                            uint64_t* words) {
   const int64_t kk0 = grp * kProbeChunks * kChunk;
   const int64_t kk1 = kk0 + kProbeChunks * kChunk < P.C ? kk0 + kProbeChunks * kChunk : P.C;
   const int64_t c0 = (kk0 * K) >> 8;  // first Philox block
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1,
 #pragma unroll
     for (int q = 0; q < 4; ++q) words[4 * i + q] = w.x[q];
   }
-  if (threadIdx.x < kProbeChunks * kChunk) {
+  if (P.scale && threadIdx.x < kProbeChunks * kChunk) {
     const int64_t kk = kk0 + threadIdx.x;
     if (kk < P.KC * kChunk) P.scl[kk] = kk < P.C ? bf16_rne(P.scale[kk]) : (uint16_t)0;
   }
@@ -157,6 +156,13 @@ __global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1,
   }
 }
 
+// Probe operands of the first step for both sides (scales from the initial iterates).
+__global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1, int K, int NB, uint64_t seed) {
+  __shared__ uint64_t words[4 * kProbeBlocks];
+  const bool first = blockIdx.x < P0.groups;
+  probe_group(first ? P0 : P1, first ? blockIdx.x : blockIdx.x - P0.groups, K, NB, seed, words);
+}
+
 struct Bf16Side {
   const u32x4* tiles;   // [RB][KC][64]
   const uint16_t* scl;  // probe operands, compressed (see ProbeSide)
@@ -167,7 +173,7 @@ struct Bf16Side {
   float* part;          // [splits][RB * 32][32 NB] partial products
   double* x;
   double* xbar;
-  double* scale_out;
+  uint16_t* scl_out;    // bf16 e^x of this side: the other pass's probe scales next step
   double target;
 };
 
@@ -292,45 +298,79 @@ __global__ __launch_bounds__(kWaves * 64) void k_bf16_pass(Bf16Side R, Bf16Side 
   else bf16_pass<NB, RW, F>(C, (b - nr) % C.groups, (int)((b - nr) / C.groups));
 }
 
+// Sum over the eight lanes of an aligned group (every lane gets the sum).
+__device__ __forceinline__ double octet_sum(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]: pairs
+  v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]: quads
+  v += dpp_mov<0x141>(v);  // row_half_mirror: groups of 8
+  return v;
+}
+
+// Index r with eight lanes: lane j of the eight adds the ranges of probes
+// 4 NB j .. 4 NB j + 4 NB - 1 in FP64 (in range order), the squares of the probes p < k
+// are summed across the eight lanes, and lane 0 of the eight updates the iterate.
 template <int NB>
-__device__ __forceinline__ void bf16_update(const Bf16Side& S, int64_t r, int k, const StepScalars& sc, int* flag) {
-  const int lane = threadIdx.x & 63;
-  if (r >= S.R) return;  // whole wavefronts leave together
-  const int64_t stride = S.RB * kRows * 32 * NB;
-  double y = 0.0;
-  if (lane < 32 * NB && lane < k) {
-    // eight ranges' loads in flight at a time, added in range order
-    const float* __restrict__ base = S.part + r * 32 * NB + lane;
-    for (int s0 = 0; s0 < S.splits; s0 += 8) {
-      float q[8];
+__device__ __forceinline__ void bf16_update(const Bf16Side& S, int64_t r, int j, int k, const StepScalars& sc,
+                                            int* flag) {
+  constexpr int PPL = 4 * NB;  // probes per lane
+  const bool live = r < S.R;
+  double ss = 0.0;
+  if (live) {
+    const int64_t stride = S.RB * kRows * 32 * NB / 4;  // float4 units
+    const float4* __restrict__ base = (const float4*)(S.part + r * 32 * NB + j * PPL);
+    double y[PPL];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) q[j] = s0 + j < S.splits ? base[(int64_t)(s0 + j) * stride] : 0.f;
+    for (int i = 0; i < PPL; ++i) y[i] = 0.0;
+    // four ranges' loads in flight at a time, added in range order
+    for (int s0 = 0; s0 < S.splits; s0 += 4) {
+      float4 q[4][NB];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (s0 + j < S.splits) y += (double)q[j];
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          q[u][b] = s0 + u < S.splits ? base[(int64_t)(s0 + u) * stride + b] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (s0 + u >= S.splits) break;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          y[4 * b + 0] += (double)q[u][b].x;
+          y[4 * b + 1] += (double)q[u][b].y;
+          y[4 * b + 2] += (double)q[u][b].z;
+          y[4 * b + 3] += (double)q[u][b].w;
+        }
+      }
     }
+#pragma unroll
+    for (int i = 0; i < PPL; ++i)
+      if (j * PPL + i < k) ss += y[i] * y[i];
   }
-  const double ss = wave_sum(y * y);
-  if (lane == 0) {
+  ss = octet_sum(ss);
+  if (live && j == 0) {
     double x = S.x[r], xb = S.xbar[r];
     if (!sgd_update(ss, k, S.target, sc, x, xb)) atomicOr(flag, 1);
     S.x[r] = x;
     S.xbar[r] = xb;
-    S.scale_out[r] = exp(x);
+    S.scl_out[r] = bf16_rne(exp(x));
   }
 }
 
-// Update of every index of both sides from the FP32 partials: one wavefront per index,
-// lane p adds the ranges of probe p in FP64 (coalesced over the probes), the squares are
-// summed across the wavefront, and lane 0 updates the iterate.  Workgroups
-// b < ceil(R.R / 4) take the rows.
+// Update of every index of both sides from the FP32 partials, 32 indices per workgroup
+// (workgroups b < ceil(R.R / 32) take the rows), followed by the workgroups that write
+// the sign bytes of the next step (they depend on the step only, and the passes of this
+// step have finished reading the current ones).
 template <int NB>
-__global__ __launch_bounds__(256) void k_bf16_update(Bf16Side R, Bf16Side C, int k, StepScalars sc, int* flag) {
-  const int64_t rw = (R.R + 3) / 4;
+__global__ __launch_bounds__(256) void k_bf16_update(Bf16Side R, Bf16Side C, int k, StepScalars sc, int* flag,
+                                                     ProbeSide N0, ProbeSide N1, uint64_t seed) {
+  __shared__ uint64_t words[4 * kProbeBlocks];
+  const int64_t rw = (R.R + 31) / 32, cw = (C.R + 31) / 32;
   const int64_t b = blockIdx.x;
-  const int64_t w = threadIdx.x >> 6;
-  if (b < rw) bf16_update<NB>(R, b * 4 + w, k, sc, flag);
-  else bf16_update<NB>(C, (b - rw) * 4 + w, k, sc, flag);
+  const int64_t i = threadIdx.x >> 3;
+  const int j = threadIdx.x & 7;
+  if (b < rw) bf16_update<NB>(R, b * 32 + i, j, k, sc, flag);
+  else if (b < rw + cw) bf16_update<NB>(C, (b - rw) * 32 + i, j, k, sc, flag);
+  else if (b < rw + cw + N0.groups) probe_group(N0, b - rw - cw, k, NB, seed, words);
+  else probe_group(N1, b - rw - cw - N0.groups, k, NB, seed, words);
 }
 
 __global__ void k_bf_init(int64_t cnt, const double* __restrict__ x0, double M, double* __restrict__ x,
@@ -386,12 +426,15 @@ struct Bufs {
 constexpr int kRW = MFE_BF16_RW;   // row blocks per wavefront
 constexpr int kF = MFE_BF16_F;     // chunks per load group (two groups in flight)
 
+// One step: both passes, then the updates with the sign bytes of the next step (none
+// after the last step: N0.groups = N1.groups = 0).
 template <int NB>
-void launch_step(const Bf16Side& R, const Bf16Side& C, int k, const StepScalars& sc, int* flag, hipStream_t st) {
+void launch_step(const Bf16Side& R, const Bf16Side& C, int k, const StepScalars& sc, int* flag,
+                 const ProbeSide& N0, const ProbeSide& N1, uint64_t seed, hipStream_t st) {
   const int64_t wgs = R.groups * R.splits + C.groups * C.splits;
   k_bf16_pass<NB, kRW, kF><<<dim3((unsigned)wgs), dim3(kWaves * 64), 0, st>>>(R, C);
-  const int64_t ub = ceil_div(R.R, 4) + ceil_div(C.R, 4);
-  k_bf16_update<NB><<<dim3((unsigned)ub), dim3(256), 0, st>>>(R, C, k, sc, flag);
+  const int64_t ub = ceil_div(R.R, 32) + ceil_div(C.R, 32) + N0.groups + N1.groups;
+  k_bf16_update<NB><<<dim3((unsigned)ub), dim3(256), 0, st>>>(R, C, k, sc, flag, N0, N1, seed);
 }
 
 // k ranges per row block: about MFE_BF16_WG workgroups (of kWaves * kRW row blocks) per
@@ -420,7 +463,7 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   u32x4 *tu, *tv;
   uint16_t *scu, *scv;
   uint8_t *sgu, *sgv;
-  double *u, *ub, *v, *vb, *su[2], *sv[2];
+  double *u, *ub, *v, *vb, *su, *sv;
   int* flag;
   MFE_CHECK(B.alloc(&tu, RBu * KCu * 64));
   MFE_CHECK(B.alloc(&tv, RBv * KCv * 64));
@@ -433,10 +476,8 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   MFE_CHECK(B.alloc(&ub, m));
   MFE_CHECK(B.alloc(&v, n));
   MFE_CHECK(B.alloc(&vb, n));
-  for (int i = 0; i < 2; ++i) {
-    MFE_CHECK(B.alloc(&su[i], m));
-    MFE_CHECK(B.alloc(&sv[i], n));
-  }
+  MFE_CHECK(B.alloc(&su, m));  // initial scales e^x (FP64), read by the first probe build
+  MFE_CHECK(B.alloc(&sv, n));
   MFE_CHECK(B.alloc(&flag, 1));
   const int Su = bf16_splits(RBu, KCu), Sv = bf16_splits(RBv, KCv);
   float *partu, *partv;
@@ -447,8 +488,8 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   const uint16_t* Ad = (const uint16_t*)A->data;
   k_tile<<<dim3((unsigned)ceil_div(RBu * KCu * 64, 256)), dim3(256), 0, st>>>(Ad, m, n, A->ld, 0, RBu, KCu, tu);
   k_tile<<<dim3((unsigned)ceil_div(RBv * KCv * 64, 256)), dim3(256), 0, st>>>(Ad, m, n, A->ld, 1, RBv, KCv, tv);
-  k_bf_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, su[0], flag);
-  k_bf_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv[0], flag);
+  k_bf_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, su, flag);
+  k_bf_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv, flag);
   MFE_HIP(hipGetLastError());
 
   hipEvent_t e0, e1;
@@ -456,23 +497,30 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   MFE_HIP(hipEventCreate(&e1));
   MFE_HIP(hipEventRecord(e0, st));
   const int64_t groups_u = ceil_div(RBu, kWaves * kRW), groups_v = ceil_div(RBv, kWaves * kRW);
-  const int64_t probe_wgs = ceil_div(KCv, kProbeChunks) + ceil_div(KCu, kProbeChunks);
+  const int64_t pg_u = ceil_div(KCu, kProbeChunks), pg_v = ceil_div(KCv, kProbeChunks);
+  const uint64_t bt = (uint64_t)p->batch;
+  // probe operands of step 1 from the initial scales (Jacobi order): the row pass takes
+  // the column scales and side-0 signs, the column pass the row scales and side-1 signs;
+  // later steps get their scales from the updates and their sign bytes from the update
+  // launch of the step before
+  if (p->steps > 0) {
+    ProbeSide P0{sv, n, KCu, stream_ctrl(bt, 1, 0), scu, sgu, pg_u};
+    ProbeSide P1{su, m, KCv, stream_ctrl(bt, 1, 1), scv, sgv, pg_v};
+    k_probe_build<<<dim3((unsigned)(pg_u + pg_v)), dim3(256), 0, st>>>(P0, P1, k, NB, p->seed);
+  }
   for (int t = 1; t <= p->steps; ++t) {
-    const int cur = t & 1, prev = cur ^ 1;
-    // probe operands from the scales of step t-1 (Jacobi order): the row pass takes the
-    // column scales and side-0 signs, the column pass the row scales and side-1 signs
-    ProbeSide P0{sv[prev], n, KCu, stream_ctrl((uint64_t)p->batch, (uint64_t)t, 0), scu, sgu, ceil_div(KCu, kProbeChunks)};
-    ProbeSide P1{su[prev], m, KCv, stream_ctrl((uint64_t)p->batch, (uint64_t)t, 1), scv, sgv, ceil_div(KCv, kProbeChunks)};
-    k_probe_build<<<dim3((unsigned)probe_wgs), dim3(256), 0, st>>>(P0, P1, k, NB, p->seed);
     StepScalars sc;
     sc.tau = (double)t + (double)p->t0;
     sc.eta = 2.0 / (p->gamma * (sc.tau + 1.0));
     sc.gamma = p->gamma;
     sc.M = p->box_M;
-    Bf16Side R{tu, scu, sgu, m, RBu, KCu, Su, groups_u, partu, u, ub, su[cur], p->alpha * p->alpha};
-    Bf16Side Cc{tv, scv, sgv, n, RBv, KCv, Sv, groups_v, partv, v, vb, sv[cur], p->beta * p->beta};
-    if (NB == 1) launch_step<1>(R, Cc, k, sc, flag, st);
-    else launch_step<2>(R, Cc, k, sc, flag, st);
+    const bool more = t < p->steps;
+    ProbeSide N0{nullptr, n, KCu, stream_ctrl(bt, (uint64_t)t + 1, 0), scu, sgu, more ? pg_u : 0};
+    ProbeSide N1{nullptr, m, KCv, stream_ctrl(bt, (uint64_t)t + 1, 1), scv, sgv, more ? pg_v : 0};
+    Bf16Side R{tu, scu, sgu, m, RBu, KCu, Su, groups_u, partu, u, ub, scv, p->alpha * p->alpha};
+    Bf16Side Cc{tv, scv, sgv, n, RBv, KCv, Sv, groups_v, partv, v, vb, scu, p->beta * p->beta};
+    if (NB == 1) launch_step<1>(R, Cc, k, sc, flag, N0, N1, p->seed, st);
+    else launch_step<2>(R, Cc, k, sc, flag, N0, N1, p->seed, st);
   }
   MFE_HIP(hipGetLastError());
   MFE_HIP(hipEventRecord(e1, st));
