@@ -104,6 +104,41 @@ def test_bf16_one_step_within_rounding_bound(m, n, k):
     _say(f"bf16 {m}x{n} k={k}: worst error / bound = {worst:.3f}")
 
 
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (1, 40, 7), (40, 1, 64), (17, 3, 33), (31, 17, 64)])
+def test_bf16_degenerate_shapes_one_step(m, n, k):
+    """Single rows or columns and shapes smaller than one tile (32 x 16) or one probe
+    block: one step from oracle states within the rounding bound."""
+    A = scaled_dense(m, n, 3.0, 500 + k)
+    D, Ab = _bf16(A)
+    al, be = A1.default_alpha_beta(m, n)
+    states = {0: (np.zeros(m), np.zeros(n))}
+    A1.equilibrate(Ab, al, be, 0.1, 10.0, 5, k=k, seed=9,
+                   on_step=lambda t, u, v, ub, vb: states.__setitem__(t, (u.copy(), v.copy())))
+    worst = _one_step_check(D, Ab, {t: states[t] for t in (0, 2, 5)}, k, 23, al, be)
+    _say(f"bf16 {m}x{n} k={k}: worst error / bound = {worst:.3f}")
+
+
+def test_bf16_zero_steps_and_warm_start():
+    """steps = 0 returns u_bar = u0, v_bar = v0 exactly and d = e^u0, e = e^v0 (to the
+    last bit of FP64 exp); a warm start outside the box is rejected."""
+    from paper_1602_06621_amd import MfeError, equilibrate
+
+    A = scaled_dense(70, 50, 3.0, 77)
+    D, _ = _bf16(A)
+    rng = np.random.default_rng(5)
+    u0, v0 = rng.uniform(-2, 2, 70), rng.uniform(-2, 2, 50)
+    g = equilibrate(D, 1.0, 1.0, 0.1, 10.0, 0, 8, 3, u0=torch.tensor(u0, device="cuda"),
+                    v0=torch.tensor(v0, device="cuda"))
+    assert np.array_equal(g["u_bar"].cpu().numpy(), u0) and np.array_equal(g["v_bar"].cpu().numpy(), v0)
+    assert np.allclose(g["d"].cpu().numpy(), np.exp(u0), rtol=4e-16, atol=0)
+    assert np.allclose(g["e"].cpu().numpy(), np.exp(v0), rtol=4e-16, atol=0)
+    bad = u0.copy()
+    bad[3] = 11.0
+    with pytest.raises(MfeError):
+        equilibrate(D, 1.0, 1.0, 0.1, 10.0, 5, 8, 3, u0=torch.tensor(bad, device="cuda"),
+                    v0=torch.tensor(v0, device="cuda"))
+
+
 def test_bf16_exact_products():
     """+-1 and power-of-two entries with u = v = 0: every product is exact in bf16 and
     FP32, so one GPU step equals the oracle's step up to the FP64 epilogue."""
