@@ -395,6 +395,15 @@ __global__ void k_bf_output(int64_t cnt, const double* __restrict__ xbar, double
   if (xbar_out) xbar_out[i] = xbar[i];
 }
 
+// Timing events released on every return path.
+struct Events {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~Events() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 struct Bufs {
   std::vector<void*> p;
   ~Bufs() {
@@ -492,10 +501,10 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   k_bf_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv, flag);
   MFE_HIP(hipGetLastError());
 
-  hipEvent_t e0, e1;
-  MFE_HIP(hipEventCreate(&e0));
-  MFE_HIP(hipEventCreate(&e1));
-  MFE_HIP(hipEventRecord(e0, st));
+  Events ev;
+  MFE_HIP(hipEventCreate(&ev.e0));
+  MFE_HIP(hipEventCreate(&ev.e1));
+  MFE_HIP(hipEventRecord(ev.e0, st));
   const int64_t groups_u = ceil_div(RBu, kWaves * kRW), groups_v = ceil_div(RBv, kWaves * kRW);
   const int64_t pg_u = ceil_div(KCu, kProbeChunks), pg_v = ceil_div(KCv, kProbeChunks);
   const uint64_t bt = (uint64_t)p->batch;
@@ -523,7 +532,7 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
     else launch_step<2>(R, Cc, k, sc, flag, N0, N1, p->seed, st);
   }
   MFE_HIP(hipGetLastError());
-  MFE_HIP(hipEventRecord(e1, st));
+  MFE_HIP(hipEventRecord(ev.e1, st));
   k_bf_output<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, ub, d, u_bar);
   k_bf_output<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, vb, e, v_bar);
   MFE_HIP(hipGetLastError());
@@ -531,9 +540,7 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   MFE_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   MFE_HIP(hipStreamSynchronize(st));
   float ms = 0.f;
-  MFE_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  MFE_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   record_timing(ms, p->steps > 0 ? ms / p->steps : 0.0);
   if (h & 2) return set_error(MFE_EINVAL, "warm start u0/v0 outside the box [-M, M] (or NaN)");
   if (h & 1) return set_error(MFE_ENONFINITE, "non-finite gradient estimate or iterate (NaN/Inf in A?)");
