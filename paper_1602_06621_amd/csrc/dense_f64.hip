@@ -290,10 +290,18 @@ __global__ __launch_bounds__(kPersistThreads) void k_dense_persistent(PersistArg
   }
 }
 
+// v from lane l ^ 16 (within each half of the wavefront), by ds_swizzle in bit mode.
+__device__ __forceinline__ double swizzle_xor16(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Register-resident variant, k = 1, m <= 8 kTinyRM, n <= 64 kTinyCM.  Row sums: each
-// lane sums its kTinyCM entries of a row, the wavefront reduces.  Column sums: each
-// wavefront sums its kTinyRM rows per column into LDS, then one thread per column adds
-// the 8 wavefront partials.
+// lane sums its kTinyCM entries of a row, and the wavefront reduces 16 rows at a time
+// by halving exchanges.  Column sums: each wavefront sums its kTinyRM rows per column
+// into LDS, then one thread per column adds the 8 wavefront partials.
 __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
   constexpr int NR = kTinyWaves * kTinyRM, NC = 64 * kTinyCM;
   __shared__ double sr[2][NR], scl[2][NC], xu[NR], xub[NR], xv[NC], xvb[NC];
@@ -342,55 +350,89 @@ __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
       cacc[c] = 0.0;
     }
     __syncthreads();
+    // Row sums, 16 rows at a time: each lane's partials of the 16 rows are reduced over
+    // the wavefront by halving exchanges (lane bit 5, 4, 3, 2: the lane keeps the half of
+    // the rows selected by its bit and adds its partner's partials of that half), after
+    // which lane l holds rows (l >> 2) & 15 summed over the 16 lanes that share bits 2-5,
+    // and two more exchanges (bits 1, 0) complete the sums in all four lanes of a quad.
+    // Quad lane 0 keeps batch 0's sum (rows 0-15), quad lane 1 batch 1's (rows 16-24).
     double ss = 0.0;
 #pragma unroll
-    for (int r0 = 0; r0 < kTinyRM; r0 += 4) {
-      double racc[4];
+    for (int b = 0; b < 2; ++b) {
+      double v[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        racc[q] = 0.0;
-        const int r = r0 + q, i = w + kTinyWaves * r;
+      for (int q = 0; q < 16; ++q) {
+        const int r = 16 * b + q, i = w + kTinyWaves * r;
+        v[q] = 0.0;
         if (r < kTinyRM && i < m) {
           const double gi = gsr[i];
 #pragma unroll
           for (int c = 0; c < kTinyCM; ++c) {
-            racc[q] += Ar[r][c] * gsj[c];
+            v[q] += Ar[r][c] * gsj[c];
             cacc[c] += Ar[r][c] * gi;
           }
         }
       }
+      const bool b5 = l & 32, b4 = l & 16, b3 = l & 8, b2 = l & 4;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double send = b5 ? v[q] : v[q + 8], keep = b5 ? v[q + 8] : v[q];
+        v[q] = keep + __shfl_xor(send, 32);
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (r0 + q < kTinyRM) {
-          double v = racc[q];
-          v = wave_sum(v);
-          if (l == r0 + q) ss = v * v;
-        }
+        const double send = b4 ? v[q] : v[q + 4], keep = b4 ? v[q + 4] : v[q];
+        v[q] = keep + swizzle_xor16(send);
       }
-    }
-    {
-      const int i = w + kTinyWaves * l;
-      if (l < kTinyRM && i < m) {
-        double xi = xu[i], xb = xub[i];
-        if (!sgd_update(ss, 1, a.tgt_row, sc, xi, xb)) atomicOr(a.flag, 1);
-        xu[i] = xi;
-        xub[i] = xb;
-        sr[cur][i] = exp(xi);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double send = b3 ? v[q] : v[q + 2], keep = b3 ? v[q + 2] : v[q];
+        v[q] = keep + dpp_mov<0x140>(send);  // row_mirror: partner differs in bit 3
       }
+      {
+        const double send = b2 ? v[0] : v[1], keep = b2 ? v[1] : v[0];
+        v[0] = keep + dpp_mov<0x141>(send);  // row_half_mirror: partner differs in bit 2
+      }
+      v[0] += dpp_mov<0x4E>(v[0]);  // quad_perm [2, 3, 0, 1]
+      v[0] += dpp_mov<0xB1>(v[0]);  // quad_perm [1, 0, 3, 2]
+      if ((l & 3) == b) ss = v[0] * v[0];
     }
 #pragma unroll
     for (int c = 0; c < kTinyCM; ++c) part[w][l + 64 * c] = cacc[c];
     if (tid < a.wps && s + 1 < a.nsteps) words[prev][tid] = next;
     __syncthreads();
-    for (int j = tid; j < n; j += kTinyThreads) {
-      double y = 0.0;
+    // Both sides' updates in one code path: rows on quad lanes 0 and 1 (the lanes that
+    // hold their sums), columns on quad lanes 2 and 3 (the sum of the 8 wavefront
+    // partials, in wavefront order), so the exp / divide chain of the update is paid once.
+    {
+      const int quad = l & 3;
+      const bool is_row = quad < 2;
+      int idx;
+      bool live;
+      if (is_row) {
+        const int r = (quad == 1 ? 16 : 0) + (l >> 2);
+        idx = w + kTinyWaves * r;
+        live = r < kTinyRM && idx < m;
+      } else {
+        idx = w * 32 + (l >> 2) * 2 + (quad - 2);
+        live = idx < n;
+        if (live) {
+          double y = 0.0;
 #pragma unroll
-      for (int q = 0; q < kTinyWaves; ++q) y += part[q][j];
-      double xj = xv[j], xb = xvb[j];
-      if (!sgd_update(y * y, 1, a.tgt_col, sc, xj, xb)) atomicOr(a.flag, 1);
-      xv[j] = xj;
-      xvb[j] = xb;
-      scl[cur][j] = exp(xj);
+          for (int q = 0; q < kTinyWaves; ++q) y += part[q][idx];
+          ss = y * y;
+        }
+      }
+      if (live) {
+        double* xs = is_row ? xu : xv;
+        double* xbs = is_row ? xub : xvb;
+        double* out = is_row ? sr[cur] : scl[cur];
+        double xi = xs[idx], xb = xbs[idx];
+        if (!sgd_update(ss, 1, is_row ? a.tgt_row : a.tgt_col, sc, xi, xb)) atomicOr(a.flag, 1);
+        xs[idx] = xi;
+        xbs[idx] = xb;
+        out[idx] = exp(xi);
+      }
     }
     __syncthreads();
   }
