@@ -103,7 +103,7 @@ __global__ void k_tile(const uint16_t* __restrict__ A, int64_t m, int64_t n, int
 // of the library's sign words); zero for p >= K or past the end.  Per chunk that is
 // 32 + 64 NB bytes instead of the 1 KiB operand tile per 32 probes.
 struct ProbeSide {
-  const double* scale;  // e^x of the indices of this side, step t-1
+  const double* scale;  // e^x of the indices of this side (first step), or null: sign bytes only
   int64_t C, KC;        // indices, k chunks
   uint64_t ctrl;        // Philox key word: (batch << 34) | (t << 2) | side
   uint16_t* scl;        // [KC * 16]
