@@ -189,8 +189,9 @@ def bench_c4(mfe):
 
     k, gamma, every, rel = 16, GAMMA, 5, 1.2
     rec = {"workload": "learned warm start: 3-layer MLP width 64 (FP32) on 4-probe sketch features; "
-                       "eval csr_f32 200000x100000, U{8..16} nnz/row, sigma=2; k=16; target = 1.2 x the "
-                       "residual of the plain run after 3000 steps"}
+                       "eval csr_f32 200000x100000, U{8..16} nnz/row, sigma=2 (more_eval: sigma 0.5, 1.5, 3); "
+                       "k=16; target = 1.2 x the residual of the plain run after 3000 steps (also: the plain "
+                       "run's residual after 1000 steps); arms: plain, plain with its best t0, sketch, mlp"}
     t0 = time.time()
     train = warmstart_training_set(32, 31, m_lo=10_000, m_hi=100_000)
     rec["train_matrices"] = len(train)
@@ -216,67 +217,102 @@ def bench_c4(mfe):
     rec["train_loss_first_last"] = [float(loss[:20].mean()), float(loss[-20:].mean())]
     rec["target_var"] = float(t.var())
 
-    # step offsets tuned on a training-distribution matrix, never on the evaluation one
+    # step offsets tuned on a training-distribution matrix, never on the evaluation ones
     tm = warmstart_matrix(100_000, 50_000, 2.0, 4242)
     al, be = mfe.default_alpha_beta(tm.m, tm.n)
     with mfe.Plan([mfe.Csr.from_arrays(tm.m, tm.n, tm.row_ptr, tm.col_idx, tm.val, device="cuda:0")],
                   max_probes=k) as plan:
         t0_mlp, sweep_mlp = W.tune_t0(plan, params, 5, al, be, learned=True, seed=12)
         t0_sk, sweep_sk = W.tune_t0(plan, params, 5, al, be, learned=False, seed=12)
-    rec["t0"] = {"mlp": t0_mlp, "sketch": t0_sk, "sweep_mlp": sweep_mlp, "sweep_sketch": sweep_sk}
+        t0_pl, sweep_pl = tune_plain_t0(plan, al, be, k, gamma, every, rel, seed=12)
+    rec["t0"] = {"mlp": t0_mlp, "sketch": t0_sk, "plain_t0": t0_pl, "sweep_mlp": sweep_mlp,
+                 "sweep_sketch": sweep_sk, "sweep_plain": sweep_pl}
+    # arm -> (t0, warm start: None = zero, False = sketch, True = network)
+    arms = {"plain": (0, None), "plain_t0": (t0_pl, None), "sketch": (t0_sk, False), "mlp": (t0_mlp, True)}
 
-    c = warmstart_matrix(200_000, 100_000, 2.0, 9001)
-    al, be = mfe.default_alpha_beta(c.m, c.n)
-    Ac = mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0")
-    with mfe.Plan([Ac], max_probes=k) as plan:
-        _, plain = plan.equilibrate_trace(al, be, gamma, BOX_M, 3000, k, 11, trace_every=every)
-        target = rel * float(plain[-1])
-        arms = {"plain": (0, None), "sketch": (t0_sk, False), "mlp": (t0_mlp, True)}
-        steps = {"plain": W.steps_to_residual(plain, target, every)}
-        for name in ("sketch", "mlp"):
-            u0, v0 = W.warm_start(plan, params, 5, learned=arms[name][1])
-            _, tr = plan.equilibrate_trace(al, be, gamma, BOX_M, 3000, k, 11, t0=arms[name][0], u0=u0, v0=v0,
-                                           trace_every=every)
-            steps[name] = W.steps_to_residual(tr, target, every)
-        rec["floor"] = float(plain[-1])
-        rec["target"] = target
-        rec["steps_to_target"] = steps
+    def evaluate(c, timing):
+        """Steps of every arm to the two targets on one held-out matrix: rel x the plain
+        run's residual after 3000 steps, and the plain run's residual after 1000 steps;
+        with timing, wall-clock seconds to the first target (median of 5 graph runs)."""
+        al, be = mfe.default_alpha_beta(c.m, c.n)
+        Ac = mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0")
+        out_rec = {}
+        with mfe.Plan([Ac], max_probes=k) as plan:
+            traces = {}
+            for name, (t0a, learned) in arms.items():
+                u0 = v0 = None
+                if learned is not None:
+                    u0, v0 = W.warm_start(plan, params, 5, learned=learned)
+                _, traces[name] = plan.equilibrate_trace(al, be, gamma, BOX_M, 3000, k, 11, t0=t0a, u0=u0, v0=v0,
+                                                         trace_every=every)
+            plain = traces["plain"]
+            target = rel * float(plain[-1])
+            rho_1000 = float(plain[1000 // every - 1])
+            steps = {n: W.steps_to_residual(tr, target, every) for n, tr in traces.items()}
+            out_rec.update(floor=float(plain[-1]), target=target, steps_to_target=steps, rho_1000=rho_1000,
+                           steps_to_rho_1000={n: W.steps_to_residual(tr, rho_1000, every) for n, tr in traces.items()})
+            if not timing:
+                return out_rec
 
-        def run(name):
-            t0a, learned = arms[name]
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            if name == "plain":
-                out = plan.equilibrate(al, be, gamma, BOX_M, steps[name], k, 11, use_graph=True)
-            else:
-                u0, v0 = W.warm_start(plan, params, 5, learned=learned)
+            def run(name):
+                t0a, learned = arms[name]
+                torch.cuda.synchronize()
+                s0 = time.perf_counter()
+                u0 = v0 = None
+                if learned is not None:
+                    u0, v0 = W.warm_start(plan, params, 5, learned=learned)
                 out = plan.equilibrate(al, be, gamma, BOX_M, steps[name], k, 11, t0=t0a, u0=u0, v0=v0,
                                        use_graph=True)
-            torch.cuda.synchronize()
-            return time.perf_counter() - s0, out
+                torch.cuda.synchronize()
+                return time.perf_counter() - s0, out
 
-        secs, reached = {}, {}
-        for name in ("plain", "sketch", "mlp"):
-            if steps[name] is None:
-                continue
-            run(name)  # graph capture
-            ts = []
-            for _ in range(5):
-                s, out = run(name)
-                ts.append(s)
-            secs[name] = float(np.median(ts))
-            reached[name] = mfe.residual(Ac, out["d"], out["e"], al, be)[0]
-        rec["seconds_to_target"] = secs
-        rec["residual_reached"] = reached
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        for _ in range(10):
-            W.warm_start(plan, params, 5)
-        torch.cuda.synchronize()
-        rec["warm_start_ms"] = (time.perf_counter() - s0) * 100
+            secs, reached = {}, {}
+            for name in arms:
+                if steps[name] is None:
+                    continue
+                run(name)  # graph capture
+                ts = []
+                for _ in range(5):
+                    s, out = run(name)
+                    ts.append(s)
+                secs[name] = float(np.median(ts))
+                reached[name] = mfe.residual(Ac, out["d"], out["e"], al, be)[0]
+            out_rec["seconds_to_target"] = secs
+            out_rec["residual_reached"] = reached
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for _ in range(10):
+                W.warm_start(plan, params, 5)
+            torch.cuda.synchronize()
+            out_rec["warm_start_ms"] = (time.perf_counter() - s0) * 100
+        return out_rec
+
+    rec.update(evaluate(warmstart_matrix(200_000, 100_000, 2.0, 9001), timing=True))
+    secs = rec.get("seconds_to_target", {})
     if "plain" in secs and "mlp" in secs:
         rec["speedup_seconds"] = secs["plain"] / secs["mlp"]
+    if "plain_t0" in secs and "mlp" in secs:
+        rec["speedup_seconds_vs_plain_t0"] = secs["plain_t0"] / secs["mlp"]
+    # more held-out matrices across the training range of sigma (steps only)
+    rec["more_eval"] = {f"sigma={sg}": evaluate(warmstart_matrix(200_000, 100_000, sg, 3000 + i), timing=False)
+                        for i, sg in enumerate((0.5, 1.5, 3.0))}
     return rec
+
+
+def tune_plain_t0(plan, alpha, beta, k, gamma, every, rel, seed, candidates=(0, 5, 10, 20, 50, 100), steps=1500):
+    """Step offset of plain SGD from zero (u, v) that reaches rel x the t0 = 0 run's final
+    residual in the fewest steps on the plan's single (tuning) matrix."""
+    from paper_1602_06621_amd import warmstart as W
+
+    got, target = {}, None
+    for t0 in candidates:
+        _, tr = plan.equilibrate_trace(alpha, beta, gamma, BOX_M, steps, k, seed, t0=t0, trace_every=every)
+        if t0 == 0:
+            target = rel * tr[-1]
+        st = W.steps_to_residual(tr, target, every)
+        got[t0] = st if st is not None else steps + 1
+    best = min(got, key=lambda c: (got[c], c))
+    return best, got
 
 
 def bench_lsqr(mfe, plan, csr, out):
