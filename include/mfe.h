@@ -127,7 +127,8 @@ int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta);
  * two tiled copies of A, 2 x 2mn bytes of device memory, for the call's duration).
  * EINVAL: alpha, beta, gamma or M <= 0 or not finite; steps < 0; probes outside 1..256;
  * t0 < 0; a required pointer NULL.  EDIM: m or n <= 0, nnz >= 2^31, ld < n.
- * EUNSUPPORTED: CSR/dense with probes > 64, or a kind not built.
+ * EUNSUPPORTED: CSR/dense with probes > 64, MFE_DENSE_BF16 with M > 80 (e^x must stay
+ * inside the bf16 range), or a kind not built.
  * ENONFINITE: a non-finite estimate or iterate occurred (the clip would hide a NaN). */
 int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
                     double* u_bar, double* v_bar);
