@@ -91,6 +91,19 @@ def test_missing_outputs_and_dims_rejected(lib):
     assert lib.mfe_equilibrate(None, C.byref(p), dummy, dummy, None, None) == -1
 
 
+def test_bf16_limits_rejected_on_host(lib):
+    """The bf16 path refuses more than 64 probes and a box beyond the bf16 range of e^x
+    (EUNSUPPORTED) and a leading dimension below n (EDIM) before any device work."""
+    s = _csr_struct(40, 30)
+    s.kind, s.ld, s.data = 1, 30, C.c_void_p(16)
+    dummy = C.c_void_p(16)
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(_params(probes=65)), dummy, dummy, None, None) == -6
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(_params(box_M=81.0)), dummy, dummy, None, None) == -6
+    assert "M <= 80" in lib.mfe_last_error().decode()
+    s.ld = 29
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(_params()), dummy, dummy, None, None) == -2
+
+
 def test_draw_signs_argument_checks(lib):
     assert lib.mfe_draw_signs(1, -1, 1, 0, 4, C.c_void_p(16), None) == -1
     assert lib.mfe_draw_signs(1, 0, 2**32, 0, 4, C.c_void_p(16), None) == -1
