@@ -139,16 +139,18 @@ def test_bf16_zero_steps_and_warm_start():
                     v0=torch.tensor(v0, device="cuda"))
 
 
-def test_bf16_exact_products():
+@pytest.mark.parametrize("batch", [0, 7])
+def test_bf16_exact_products(batch):
     """+-1 and power-of-two entries with u = v = 0: every product is exact in bf16 and
-    FP32, so one GPU step equals the oracle's step up to the FP64 epilogue."""
+    FP32, so one GPU step equals the oracle's step up to the FP64 epilogue (also with a
+    nonzero batch index of the sign stream)."""
     from paper_1602_06621_amd import equilibrate
 
     rng = np.random.default_rng(4)
     A = rng.choice([-2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 2.0], size=(96, 80))
     D, Ab = _bf16(A)
-    g = equilibrate(D, 1.0, 1.0, 0.1, 10.0, 1, 8, 3)
-    o = A1.equilibrate(Ab, 1.0, 1.0, 0.1, 10.0, 1, k=8, seed=3)
+    g = equilibrate(D, 1.0, 1.0, 0.1, 10.0, 1, 8, 3, batch=batch)
+    o = A1.equilibrate(Ab, 1.0, 1.0, 0.1, 10.0, 1, k=8, seed=3, batch=batch)
     assert np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max() < 1e-13
     assert np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max() < 1e-13
 
