@@ -13,7 +13,8 @@ The other workloads of the build are measured under "extra" (same run, same GPU)
   c0    dense FP64 200 x 100, k = 1, T = 300 (latency case: microseconds per step)
   c2    512 uneven CSR matrices in one plan, k = 8, T = 1000, one HIP graph
   c3    dense bf16 16384 x 8192, k = 64, T = 500 on the matrix cores
-  c4    learned warm start vs plain SGD: steps and seconds to equal residual (200000 x 100000)
+  c4    learned warm start vs plain SGD (t0 = 0 and its best t0) and the sketch-only start:
+        steps and seconds to equal residual on a 200000 x 100000 matrix, steps on three more
   lsqr  LSQR on the headline matrix to 1e-6 with (d, e), with (1, e) and without
   var   Section 6 variants: per-index targets and blocks (16 rows / 8 columns) on the
         headline matrix; Algorithm 2 on a symmetric 1,000,000 x 1,000,000 matrix
