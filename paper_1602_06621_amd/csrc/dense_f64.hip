@@ -142,6 +142,7 @@ constexpr int kPersistMaxWords = 1024;                 // sign words per step (o
 // (2 wavefronts per SIMD leave each lane 256 registers).
 constexpr int kTinyThreads = 512, kTinyWaves = kTinyThreads / 64;
 constexpr int kTinyRM = 25, kTinyCM = 2;
+constexpr int kTinyStageWords = 5120;  // 40 KB of LDS
 
 struct PersistArgs {
   const double* A;   // m x n, row stride ld
@@ -307,7 +308,9 @@ __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
   __shared__ double sr[2][NR], scl[2][NC], xu[NR], xub[NR], xv[NC], xvb[NC];
   __shared__ double gsr[NR];  // (-1)^w_i e^(u_i) of the previous step, with this step's sign
   __shared__ double part[kTinyWaves][NC];
-  __shared__ uint64_t words[2][kPersistMaxWords];
+  // sign words of up to kTinyStageWords / wps steps, loaded together (a global load issued
+  // inside a step would be waited for at one of the step's barriers)
+  __shared__ uint64_t words[kTinyStageWords];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int m = (int)a.m, n = (int)a.n;
   double Ar[kTinyRM][kTinyCM];
@@ -328,13 +331,16 @@ __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
     xvb[j] = a.vb[j];
     scl[1][j] = exp(xv[j]);
   }
-  if (tid < a.wps) words[0][tid] = a.sw[tid];
+  const int per_fill = kTinyStageWords / a.wps;  // steps per staging load
   __syncthreads();
   for (int s = 0; s < a.nsteps; ++s) {
     const int cur = s & 1, prev = cur ^ 1;
-    uint64_t next = 0;
-    if (tid < a.wps && s + 1 < a.nsteps) next = a.sw[(int64_t)(s + 1) * a.wps + tid];
-    const uint64_t* w0 = words[cur];
+    if (s % per_fill == 0) {
+      const int ns = min(per_fill, a.nsteps - s);
+      for (int q = tid; q < ns * a.wps; q += kTinyThreads) words[q] = a.sw[(int64_t)s * a.wps + q];
+      __syncthreads();
+    }
+    const uint64_t* w0 = words + (s % per_fill) * a.wps;
     const uint64_t* w1 = w0 + 4 * a.nb0 + 4;
     const StepScalars sc = persist_scalars(a, s);
     // signed row scales of this step (one thread per row), then one pass over the register
@@ -399,7 +405,6 @@ __global__ __launch_bounds__(kTinyThreads) void k_dense_tiny(PersistArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < kTinyCM; ++c) part[w][l + 64 * c] = cacc[c];
-    if (tid < a.wps && s + 1 < a.nsteps) words[prev][tid] = next;
     __syncthreads();
     // Both sides' updates in one code path: rows on quad lanes 0 and 1 (the lanes that
     // hold their sums), columns on quad lanes 2 and 3 (the sum of the 8 wavefront
