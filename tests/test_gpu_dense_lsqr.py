@@ -98,6 +98,24 @@ def test_dense_whole_run_elementwise(config0, k):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("T", [300, 700])
+def test_dense_register_resident_long_run_elementwise(T):
+    """The register-resident path (200 x 100, k = 1) over 700 steps in one launch, which
+    reloads its staged sign words twice (at steps 320 and 640): with gamma = 1 the
+    iteration contracts rounding differences (the oracle's own u_bar moves by 5e-15 under
+    1e-16 perturbations of z, and by 0.08 with another seed), so the whole run is compared
+    elementwise."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(200, 100, 1.0, 1000)
+    al, be = A1.default_alpha_beta(200, 100)
+    g = equilibrate(_dense(A), al, be, 1.0, 10.0, T, 1, 2000)
+    o = A1.equilibrate(A, al, be, 1.0, 10.0, T, k=1, seed=2000)
+    err = max(np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max(), np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max())
+    _say(f"register-resident k=1 gamma=1 T={T}: max error {err:.3e}")
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("m,n,k", [(1700, 38, 16), (1500, 170, 4), (3500, 18, 16), (3000, 700, 4)])
 def test_dense_one_step_maps_persistent_limit_and_multi_launch(m, n, k):
     """Small dense matrices run all steps in one persistent workgroup: (1700, 38, k = 16)
