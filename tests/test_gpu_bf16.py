@@ -55,6 +55,25 @@ def test_bf16_whole_run(m, n, k, T):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("m,n,k,T,sigma", [(1024, 512, 64, 300, 3.0), (300, 170, 16, 600, 3.0),
+                                           (1000, 333, 40, 300, 1.0)])
+def test_bf16_whole_run_without_chaos(m, n, k, T, sigma):
+    """With gamma = 1 the iteration contracts perturbations, so a whole run stays within
+    the bf16 path's per-step arithmetic error of the oracle on the rounded matrix
+    (measured 1.8e-4 to 1.9e-3) while the oracle with another seed lands 2.4e-2 to 3.2e-2
+    away: 5e-3 checks every step's probes and update, not only the statistics."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(m, n, sigma, 300 + k)
+    D, Ab = _bf16(A)
+    al, be = A1.default_alpha_beta(m, n)
+    g = equilibrate(D, al, be, 1.0, 10.0, T, k, 17)
+    o = A1.equilibrate(Ab, al, be, 1.0, 10.0, T, k=k, seed=17)
+    err = max(np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max(), np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max())
+    _say(f"bf16 {m}x{n} k={k} T={T} gamma=1: error {err:.3e}")
+    assert err <= 5e-3
+
+
 def _one_step_bound(Ab, u, v, S, W, k, eta, tau):
     """Rigorous bound on |u_bar_gpu - u_bar_oracle| (and v) after one step from (u, v).
 
