@@ -75,6 +75,19 @@ def test_small_parity_several_tiles(k):
     assert np.allclose(g["e"], np.exp(o["v_bar"]), rtol=TOL, atol=0)
 
 
+@pytest.mark.parametrize("k", [1, 2])
+def test_whole_run_without_chaos_few_probes(k):
+    """One and two probes per step are chaotic over whole runs at gamma = 0.1; with
+    gamma = 1 the iteration contracts perturbations (the oracle's own u_bar moves by 1e-14
+    under 1e-16 perturbations of z, by 0.2 with another seed), so 500 steps of the
+    one-launch path (3,000 x 1,500, 8 entries per row) are compared elementwise."""
+    csr = scaled_sparse(3000, 1500, 8, 2.0, 77)
+    g, o = _both(csr, k, 500, 5, gamma=1.0)
+    err = _err(g, o)
+    _say("k", k, "gamma 1, 500 steps: max err", err)
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("k", [1, 2, 16])
 def test_one_step_map_along_oracle_trajectory(k):
     """From the oracle's states (u^t, v^t, u_bar^t, v_bar^t), one GPU step with t0 = t equals
