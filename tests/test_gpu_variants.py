@@ -139,6 +139,38 @@ def test_block_parity(rows, cols, targets, k):
     assert np.allclose(out["e"], o["e"], rtol=TOL, atol=0)
 
 
+@pytest.mark.parametrize("k", [1, 16])
+def test_variants_whole_run_without_chaos(k):
+    """With a large enough gamma the iterations contract perturbations, so 400 steps of
+    each Section 6 variant are compared elementwise at 1e-10 (with k = 1 too, where
+    gamma = 0.1 runs are chaotic): blocks of 1-20 rows and 1-10 columns with per-index
+    targets at gamma = 4 (a block sums up to 20 rows' estimates; at gamma = 1 the
+    oracle's own spread under 1e-15 perturbations of A is still 2.2e-7 for k = 1, at
+    gamma = 4 it is 1.7e-14, and another seed moves u_bar by 0.13), and Algorithm 2 on a
+    symmetric matrix at gamma = 1."""
+    from paper_1602_06621_amd import Plan
+
+    csr = scaled_sparse(300, 170, 7, 1.5, 61 + k)
+    al, be = A1.default_alpha_beta(csr.m, csr.n)
+    rp, cp = _random_blocks(csr.m, 20, 5), _random_blocks(csr.n, 10, 6)
+    g = np.random.default_rng(9)
+    rt, ct = al**2 * g.uniform(0.5, 2.0, csr.m), be**2 * g.uniform(0.5, 2.0, csr.n)
+    with Plan([_gpu(csr)], max_probes=k) as plan:
+        plan.set_targets(torch.tensor(rt, device="cuda"), torch.tensor(ct, device="cuda"))
+        plan.set_blocks(rp, cp)
+        out = _np(plan.equilibrate(al, be, 4.0, 10.0, 400, k, 77, use_graph=True))
+    o = V.equilibrate_general(csr.to_scipy(), 4.0, 10.0, 400, k=k, seed=77, row_ptr=rp, col_ptr=cp,
+                              row_target=rt, col_target=ct, alpha=al, beta=be)
+    err = max(np.abs(out["u_bar"] - o["u_bar"]).max(), np.abs(out["v_bar"] - o["v_bar"]).max())
+    sym = symmetric_sparse(300, 4, 1.5, 390 + k)
+    with Plan.symmetric_plan(_gpu(sym), max_probes=k) as plan:
+        so = _np(plan.equilibrate(1.0, 1.0, 1.0, 10.0, 400, k, 4001, use_graph=True))
+    os_ = V.equilibrate_symmetric(sym.to_scipy(), 1.0, 1.0, 10.0, 400, k=k, seed=4001)
+    serr = np.abs(so["u_bar"] - os_["u_bar"]).max()
+    _say("400 steps: blocks+targets (gamma 4)", err, "symmetric (gamma 1)", serr)
+    assert err <= 1e-10 and serr <= 1e-10
+
+
 def _one_step_cases(m_blocks, n_blocks, seed):
     g = np.random.default_rng(seed)
     for t0 in (0, 7, 100):
