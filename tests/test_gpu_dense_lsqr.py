@@ -116,6 +116,22 @@ def test_dense_register_resident_long_run_elementwise(T):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("m,n,k", [(1000, 333, 1), (1000, 333, 3), (2000, 1000, 1)])
+def test_dense_whole_run_without_chaos(m, n, k):
+    """The persistent workgroup path (1000 x 333: m + n <= 1792, m n k <= 2^20) and the
+    multi-launch path (2000 x 1000) over 400 steps at gamma = 1, elementwise at 1e-9 (the
+    oracle's own spread: 1e-12 for k = 1, 7e-15 for k = 3; another seed: 0.08 to 0.16)."""
+    from paper_1602_06621_amd import equilibrate
+
+    A = scaled_dense(m, n, 1.5, 700 + m)
+    al, be = A1.default_alpha_beta(m, n)
+    g = equilibrate(_dense(A), al, be, 1.0, 10.0, 400, k, 9)
+    o = A1.equilibrate(A, al, be, 1.0, 10.0, 400, k=k, seed=9)
+    err = max(np.abs(g["u_bar"].cpu().numpy() - o["u_bar"]).max(), np.abs(g["v_bar"].cpu().numpy() - o["v_bar"]).max())
+    _say(f"dense {m}x{n} k={k} gamma=1 T=400: max error {err:.3e}")
+    assert err <= 1e-9
+
+
 @pytest.mark.parametrize("m,n,k", [(1700, 38, 16), (1500, 170, 4), (3500, 18, 16), (3000, 700, 4)])
 def test_dense_one_step_maps_persistent_limit_and_multi_launch(m, n, k):
     """Small dense matrices run all steps in one persistent workgroup: (1700, 38, k = 16)
