@@ -268,6 +268,29 @@ def test_batched_plan_matches_per_matrix_oracle():
         c0 += c.n
 
 
+def test_batched_plan_one_probe_whole_run_without_chaos():
+    """The same batch with one probe per step over 400 steps at gamma = 1 (no chaos):
+    every matrix elementwise at 1e-10 against the oracle with its own batch index."""
+    from paper_1602_06621_amd import Plan
+
+    shapes = [(130, 40), (64, 64), (1, 7), (257, 200), (90, 23)]
+    mats = [scaled_sparse(m, n, poisson_lengths(m, 4.0, n, 50 + i), 2.0, 60 + i) for i, (m, n) in enumerate(shapes)]
+    with Plan([_gpu(c) for c in mats], max_probes=1) as plan:
+        out = plan.equilibrate(gamma=1.0, steps=400, probes=1, seed=77, use_graph=True)
+        ub = out["u_bar"].cpu().numpy()
+        vb = out["v_bar"].cpu().numpy()
+    r0 = c0 = 0
+    worst = 0.0
+    for b, c in enumerate(mats):
+        al, be = A1.default_alpha_beta(c.m, c.n)
+        o = A1.equilibrate(c.to_scipy(), al, be, 1.0, 10.0, 400, k=1, seed=77, batch=b)
+        worst = max(worst, np.abs(ub[r0:r0 + c.m] - o["u_bar"]).max(), np.abs(vb[c0:c0 + c.n] - o["v_bar"]).max())
+        r0 += c.m
+        c0 += c.n
+    _say("batched k=1 gamma=1: worst", worst)
+    assert worst <= 1e-10
+
+
 def test_batched_plan_with_batch_base_warm_start_and_offset():
     """Batched plan run with sign batch base 5, per-matrix warm starts (concatenated in plan
     order) and t0 = 10: matrix b must equal the oracle with batch 5 + b and its slice of
