@@ -340,6 +340,22 @@ def test_full_size_first_steps_elementwise(config1):
     assert err <= TOL
 
 
+def test_full_size_20_steps_without_chaos(config1):
+    """Full size, the benchmarked launch (one launch per step, graph replay), 20 steps at
+    gamma = 1, where perturbations are not amplified: every output elementwise at 1e-9."""
+    from paper_1602_06621_amd import Plan
+
+    _say("full size, 20 steps, gamma 1")
+    al, be = A1.default_alpha_beta(config1.m, config1.n)
+    with Plan([_gpu(config1)], max_probes=16) as plan:
+        g = plan.equilibrate(al, be, 1.0, 10.0, steps=20, probes=16, seed=2001, use_graph=True)
+        ub, vb = g["u_bar"].cpu().numpy(), g["v_bar"].cpu().numpy()
+    o = A1.equilibrate(config1.to_scipy(), al, be, 1.0, 10.0, 20, k=16, seed=2001)
+    err = max(np.abs(ub - o["u_bar"]).max(), np.abs(vb - o["v_bar"]).max())
+    _say("max err", err)
+    assert err <= 1e-9
+
+
 def test_full_size_bench_configuration_properties(config1):
     """2000 steps, k = 16, graph replay (the benchmarked launch): invariants that hold at
     any size -- box, iterate bound alpha^2/gamma carried to the average, finiteness,
