@@ -57,7 +57,12 @@ typedef enum {
   MFE_DENSE_BF16 = 1,  /* dense row-major bfloat16 bit patterns (uint16): data (device), ld >= n */
   MFE_CSR_F32 = 2,     /* CSR: row_ptr int32[m+1], col_idx int32[nnz], val float[nnz] (device);
                           column indices within a row sorted ascending and unique */
-  MFE_OPERATOR = 3     /* matrix-free: only apply() is used */
+  MFE_OPERATOR = 3,    /* matrix-free: only apply() is used */
+  MFE_CSR_F64 = 4      /* CSR with FP64 values (val then points to double[nnz]): declared so the
+                          kind can be named, not built; every call taking a matrix returns
+                          MFE_EUNSUPPORTED for it.  (The sparse engine accumulates in FP64 from
+                          FP32 values; a caller holding FP64 values can round them to FP32 or
+                          wrap its own product as MFE_OPERATOR.) */
 } mfe_kind;
 
 /* Matrix-free operator (the setting of Section 3): Y = A X (trans = 0, X is n x k,
@@ -117,6 +122,17 @@ typedef struct mfe_plan mfe_plan;
  * m alpha^2 = n beta^2 (Section 1) and alpha beta = 1.  Host pointers.
  * EINVAL if m <= 0, n <= 0 or an output is NULL. */
 int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta);
+
+/* Section 1: rows of norm alpha and columns of norm beta can only be reached exactly when
+ * m alpha^2 = n beta^2 (both sides then sum to ||DAE||_F^2).  Host-only check, no device
+ * work.  *rel (host, nullable) receives |m alpha^2 - n beta^2| / max(m alpha^2, n beta^2);
+ * above 1e-12 a message starting with "warning:" is left in mfe_last_error().  Returns
+ * MFE_OK either way: a mismatch is not an error, since the regularised problem of
+ * Section 2.3 has a unique solution for any alpha, beta > 0.  EINVAL: m, n, alpha or
+ * beta not positive (or not finite).  mfe_equilibrate, mfe_plan_equilibrate (per
+ * matrix), mfe_plan_equilibrate_trace and mfe_plan_autotune run the same check and keep
+ * the warning in mfe_last_error() when they return MFE_OK. */
+int mfe_check_targets(int64_t m, int64_t n, double alpha, double beta, double* rel);
 
 /* Algorithm 1 on one matrix (any kind).  Outputs are device FP64 arrays:
  * d [m] = e^u_bar, e [n] = e^v_bar (required); u_bar [m], v_bar [n] (nullable).
@@ -215,6 +231,26 @@ int mfe_draw_signs(uint64_t seed, int32_t batch, int64_t step, int32_t side, int
 int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
                              const double* beta_b, double gamma, double box_M, float* feat_rows,
                              float* feat_cols, double* u_sketch, double* v_sketch, void* stream);
+
+/* Training set of the warm-start network from a plan whose matrices have been
+ * equilibrated: labels u_label [sum m], v_label [sum n] (device FP64, e.g. u_bar, v_bar of a
+ * plain Algorithm 1 run), sketch features as mfe_plan_sketch_features(seed, probes,
+ * alpha_b, beta_b, gamma, box_M).  From matrix b it takes min(per_matrix, m_b) rows and
+ * min(per_matrix, n_b) columns, one per stratum: the c-th of the cnt samples of a side of
+ * m_b indices comes from [floor(c m_b / cnt), floor((c+1) m_b / cnt)), at offset
+ * Philox4x64-10(counter (c+1, 0, 0, 0), key (sample_seed, (((b << 1) | side) << 2) | 3))
+ * word 0 mod the stratum size (side 0 rows, 1 columns), so no index is taken twice.
+ * Sample order: the rows of matrix 0, 1, ..., then the columns of matrix 0, 1, ...
+ * Outputs (device): X [count][8] FP32 (the sample's features, copied), t [count] FP32
+ * (label - sketch initialisation, rounded once from FP64), idx [count] int64 (nullable:
+ * the sample's index in the plan's concatenated rows, or columns).  *count (host)
+ * receives the number of samples; with X == NULL only *count is computed (no device work).
+ * EINVAL: plan, labels or count NULL, per_matrix < 1, probes not in {4, 8, 16};
+ * EUNSUPPORTED: a plan with Section 6 settings. */
+int mfe_plan_training_set(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
+                          const double* beta_b, double gamma, double box_M, const double* u_label,
+                          const double* v_label, int64_t per_matrix, uint64_t sample_seed, float* X,
+                          float* t, int64_t* idx, int64_t* count, void* stream);
 
 /* Sizes of the warm-start network: parameter count, feature count (8), width (64). */
 int mfe_mlp_sizes(int32_t* n_params, int32_t* n_features, int32_t* width);

@@ -17,6 +17,7 @@ from ._ffi import (  # noqa: F401
     MfeError,
     Operator,
     Plan,
+    check_targets,
     default_alpha_beta,
     draw_signs,
     equilibrate,

@@ -98,6 +98,9 @@ def _lib():
         "mfe_mlp_loss_grad": [vp, vp, vp, i64, vp, C.POINTER(dbl), vp],
         "mfe_mlp_train": [vp, vp, vp, i32, vp, vp, i64, i64, i32, C.c_float, u64, vp, vp],
         "mfe_warmstart_apply": [i64, vp, vp, dbl, vp, vp],
+        "mfe_check_targets": [i64, i64, dbl, dbl, C.POINTER(dbl)],
+        "mfe_plan_training_set": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, i64, u64, vp, vp, vp, C.POINTER(i64),
+                                  vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -113,6 +116,14 @@ def _lib():
 
 def last_error() -> str:
     return _lib().mfe_last_error().decode()
+
+
+def check_targets(m: int, n: int, alpha: float, beta: float):
+    """mfe_check_targets: (relative mismatch of m alpha^2 and n beta^2, warning text or "")."""
+    rel = C.c_double()
+    _check(_lib().mfe_check_targets(int(m), int(n), float(alpha), float(beta), C.byref(rel)))
+    msg = last_error()
+    return rel.value, (msg if msg.startswith("warning:") else "")
 
 
 def version() -> str:
@@ -442,6 +453,29 @@ class Plan:
                                                float(gamma), float(M), _ptr(fr), _ptr(fc), _ptr(us), _ptr(vs),
                                                _stream(stream)))
         return dict(feat_rows=fr, feat_cols=fc, u_sketch=us, v_sketch=vs)
+
+    def training_set(self, seed, u_label, v_label, per_matrix=4096, sample_seed=0, probes=4, gamma=0.1, M=10.0,
+                     alpha=None, beta=None, stream=None, device="cuda"):
+        """(X [count, 8] FP32, t [count] FP32, idx [count] int64): stratified samples of up
+        to per_matrix rows and columns of every matrix, their sketch features and the
+        targets label - sketch initialisation (see mfe_plan_training_set)."""
+        ah = bh = None
+        if alpha is not None:
+            ah, bh, _, _ = self._targets(alpha, beta)
+        lib = _lib()
+        u_label = u_label.to(torch.float64).contiguous()
+        v_label = v_label.to(torch.float64).contiguous()
+        if u_label.numel() != self.M or v_label.numel() != self.N:
+            raise ValueError("labels need sum m row values and sum n column values")
+        cnt = C.c_int64()
+        args = (self._h, int(seed) & ((1 << 64) - 1), int(probes), ah, bh, float(gamma), float(M), _ptr(u_label),
+                _ptr(v_label), int(per_matrix), int(sample_seed) & ((1 << 64) - 1))
+        _check(lib.mfe_plan_training_set(*args, None, None, None, C.byref(cnt), _stream(stream)))
+        X = torch.empty(cnt.value, 8, dtype=torch.float32, device=device)
+        t = torch.empty(cnt.value, dtype=torch.float32, device=device)
+        idx = torch.empty(cnt.value, dtype=torch.int64, device=device)
+        _check(lib.mfe_plan_training_set(*args, _ptr(X), _ptr(t), _ptr(idx), C.byref(cnt), _stream(stream)))
+        return X, t, idx
 
     def warm_start(self, params, seed, probes=4, gamma=0.1, M=10.0, learned=True, alpha=None, beta=None,
                    stream=None, device="cuda"):

@@ -1,4 +1,5 @@
 // C ABI entry points of libmfe: validation, dispatch and error reporting.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -57,6 +58,41 @@ int check_params(const mfe_equil_params* p, bool check_targets) {
   return MFE_OK;
 }
 
+// Section 1: exact equilibration needs m alpha^2 = n beta^2.  A mismatch is reported as
+// a warning (the regularised problem is well posed for any positive targets).
+int check_targets(int64_t m, int64_t n, double alpha, double beta, double* rel_out) {
+  auto pos = [](double x) { return x > 0 && std::isfinite(x); };
+  if (m <= 0 || n <= 0) return set_error(MFE_EINVAL, "m and n must be positive");
+  if (!pos(alpha) || !pos(beta)) return set_error(MFE_EINVAL, "alpha and beta must be positive and finite");
+  const double a = (double)m * alpha * alpha, b = (double)n * beta * beta;
+  const double rel = std::fabs(a - b) / std::max(a, b);
+  if (rel_out) *rel_out = rel;
+  if (rel > 1e-12)
+    set_warning("m alpha^2 = %.17g differs from n beta^2 = %.17g (relative %.3g): rows of norm alpha and "
+                "columns of norm beta cannot both be reached exactly (Section 1); the regularised problem "
+                "is solved as stated",
+                a, b, rel);
+  return MFE_OK;
+}
+
+// The same check for every matrix of a plan (symmetric plans have one target); the
+// first mismatched matrix is named.  Invalid values are left to the run to reject.
+void check_plan_targets(const mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b,
+                        const double* beta_b) {
+  if (p->symmetric) return;
+  for (int b = 0; b < p->count; ++b) {
+    const double al = alpha_b ? alpha_b[b] : prm->alpha;
+    const double be = beta_b ? beta_b[b] : prm->beta;
+    if (!(al > 0) || !(be > 0) || !std::isfinite(al) || !std::isfinite(be)) return;
+    double rel = 0.0;
+    (void)check_targets(p->meta[b].m, p->meta[b].n, al, be, &rel);
+    if (rel > 1e-12) {
+      if (p->count > 1) g_last_error += " (matrix " + std::to_string(b) + " of the plan)";
+      return;
+    }
+  }
+}
+
 }  // namespace mfe
 
 using namespace mfe;
@@ -66,6 +102,11 @@ extern "C" {
 const char* mfe_last_error(void) { return g_last_error.c_str(); }
 
 const char* mfe_version(void) { return "mfe 0.1 (gfx950)"; }
+
+int mfe_check_targets(int64_t m, int64_t n, double alpha, double beta, double* rel) {
+  clear_error();
+  return check_targets(m, n, alpha, beta, rel);
+}
 
 int mfe_default_alpha_beta(int64_t m, int64_t n, double* alpha, double* beta) {
   clear_error();
@@ -141,6 +182,7 @@ int mfe_plan_equilibrate(mfe_plan* plan, const mfe_equil_params* p, const double
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   MFE_CHECK(check_params(p, alpha_b == nullptr || beta_b == nullptr));
   if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "sparse path supports at most 64 probes per step");
+  check_plan_targets(plan, p, alpha_b, beta_b);
   return plan_run(plan, p, alpha_b, beta_b, use_graph, d, e, u_bar, v_bar);
 }
 
@@ -171,6 +213,10 @@ int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, d
   MFE_CHECK(check_params(p, true));
   if (!d || !e) return set_error(MFE_EINVAL, "outputs d and e are required");
   if (A->m <= 0 || A->n <= 0) return set_error(MFE_EDIM, "m and n must be positive");
+  if (A->kind == MFE_CSR_F64)
+    return set_error(MFE_EUNSUPPORTED, "CSR with FP64 values is not built (store the values as FP32, or pass "
+                                       "the product as MFE_OPERATOR)");
+  MFE_CHECK(check_targets(A->m, A->n, p->alpha, p->beta, nullptr));
   switch (A->kind) {
     case MFE_CSR_F32: {
       if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "sparse path supports at most 64 probes per step");
@@ -246,6 +292,7 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
   if (p->probes > plan->max_probes) return set_error(MFE_EINVAL, "probes exceed the plan's max_probes");
   if (plan_has_variant(plan))
     return set_error(MFE_EUNSUPPORTED, "the residual trace measures the standard problem (no variant settings)");
+  check_plan_targets(plan, p, nullptr, nullptr);
   return plan_equilibrate_trace(plan, p, trace_every, rms_trace, d, e, u_bar, v_bar);
 }
 
@@ -321,7 +368,11 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   MFE_CHECK(check_params(p, true));
   if (p->probes > plan->max_probes) return set_error(MFE_EINVAL, "probes exceed the plan's max_probes");
-  return plan_autotune(plan, p, alpha_b, beta_b, trial_steps, chosen, best_step_ms, n_candidates);
+  check_plan_targets(plan, p, alpha_b, beta_b);
+  const std::string warn = g_last_error;
+  const int rc = plan_autotune(plan, p, alpha_b, beta_b, trial_steps, chosen, best_step_ms, n_candidates);
+  if (rc == MFE_OK) g_last_error = warn;
+  return rc;
 }
 
 int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
@@ -333,6 +384,21 @@ int mfe_plan_sketch_features(mfe_plan* plan, uint64_t seed, int32_t probes, cons
   if (!feat_rows || !feat_cols || !u_sketch || !v_sketch) return set_error(MFE_EINVAL, "NULL output");
   return plan_sketch_features(plan, seed, probes, alpha_b, beta_b, gamma, box_M, feat_rows, feat_cols, u_sketch,
                               v_sketch, (hipStream_t)stream);
+}
+
+int mfe_plan_training_set(mfe_plan* plan, uint64_t seed, int32_t probes, const double* alpha_b,
+                          const double* beta_b, double gamma, double box_M, const double* u_label,
+                          const double* v_label, int64_t per_matrix, uint64_t sample_seed, float* X, float* t,
+                          int64_t* idx, int64_t* count, void* stream) {
+  clear_error();
+  if (!plan || !u_label || !v_label || !count) return set_error(MFE_EINVAL, "plan, labels or count is NULL");
+  if (per_matrix < 1) return set_error(MFE_EINVAL, "per_matrix must be >= 1");
+  if (!(gamma > 0) || !(box_M > 0)) return set_error(MFE_EINVAL, "gamma and M must be positive");
+  if (X && !t) return set_error(MFE_EINVAL, "t is NULL");
+  if (plan_has_variant(plan))
+    return set_error(MFE_EUNSUPPORTED, "warm starts are trained for the standard problem (no variant settings)");
+  return plan_training_set(plan, seed, probes, alpha_b, beta_b, gamma, box_M, u_label, v_label, per_matrix,
+                           sample_seed, X, t, idx, count, (hipStream_t)stream);
 }
 
 int mfe_mlp_sizes(int32_t* n_params, int32_t* n_features, int32_t* width) {

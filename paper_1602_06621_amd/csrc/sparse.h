@@ -220,6 +220,9 @@ int plan_sketch_features(mfe_plan* p, uint64_t seed, int32_t ks, const double* a
 int plan_warmstart(mfe_plan* p, const float* params, uint64_t seed, int32_t ks, const double* alpha_b,
                    const double* beta_b, double gamma, double M, int learned, double* u0, double* v0,
                    hipStream_t st);
+int plan_training_set(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
+                      double gamma, double M, const double* u_label, const double* v_label, int64_t per_matrix,
+                      uint64_t sample_seed, float* X, float* t, int64_t* idx, int64_t* count, hipStream_t st);
 int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st);
 int mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const float* X, const float* t,
               int64_t total, int64_t batch, int32_t iters, float lr, uint64_t seed, double* loss_trace,

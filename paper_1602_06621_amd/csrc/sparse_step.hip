@@ -505,6 +505,13 @@ int ensure(T** ptr, int64_t count) {
 // (columns) and one for side 1 (rows), each starting on a Philox block boundary.
 int build_sign_layout(mfe_plan* p, int k, int64_t batch_base) {
   if (p->sign_k == k && p->sign_batch_base == batch_base) return MFE_OK;
+  // A cached graph holds the addresses of the sign buffers freed below: drop it, so
+  // that the next graph run captures the new ones (its key alone cannot tell, since a
+  // later run may come back to the same k and batch).
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
   for (int i = 0; i < 2; ++i) {
     (void)hipFree(p->signs[i]);
     p->signs[i] = nullptr;

@@ -370,6 +370,36 @@ __global__ void k_apply_delta(int64_t n, const double* __restrict__ s, const flo
   if (i < n) out[i] = fmin(fmax(s[i] + (double)(d ? d[i] : 0.f), -M), M);
 }
 
+// One training sample per thread, for one side: sample s of matrix b is stratum
+// c = s - soff[b] of that matrix's cnt = soff[b+1] - soff[b] strata over its nb indices,
+// [floor(c nb / cnt), floor((c+1) nb / cnt)), at a Philox offset inside the stratum.
+// Copies the index's features and writes label - sketch (rounded once to FP32).
+__global__ void k_training_samples(const int64_t* __restrict__ soff, const int64_t* __restrict__ ibase,
+                                   int count, int side, uint64_t seed, const float* __restrict__ feat,
+                                   const double* __restrict__ label, const double* __restrict__ sketch,
+                                   int64_t out0, float* __restrict__ X, float* __restrict__ t,
+                                   int64_t* __restrict__ idx) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= soff[count]) return;
+  int lo = 0, hi = count;  // the matrix b with soff[b] <= s < soff[b+1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (soff[mid] <= s) lo = mid;
+    else hi = mid;
+  }
+  const int b = lo;
+  const int64_t cnt = soff[b + 1] - soff[b], nb = ibase[b + 1] - ibase[b], c = s - soff[b];
+  const int64_t a = (int64_t)(((unsigned __int128)c * (uint64_t)nb) / (uint64_t)cnt);
+  const int64_t e = (int64_t)(((unsigned __int128)(c + 1) * (uint64_t)nb) / (uint64_t)cnt);
+  int64_t off;
+  philox_index(seed, ((uint64_t)b << 1) | (uint64_t)side, (uint64_t)c, e - a, off);
+  const int64_t g = ibase[b] + a + off;
+  const int64_t o = out0 + s;
+  for (int f = 0; f < kF; ++f) X[o * kF + f] = feat[g * kF + f];
+  t[o] = (float)(label[g] - sketch[g]);
+  if (idx) idx[o] = g;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- drivers
@@ -576,6 +606,66 @@ int plan_warmstart(mfe_plan* p, const float* params, uint64_t seed, int32_t ks, 
   return MFE_OK;
 }
 
+
+int plan_training_set(mfe_plan* p, uint64_t seed, int32_t ks, const double* alpha_b, const double* beta_b,
+                      double gamma, double M, const double* u_label, const double* v_label, int64_t per_matrix,
+                      uint64_t sample_seed, float* X, float* t, int64_t* idx, int64_t* count, hipStream_t st) {
+  if (ks != 4 && ks != 8 && ks != 16) return set_error(MFE_EINVAL, "sketch probes must be 4, 8 or 16");
+  const int nmat = p->count;
+  // per-side sample offsets and index bases (rows: side 0, columns: side 1)
+  std::vector<int64_t> tab(4 * ((size_t)nmat + 1));
+  int64_t* soff_r = tab.data();
+  int64_t* soff_c = soff_r + nmat + 1;
+  int64_t* base_r = soff_c + nmat + 1;
+  int64_t* base_c = base_r + nmat + 1;
+  soff_r[0] = soff_c[0] = base_r[0] = base_c[0] = 0;
+  for (int b = 0; b < nmat; ++b) {
+    soff_r[b + 1] = soff_r[b] + std::min<int64_t>(per_matrix, p->meta[b].m);
+    soff_c[b + 1] = soff_c[b] + std::min<int64_t>(per_matrix, p->meta[b].n);
+    base_r[b + 1] = base_r[b] + p->meta[b].m;
+    base_c[b + 1] = base_c[b] + p->meta[b].n;
+  }
+  *count = soff_r[nmat] + soff_c[nmat];
+  if (!X) return MFE_OK;
+  MFE_CHECK(ensure_mats(p, st));
+  // scratch: the offset tables, features and sketch initialisations, then the sketch's own
+  Carver head{nullptr};
+  head.take<int64_t>((int64_t)tab.size());
+  head.take<float>(p->M * kF);
+  head.take<float>(p->N * kF);
+  head.take<double>(p->M);
+  head.take<double>(p->N);
+  const size_t head_bytes = (head.off + 255) & ~(size_t)255;
+  size_t bytes = head_bytes;
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, nullptr, nullptr, nullptr, nullptr, st, nullptr,
+                        &bytes));
+  char* ws;
+  MFE_CHECK(plan_workspace(p, bytes, &ws));
+  Carver cv{ws};
+  int64_t* d_tab = cv.take<int64_t>((int64_t)tab.size());
+  float* fr = cv.take<float>(p->M * kF);
+  float* fc = cv.take<float>(p->N * kF);
+  double* us = cv.take<double>(p->M);
+  double* vs = cv.take<double>(p->N);
+  // ordered on st after earlier users of the scratch; waited for, so that `tab` may go
+  MFE_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(int64_t) * tab.size(), hipMemcpyHostToDevice, st));
+  MFE_HIP(hipStreamSynchronize(st));
+  MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, fr, fc, us, vs, st, ws + head_bytes, &bytes));
+  const int64_t nr = soff_r[nmat], nc = soff_c[nmat];
+  const int64_t* d_soff_r = d_tab;
+  const int64_t* d_soff_c = d_soff_r + nmat + 1;
+  const int64_t* d_base_r = d_soff_c + nmat + 1;
+  const int64_t* d_base_c = d_base_r + nmat + 1;
+  if (nr > 0)
+    k_training_samples<<<(unsigned)ceil_div(nr, 256), 256, 0, st>>>(d_soff_r, d_base_r, nmat, 0, sample_seed, fr,
+                                                                    u_label, us, 0, X, t, idx);
+  if (nc > 0)
+    k_training_samples<<<(unsigned)ceil_div(nc, 256), 256, 0, st>>>(d_soff_c, d_base_c, nmat, 1, sample_seed, fc,
+                                                                    v_label, vs, nr, X, t, idx);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipStreamSynchronize(st));
+  return MFE_OK;
+}
 
 int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st) {
   if (count <= 0) return MFE_OK;

@@ -32,22 +32,11 @@ def init_params(seed: int, device="cuda") -> torch.Tensor:
 
 def training_set(plan, sketch_seed, label_out, per_matrix=4096, probes=4, gamma=0.1, M=10.0, seed=0):
     """(X, t) from a plan whose matrices were equilibrated into `label_out` (u_bar, v_bar):
-    up to `per_matrix` rows and as many columns sampled from every matrix."""
-    f = plan.sketch_features(sketch_seed, probes, gamma, M)
-    tr = (label_out["u_bar"] - f["u_sketch"]).float()
-    tc = (label_out["v_bar"] - f["v_sketch"]).float()
-    g = np.random.Generator(np.random.PCG64(seed))
-    ri, ci = [], []
-    r0 = c0 = 0
-    for mat in plan.mats:
-        ri.append(r0 + g.choice(mat.m, min(per_matrix, mat.m), replace=False))
-        ci.append(c0 + g.choice(mat.n, min(per_matrix, mat.n), replace=False))
-        r0 += mat.m
-        c0 += mat.n
-    ri = torch.tensor(np.concatenate(ri), device=tr.device)
-    ci = torch.tensor(np.concatenate(ci), device=tr.device)
-    X = torch.cat([f["feat_rows"][ri], f["feat_cols"][ci]]).contiguous()
-    t = torch.cat([tr[ri], tc[ci]]).contiguous()
+    up to `per_matrix` rows and as many columns of every matrix, one per stratum
+    (mfe_plan_training_set: features, label - sketch targets and the sampling all run in
+    the library)."""
+    X, t, _ = plan.training_set(sketch_seed, label_out["u_bar"], label_out["v_bar"], per_matrix=per_matrix,
+                                sample_seed=seed, probes=probes, gamma=gamma, M=M)
     return X, t
 
 

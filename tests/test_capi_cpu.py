@@ -165,3 +165,46 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setenv("MFE_LIBRARY", str(tmp_path / "absent.so"))
     with pytest.raises(_ffi.LibraryMissing):
         _ffi.default_alpha_beta(2, 2)
+
+
+def test_target_relation_check_warns_without_failing(lib):
+    """Section 1: m alpha^2 = n beta^2 is needed for exact equilibration.  The host-only
+    check returns OK either way and leaves a warning when the relation fails."""
+    rel = C.c_double()
+    a = (100 / 200) ** 0.25
+    assert lib.mfe_check_targets(200, 100, a, 1 / a, C.byref(rel)) == 0
+    assert rel.value < 1e-15
+    assert lib.mfe_last_error().decode() == ""
+    assert lib.mfe_check_targets(200, 100, 1.0, 1.0, C.byref(rel)) == 0
+    assert rel.value == pytest.approx(0.5, rel=1e-15)     # |200 - 100| / 200
+    msg = lib.mfe_last_error().decode()
+    assert msg.startswith("warning:") and "Section 1" in msg
+    assert lib.mfe_check_targets(0, 100, 1.0, 1.0, C.byref(rel)) == -1
+    assert lib.mfe_check_targets(10, 10, float("nan"), 1.0, None) == -1
+    from paper_1602_06621_amd import check_targets
+
+    r, w = check_targets(3, 12, 2.0, 1.0)      # 3 * 4 = 12 * 1
+    assert r == 0.0 and w == ""
+
+
+def test_csr_f64_kind_declared_and_refused(lib):
+    """MFE_CSR_F64 is named in the header and refused with EUNSUPPORTED before any
+    device work."""
+    text = open(HEADER).read()
+    assert "MFE_CSR_F64 = 4" in text
+    s = _csr_struct()
+    s.kind = 4
+    dummy = C.c_void_p(16)
+    assert lib.mfe_equilibrate(C.byref(s), C.byref(_params()), dummy, dummy, None, None) == -6
+    assert "FP64 values" in lib.mfe_last_error().decode()
+    h = C.c_void_p()
+    assert lib.mfe_plan_create(C.byref(s), 1, 4, None, C.byref(h)) == -6
+
+
+def test_training_set_argument_checks(lib):
+    cnt = C.c_int64()
+    buf = C.c_void_p(16)
+    assert lib.mfe_plan_training_set(None, 1, 4, None, None, 0.1, 10.0, buf, buf, 8, 0, None, None, None,
+                                     C.byref(cnt), None) == -1
+    assert lib.mfe_plan_training_set(buf, 1, 4, None, None, 0.1, 10.0, buf, buf, 0, 0, None, None, None,
+                                     C.byref(cnt), None) == -1

@@ -245,6 +245,30 @@ def test_deterministic_and_graph_replay_identical():
             assert torch.equal(a[key], c[key])
 
 
+def test_graph_recaptured_after_sign_buffers_change():
+    """A cached graph must not replay with sign buffers that a run with another k (or
+    another batch index) has freed and reallocated: graph k = 16, then an ungraphed
+    k = 8 run, then a traced run with k = 4, then graph k = 16 again, all bitwise equal to
+    a fresh plan's graph run."""
+    from paper_1602_06621_amd import Plan
+
+    csr = scaled_sparse(3000, 1700, 6, 2.0, 19)
+    _say("graph recapture 3000x1700")
+    with Plan([_gpu(csr)], max_probes=16) as fresh:
+        ref = fresh.equilibrate(steps=60, probes=16, seed=4, use_graph=True)
+        ref = {k: v.clone() for k, v in ref.items()}
+    with Plan([_gpu(csr)], max_probes=16) as plan:
+        plan.equilibrate(steps=60, probes=16, seed=4, use_graph=True)
+        plan.equilibrate(steps=60, probes=8, seed=4)
+        al, be = A1.default_alpha_beta(csr.m, csr.n)
+        plan.equilibrate_trace(al, be, steps=20, probes=4, seed=4, trace_every=10)
+        plan.equilibrate(steps=60, probes=16, seed=4, batch=2)
+        again = plan.equilibrate(steps=60, probes=16, seed=4, use_graph=True)
+        torch.cuda.synchronize()
+        for key in ("u_bar", "v_bar", "d", "e"):
+            assert torch.equal(again[key], ref[key]), key
+
+
 def test_batched_plan_matches_per_matrix_oracle():
     """Several uneven matrices in one plan: matrix b uses sign batch index b."""
     from paper_1602_06621_amd import Plan
@@ -509,3 +533,22 @@ def test_autotune_keeps_results_bitwise():
             for key in ("u_bar", "v_bar"):
                 assert torch.equal(b[key], c[key])
                 assert torch.equal(a[key], b[key])
+
+
+def test_mismatched_targets_run_with_a_warning():
+    """m alpha^2 != n beta^2 (Section 1): the run succeeds and mfe_last_error holds a
+    warning naming the relation; with the paper's alpha, beta it holds nothing."""
+    from paper_1602_06621_amd import Plan, equilibrate, last_error
+
+    csr = scaled_sparse(400, 200, 5, 1.0, 23)
+    A = _gpu(csr)
+    equilibrate(A, 1.0, 1.0, 0.1, 10.0, 5, 4, 1)
+    assert last_error().startswith("warning:") and "Section 1" in last_error()
+    al, be = A1.default_alpha_beta(csr.m, csr.n)
+    equilibrate(A, al, be, 0.1, 10.0, 5, 4, 1)
+    assert last_error() == ""
+    with Plan([A, _gpu(scaled_sparse(300, 300, 4, 1.0, 24))], max_probes=4) as plan:
+        plan.equilibrate([al, 1.0], [be, 1.0], steps=3, probes=4, seed=1)
+        assert last_error() == ""
+        plan.equilibrate([al, 1.0], [be, 2.0], steps=3, probes=4, seed=1)
+        assert last_error().startswith("warning:") and "matrix 1" in last_error()

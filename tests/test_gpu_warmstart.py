@@ -139,3 +139,43 @@ def test_one_call_warm_start_equals_composed_steps():
             dv = mlp_forward(params, f["feat_cols"]) if learned else None
             assert torch.equal(u0, warmstart_apply(f["u_sketch"], du, 10.0))
             assert torch.equal(v0, warmstart_apply(f["v_sketch"], dv, 10.0))
+
+
+def test_training_set_call_samples_strata_and_targets():
+    """mfe_plan_training_set: every sample lies in its own stratum at the Philox offset the
+    header states (recomputed here from the published Philox definition), its features are
+    the sketch features of that index bit for bit, and its target is label - sketch
+    initialisation rounded once to FP32.  Matrices smaller than per_matrix give every index."""
+    from paper_1602_06621_amd import Plan
+
+    mats = [warmstart_matrix(900, 450, 1.5, 31), warmstart_matrix(100, 300, 2.5, 32, lo=1, hi=4)]
+    per, sseed = 256, 17
+    with Plan([_gpu(c) for c in mats], max_probes=4) as plan:
+        lab = plan.equilibrate(None, None, 0.1, 10.0, 50, 4, 5)
+        X, t, idx = plan.training_set(5, lab["u_bar"], lab["v_bar"], per_matrix=per, sample_seed=sseed)
+        f = plan.sketch_features(5, 4, 0.1, 10.0)
+        X, t, idx = X.cpu().numpy(), t.cpu().numpy(), idx.cpu().numpy()
+        fr, fc = f["feat_rows"].cpu().numpy(), f["feat_cols"].cpu().numpy()
+        us, vs = f["u_sketch"].cpu().numpy(), f["v_sketch"].cpu().numpy()
+        ub, vb = lab["u_bar"].cpu().numpy(), lab["v_bar"].cpu().numpy()
+    want, s = [], 0
+    for side, sizes in ((0, [c.m for c in mats]), (1, [c.n for c in mats])):
+        base = 0
+        for b, nb in enumerate(sizes):
+            cnt = min(per, nb)
+            for c in range(cnt):
+                a, e = c * nb // cnt, (c + 1) * nb // cnt
+                off = philox4x64([c + 1, 0, 0, 0], [sseed, (((b << 1) | side) << 2) | 3])[0] % (e - a)
+                want.append((side, base + a + off))
+            base += nb
+    assert len(want) == len(idx)
+    nr = sum(min(per, c.m) for c in mats)
+    for s, (side, g) in enumerate(want):
+        assert idx[s] == g
+    ri, ci = idx[:nr], idx[nr:]
+    assert len(set(ri.tolist())) == len(ri) and len(set(ci.tolist())) == len(ci)
+    assert np.array_equal(X[:nr], fr[ri]) and np.array_equal(X[nr:], fc[ci])
+    assert np.array_equal(t[:nr], (ub[ri] - us[ri]).astype(np.float32))
+    assert np.array_equal(t[nr:], (vb[ci] - vs[ci]).astype(np.float32))
+    # the second matrix has 100 rows < per: all of them, in order
+    assert np.array_equal(ri[per:], 900 + np.arange(100))
