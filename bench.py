@@ -44,13 +44,25 @@ T_STEPS, K_PROBES, GAMMA, BOX_M = 2000, 16, 0.1, 10.0
 GEN_SEED, PROBE_SEED = 1001, 2001
 # HBM-side bytes per step of k_phase_both<16, true, 8> on the headline workload, from
 # rocprofv3 FETCH_SIZE (x 2.00) and WRITE_SIZE (x 1.00) per launch, calibrated against a
-# plain 512 MiB copy (profiles/k_phase_csr_1e6x5e5_k16.md).  None when the kernel has
-# changed since the counters were taken.
+# plain 512 MiB copy; TRAFFIC_SOURCE names the profile summary they were read from.  None
+# when the kernel has changed since the counters were taken.
 TRAFFIC_BYTES_PER_STEP = (909.5 + 39.1) * 1e6
+TRAFFIC_SOURCE = "profiles/k_phase_csr_1e6x5e5_k16.md (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 per launch)"
+
+
+def step_bytes(m, n, nnz, k):
+    """Algorithmic HBM bytes of one step of the two-structure design: per stored entry and
+    product 8 B (FP32 value + int32 index), the two offset arrays (4 B per row and per
+    column), per row or column 40 B (iterate and average read and written, 32 B; the
+    FP32-sized scale written and read once, 8 B) and its k sign bits written and read
+    once (k/4 B).  The headline workload: 232 MB.  This is the roofline's byte count."""
+    return 2 * nnz * 8 + 4 * (m + 1) + 4 * (n + 1) + (m + n) * (40 + k / 4.0)
 
 
 def sparse_algorithmic_bytes(m, n, nnz, k):
-    """HBM bytes one step (both direction launches) must move at minimum.
+    """HBM bytes one step moves in this library's layout (for comparison with
+    step_bytes: the sliced layouts' row lengths and original indices, 8-byte packed
+    descriptors read and written, generated sign bits).
 
     Per stored entry and direction: 8 B (int32 index + FP32 value).  Per row or column:
     iterate read+write 16 B, average read+write 16 B, descriptor write and its
@@ -80,6 +92,20 @@ def bf16_algorithmic(m, n, k):
     """Per step: A read once (the minimum; the kernel reads its two tiled copies once
     each), plus probe operands and FP64 state; FLOPs of both products."""
     return 2 * m * n + (m + n) * (2 * k + 40), 2 * 2.0 * m * n * k
+
+
+def measure_ceilings(mfe, m, n, nnz, stream_bytes=1 << 30):
+    """The two rates the sparse step is bounded by, measured on this GPU in this run: a
+    plain streaming read (1 GiB, 16-byte non-temporal loads) and random 8-byte gathers
+    from tables of the headline's descriptor-table sizes (n x 8 B gathered by the row
+    direction, m x 8 B by the column direction), nnz gathers each, as each direction
+    makes per step."""
+    stream_ms = mfe.probe_stream(stream_bytes, reps=5)
+    g_cols = mfe.probe_gather(8 * n, nnz, reps=5)   # the row direction's table
+    g_rows = mfe.probe_gather(8 * m, nnz, reps=5)   # the column direction's table
+    return {"stream_read_gbs": stream_bytes / (stream_ms / 1e3) / 1e9,
+            "gather_ms": {f"{8 * n / 2**20:.1f} MiB": g_cols, f"{8 * m / 2**20:.1f} MiB": g_rows},
+            "gathers_each": nnz, "gather_floor_ms": g_cols + g_rows}
 
 
 def load_lib():
@@ -180,8 +206,10 @@ def bench_c3(mfe):
 
 def bench_c4(mfe):
     """Learned warm start against plain SGD: steps and seconds to equal residual on a
-    held-out 200,000 x 100,000 matrix (training matrices are smaller and fewer than
-    the paper-scale set; the sizes are in the returned record)."""
+    held-out 200,000 x 100,000 matrix.  Training: 64 generated matrices with m in
+    [10k, 200k] (the configuration's range; 64 instead of 20,000 matrices keeps the labels
+    to seconds, and more matrices were measured not to move the result), n = m/2,
+    U{8..16} entries per row, sigma in [0.5, 3]."""
     import numpy as np
     import torch
 
@@ -192,9 +220,10 @@ def bench_c4(mfe):
     rec = {"workload": "learned warm start: 3-layer MLP width 64 (FP32) on 4-probe sketch features; "
                        "eval csr_f32 200000x100000, U{8..16} nnz/row, sigma=2 (more_eval: sigma 0.5, 1.5, 3); "
                        "k=16; target = 1.2 x the residual of the plain run after 3000 steps (also: the plain "
-                       "run's residual after 1000 steps); arms: plain, plain with its best t0, sketch, mlp"}
+                       "run's residual after 1000 steps); arms: plain, plain with its best t0, sketch, mlp; "
+                       "training: 64 csr_f32 matrices, m~U[10k,200k], n=m/2, U{8..16} nnz/row, sigma~U[0.5,3]"}
     t0 = time.time()
-    train = warmstart_training_set(32, 31, m_lo=10_000, m_hi=100_000)
+    train = warmstart_training_set(64, 31, m_lo=10_000, m_hi=200_000)
     rec["train_matrices"] = len(train)
     rec["train_rows"] = int(sum(c.m for c in train))
     rec["train_nnz"] = int(sum(c.nnz for c in train))
@@ -255,31 +284,37 @@ def bench_c4(mfe):
             if not timing:
                 return out_rec
 
-            def run(name):
+            def run(name, nsteps):
                 t0a, learned = arms[name]
                 torch.cuda.synchronize()
                 s0 = time.perf_counter()
                 u0 = v0 = None
                 if learned is not None:
                     u0, v0 = W.warm_start(plan, params, 5, learned=learned)
-                out = plan.equilibrate(al, be, gamma, BOX_M, steps[name], k, 11, t0=t0a, u0=u0, v0=v0,
+                out = plan.equilibrate(al, be, gamma, BOX_M, nsteps, k, 11, t0=t0a, u0=u0, v0=v0,
                                        use_graph=True)
                 torch.cuda.synchronize()
                 return time.perf_counter() - s0, out
 
-            secs, reached = {}, {}
-            for name in arms:
-                if steps[name] is None:
-                    continue
-                run(name)  # graph capture
-                ts = []
-                for _ in range(5):
-                    s, out = run(name)
-                    ts.append(s)
-                secs[name] = float(np.median(ts))
-                reached[name] = mfe.residual(Ac, out["d"], out["e"], al, be)[0]
-            out_rec["seconds_to_target"] = secs
-            out_rec["residual_reached"] = reached
+            def seconds(step_counts):
+                """Median wall-clock of 5 graph runs (after one capture run) of each arm to
+                its step count, warm start included, and the residual reached."""
+                secs, reached = {}, {}
+                for name in arms:
+                    if step_counts[name] is None:
+                        continue
+                    run(name, step_counts[name])  # graph capture
+                    ts = []
+                    for _ in range(5):
+                        s, out = run(name, step_counts[name])
+                        ts.append(s)
+                    secs[name] = float(np.median(ts))
+                    reached[name] = mfe.residual(Ac, out["d"], out["e"], al, be)[0]
+                return secs, reached
+
+            out_rec["seconds_to_target"], out_rec["residual_reached"] = seconds(steps)
+            out_rec["seconds_to_rho_1000"], out_rec["residual_reached_rho_1000"] = seconds(
+                out_rec["steps_to_rho_1000"])
             torch.cuda.synchronize()
             s0 = time.perf_counter()
             for _ in range(10):
@@ -294,6 +329,11 @@ def bench_c4(mfe):
         rec["speedup_seconds"] = secs["plain"] / secs["mlp"]
     if "plain_t0" in secs and "mlp" in secs:
         rec["speedup_seconds_vs_plain_t0"] = secs["plain_t0"] / secs["mlp"]
+    secs = rec.get("seconds_to_rho_1000", {})
+    if "plain" in secs and "mlp" in secs:
+        rec["speedup_seconds_rho_1000"] = secs["plain"] / secs["mlp"]
+    if "plain_t0" in secs and "mlp" in secs:
+        rec["speedup_seconds_rho_1000_vs_plain_t0"] = secs["plain_t0"] / secs["mlp"]
     # more held-out matrices across the training range of sigma (steps only)
     rec["more_eval"] = {f"sigma={sg}": evaluate(warmstart_matrix(200_000, 100_000, sg, 3000 + i), timing=False)
                         for i, sg in enumerate((0.5, 1.5, 3.0))}
@@ -633,6 +673,23 @@ def profile_run():
     print(json.dumps({"profile": "done", "copy_bytes": 512 * 1024 * 1024}), flush=True)
 
 
+def blas_threads():
+    """Threads of the BLAS libraries numpy/scipy loaded (threadpoolctl), or None."""
+    try:
+        from threadpoolctl import threadpool_info
+
+        return {i.get("internal_api", "?"): i.get("num_threads") for i in threadpool_info()}
+    except Exception:
+        return None
+
+
+def profile_ceilings():
+    """Counter / trace run of the two ceiling probes at the headline's sizes."""
+    mfe = load_lib()
+    c = measure_ceilings(mfe, M_ROWS, N_COLS, M_ROWS * NNZ_ROW)
+    print(json.dumps({"profile": "ceilings", **c}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -643,13 +700,14 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--profile", nargs="?", const="c1", default=None,
-                    choices=["c1", "c0", "c2", "c3", "c4", "var", "ccp", "lsqr"],
+                    choices=["c1", "c0", "c2", "c3", "c4", "var", "ccp", "lsqr", "ceilings"],
                     help="short run for hardware counters: 20 steps of the headline workload (c1, "
                          "default) or of the bf16 workload (c3), then a 512 MiB device copy used to "
                          "calibrate FETCH_SIZE / WRITE_SIZE; c4: ten warm-start calls; var: 20 steps "
                          "of each Section 6 variant; ccp: 200 CCP iterations plain and equilibrated; "
                          "c2: 20 batched steps and the calibration copy; c0: three dense runs; "
-                         "lsqr: 200 LSQR iterations on the headline matrix")
+                         "lsqr: 200 LSQR iterations on the headline matrix; ceilings: the streaming-read "
+                         "and random-gather probes at the headline's sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding "
@@ -659,7 +717,8 @@ def main():
     work = set(args.workloads.split(","))
     if args.profile:
         {"c1": profile_run, "c0": profile_c0, "c2": profile_c2, "c3": profile_c3, "c4": profile_c4,
-         "var": profile_var, "ccp": profile_ccp, "lsqr": profile_lsqr}[args.profile]()
+         "var": profile_var, "ccp": profile_ccp, "lsqr": profile_lsqr,
+         "ceilings": profile_ceilings}[args.profile]()
         return
 
     import numpy as np
@@ -696,8 +755,9 @@ def main():
     pairs = T_STEPS * K_PROBES
     value = pairs / (ms_per_step / 1e3)
     kern_ms = float(np.mean(step_ms_samples)) if step_ms_samples else float("nan")
-    bytes_launch = sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, K_PROBES)
+    bytes_launch = step_bytes(csr.m, csr.n, csr.nnz, K_PROBES)
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
+    ceil = measure_ceilings(mfe, csr.m, csr.n, csr.nnz)
 
     extra = {"prep_ms": prep_ms, "gen_s": gen_s,
              "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
@@ -726,7 +786,8 @@ def main():
         cpu_s = time.perf_counter() - t0
         cpu = {"value": args.cpu_steps * K_PROBES / cpu_s, "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "sample": f"first {args.cpu_steps} of the {T_STEPS} steps of the same workload "
-                         "(FP64 numpy/scipy; scipy sparse products are single-threaded)"}
+                         "(FP64 numpy/scipy; scipy sparse products are single-threaded)",
+               "affinity_cores": len(os.sched_getaffinity(0)), "blas_threads": blas_threads()}
 
     line = {
         "metric": "probe-matvec pairs/s",
@@ -747,11 +808,19 @@ def main():
                    "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_BYTES_PER_STEP,
+                     "traffic_source": TRAFFIC_SOURCE,
                      "kernel": "k_phase_both<16,true,8> (both directions of one step in one launch)",
                      "kernel_ms": kern_ms, "algorithmic_bytes": bytes_launch,
+                     "layout_bytes": sparse_algorithmic_bytes(csr.m, csr.n, csr.nnz, K_PROBES),
                      # HBM bytes the counters saw per step, over the same kernel time
                      "traffic_gbs": (TRAFFIC_BYTES_PER_STEP / (kern_ms / 1e3) / 1e9
-                                     if TRAFFIC_BYTES_PER_STEP else None)},
+                                     if TRAFFIC_BYTES_PER_STEP else None),
+                     # the second bound: 2 nnz random 8-byte gathers per step, against the
+                     # gather rate measured in this run for the same table sizes
+                     "gather": {"achieved": 2 * csr.nnz / (kern_ms / 1e3),
+                                "peak": 2 * csr.nnz / (ceil["gather_floor_ms"] / 1e3), "unit": "gathers/s",
+                                "frac": ceil["gather_floor_ms"] / kern_ms},
+                     "ceilings": ceil},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -386,6 +386,23 @@ int mfe_plan_set_targets(mfe_plan* plan, const double* row_target, const double*
 int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_blocks, const int64_t* col_ptr,
                         int64_t col_blocks);
 
+/* ---- Measurement probes (the ceilings the sparse step is compared against) ---------
+ *
+ * Each product of Algorithm 1 (Section 3.2) on a sparse matrix reads, per stored entry,
+ * one 8-byte descriptor of the other side at a random position, so the step is bounded
+ * by the rate of random gathers from a table of the descriptor table's size as well as by
+ * the streaming rate.  These calls measure the two rates in isolation on the current
+ * device: mean milliseconds per launch over `reps` launches (HIP events, after one
+ * untimed launch), written to the host pointer ms.  They allocate and free their own
+ * device buffers.  EINVAL for sizes or reps out of range, NULL ms. */
+
+/* `gathers` random 8-byte reads (hashed indices, 8 in flight per lane) from a table of
+ * table_bytes bytes (>= 8). */
+int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, void* stream);
+
+/* One read of a buffer of `bytes` bytes (>= 16) with 16-byte non-temporal loads. */
+int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream);
+
 /* Thread-local description of the last non-OK status (or a warning), never NULL. */
 const char* mfe_last_error(void);
 

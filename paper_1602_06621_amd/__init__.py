@@ -29,6 +29,8 @@ from ._ffi import (  # noqa: F401
     mlp_loss_grad,
     mlp_sizes,
     mlp_train,
+    probe_gather,
+    probe_stream,
     residual,
     version,
     warmstart_apply,

@@ -99,6 +99,8 @@ def _lib():
         "mfe_mlp_train": [vp, vp, vp, i32, vp, vp, i64, i64, i32, C.c_float, u64, vp, vp],
         "mfe_warmstart_apply": [i64, vp, vp, dbl, vp, vp],
         "mfe_check_targets": [i64, i64, dbl, dbl, C.POINTER(dbl)],
+        "mfe_probe_gather": [i64, i64, i32, C.POINTER(dbl), vp],
+        "mfe_probe_stream": [i64, i32, C.POINTER(dbl), vp],
         "mfe_plan_training_set": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, i64, u64, vp, vp, vp, C.POINTER(i64),
                                   vp],
     }
@@ -124,6 +126,20 @@ def check_targets(m: int, n: int, alpha: float, beta: float):
     _check(_lib().mfe_check_targets(int(m), int(n), float(alpha), float(beta), C.byref(rel)))
     msg = last_error()
     return rel.value, (msg if msg.startswith("warning:") else "")
+
+
+def probe_gather(table_bytes: int, gathers: int, reps: int = 5, stream=None) -> float:
+    """Milliseconds per launch of `gathers` random 8-byte reads from a table of table_bytes."""
+    ms = C.c_double()
+    _check(_lib().mfe_probe_gather(int(table_bytes), int(gathers), int(reps), C.byref(ms), _stream(stream)))
+    return ms.value
+
+
+def probe_stream(nbytes: int, reps: int = 5, stream=None) -> float:
+    """Milliseconds per launch of one streaming read of nbytes."""
+    ms = C.c_double()
+    _check(_lib().mfe_probe_stream(int(nbytes), int(reps), C.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def version() -> str:

@@ -1,0 +1,161 @@
+// Measurement probes for the ceilings the sparse engine's step is compared against.
+//
+// Every product of Algorithm 1 (Section 3.2) on a sparse matrix needs, per stored entry,
+// one random 8-byte read of the other side's descriptor table, so the step is bounded by
+// two rates of the memory system rather than by the HBM peak alone:
+//   * the rate of random 8-byte gathers from a table of a given size (which decides how
+//     much of it the L2 of each XCD holds), and
+//   * the rate of a plain streaming read (the entry streams).
+// These kernels measure both in isolation: the gather probe reads hashed indices (no
+// index stream) with eight gathers in flight per lane; the stream probe reads a buffer
+// once with 16-byte non-temporal loads.  Both fold what they read into one word per
+// thread so nothing is optimised away.
+#include "common.h"
+
+namespace mfe {
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kProbeThreads = 256;
+constexpr int kGatherBatch = 8;
+
+// 64-bit finaliser of MurmurHash3 (Appleby): a bijective mix, used to spread indices.
+__device__ inline uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+__global__ void k_fill_table(uint64_t* __restrict__ t, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = mix64((uint64_t)i + 1);
+}
+
+// Thread g performs gathers g, g + G, g + 2G, ... (G = grid size) below `total`, in
+// batches of kGatherBatch independent loads.
+__global__ __launch_bounds__(kProbeThreads) void k_gather_probe(const uint64_t* __restrict__ table, int64_t n,
+                                                                int64_t total, uint64_t salt,
+                                                                uint64_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t G = (int64_t)gridDim.x * blockDim.x;
+  uint64_t acc = 0;
+  for (int64_t q0 = g; q0 < total; q0 += G * kGatherBatch) {
+    uint64_t v[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int64_t q = q0 + (int64_t)u * G;
+      v[u] = q < total ? table[mix64((uint64_t)q ^ salt) % (uint64_t)n] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) acc ^= v[u];
+  }
+  out[g] = acc;
+}
+
+__global__ __launch_bounds__(kProbeThreads) void k_stream_probe(const u32x4* __restrict__ buf, int64_t n16,
+                                                                uint32_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t G = (int64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  int64_t i = g;
+  for (; i + 3 * G < n16; i += 4 * G) {
+    const u32x4 a = __builtin_nontemporal_load(buf + i);
+    const u32x4 b = __builtin_nontemporal_load(buf + i + G);
+    const u32x4 c = __builtin_nontemporal_load(buf + i + 2 * G);
+    const u32x4 d = __builtin_nontemporal_load(buf + i + 3 * G);
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
+  for (; i < n16; i += G) {
+    const u32x4 a = __builtin_nontemporal_load(buf + i);
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  out[g] = acc;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+int probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, hipStream_t st) {
+  const int64_t n = table_bytes / 8;
+  const int blocks = 2048;
+  DevBuf tab, out;
+  MFE_HIP(hipMalloc(&tab.p, sizeof(uint64_t) * (size_t)n));
+  MFE_HIP(hipMalloc(&out.p, sizeof(uint64_t) * (size_t)blocks * kProbeThreads));
+  k_fill_table<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((uint64_t*)tab.p, n);
+  EventPair ev;
+  MFE_HIP(hipEventCreate(&ev.a));
+  MFE_HIP(hipEventCreate(&ev.b));
+  // one untimed launch warms the table into the caches, as the step's tables are
+  k_gather_probe<<<blocks, kProbeThreads, 0, st>>>((const uint64_t*)tab.p, n, gathers, 0, (uint64_t*)out.p);
+  MFE_HIP(hipEventRecord(ev.a, st));
+  for (int r = 0; r < reps; ++r)
+    k_gather_probe<<<blocks, kProbeThreads, 0, st>>>((const uint64_t*)tab.p, n, gathers, (uint64_t)r + 1,
+                                                     (uint64_t*)out.p);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipEventRecord(ev.b, st));
+  MFE_HIP(hipEventSynchronize(ev.b));
+  float t = 0.f;
+  MFE_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+  *ms = (double)t / reps;
+  return MFE_OK;
+}
+
+int probe_stream(int64_t bytes, int32_t reps, double* ms, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  const int blocks = 8192;
+  DevBuf buf, out;
+  MFE_HIP(hipMalloc(&buf.p, (size_t)n16 * 16));
+  MFE_HIP(hipMalloc(&out.p, sizeof(uint32_t) * (size_t)blocks * kProbeThreads));
+  MFE_HIP(hipMemsetAsync(buf.p, 1, (size_t)n16 * 16, st));
+  EventPair ev;
+  MFE_HIP(hipEventCreate(&ev.a));
+  MFE_HIP(hipEventCreate(&ev.b));
+  k_stream_probe<<<blocks, kProbeThreads, 0, st>>>((const u32x4*)buf.p, n16, (uint32_t*)out.p);
+  MFE_HIP(hipEventRecord(ev.a, st));
+  for (int r = 0; r < reps; ++r)
+    k_stream_probe<<<blocks, kProbeThreads, 0, st>>>((const u32x4*)buf.p, n16, (uint32_t*)out.p);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipEventRecord(ev.b, st));
+  MFE_HIP(hipEventSynchronize(ev.b));
+  float t = 0.f;
+  MFE_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+  *ms = (double)t / reps;
+  return MFE_OK;
+}
+
+}  // namespace mfe
+
+extern "C" {
+
+int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, void* stream) {
+  mfe::clear_error();
+  if (table_bytes < 8 || gathers < 1 || reps < 1 || !ms)
+    return mfe::set_error(MFE_EINVAL, "need table_bytes >= 8, gathers >= 1, reps >= 1 and ms");
+  return mfe::probe_gather(table_bytes, gathers, reps, ms, (hipStream_t)stream);
+}
+
+int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream) {
+  mfe::clear_error();
+  if (bytes < 16 || reps < 1 || !ms) return mfe::set_error(MFE_EINVAL, "need bytes >= 16, reps >= 1 and ms");
+  return mfe::probe_stream(bytes, reps, ms, (hipStream_t)stream);
+}
+
+}  // extern "C"

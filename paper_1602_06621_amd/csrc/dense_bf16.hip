@@ -1,8 +1,10 @@
 // Algorithm 1 (Section 3.2) for dense bfloat16 A on the matrix cores (MFMA).
 //
 // Per step the two products are GEMMs against the probe block: Y = A (E S) (m x k) and
-// X = A' (D W) (n x k), k <= 64.  Probe operands are exact signs times bf16(e^x);
-// products accumulate in FP32 on v_mfma_f32_32x32x16_bf16; the square / step /
+// X = A' (D W) (n x k), k <= 64.  The scale e^x of a probe operand is carried as two
+// bf16 numbers, hi = bf16(e^x) and lo = bf16(e^x - hi) (relative error of hi + lo at most
+// about 2^-17 instead of bf16's 2^-9), each times the exact sign: two MFMA products per
+// tile, accumulated together in FP32 on v_mfma_f32_32x32x16_bf16.  The square / step /
 // project / average update runs in FP64.
 //
 // Layout.  The library keeps two copies of A in an MFMA-native tiled layout: tile
@@ -10,11 +12,11 @@
 // values A[32 rb + l%32][16 kc + 8 (l/32) + j], j < 8, in 16 consecutive bytes, so a
 // wavefront reads each tile with one fully coalesced 16-byte load per lane.  The second
 // copy is A' in the same layout, which turns the transposed product into the same
-// kernel.  Tiles are padded with zeros.  The probe operand of a chunk has the matching
-// layout (lane l holds probe 32 nb + l%32 at the same 8 k values), but is not stored as
-// a tile: per k chunk the pass loads the 16 bf16
-// scales and one sign byte per (probe, half chunk), 32 + 64 NB bytes, and assembles the
-// MFMA operand in registers (sign bit XORed into each scale).  A step is two launches:
+// kernel.  Tiles are padded with zeros.  The probe operands of a chunk have the matching
+// layout (lane l holds probe 32 nb + l%32 at the same 8 k values), but are not stored as
+// tiles: per k chunk the pass loads the 16 hi and 16 lo bf16 scales and one sign byte per
+// (probe, half chunk), 64 + 64 NB bytes, and assembles the two MFMA operands in registers
+// (sign bit XORed into each scale).  A step is two launches:
 // both passes (rows over A, then columns over A'), and the update of both sides, which
 // also writes the bf16 scales and (extra workgroups) the Philox sign bytes of the next
 // step.  A separate probe build makes the operands of the first step.
@@ -65,6 +67,17 @@ __device__ inline uint16_t bf16_rne(double x) {
   return (uint16_t)((sign << 15) | (e8 << 7) | keep);
 }
 
+// The low part of a two-term bf16 scale: bf16(x - hi), where hi = bf16_rne(x).  Values
+// below the smallest normal bf16 (2^-126) are flushed to zero; for the scales here
+// (x >= e^-80) that happens only when x - hi is below 2^-126, i.e. the two terms are
+// then exact to at least 2^-11 relative (2^-17 or better for x >= 2^-108).
+__device__ inline uint16_t bf16_lo(double x, uint16_t hi) {
+  const double h = (double)__uint_as_float((uint32_t)hi << 16);
+  const double r = x - h;  // exact in FP64: h has 8 significant bits and |r| <= ulp(h) / 2
+  if (!(fabs(r) >= 0x1p-126)) return (uint16_t)0;
+  return bf16_rne(r);
+}
+
 // Tiles of A (trans = 0) or A' (trans = 1) from the row-major input (bf16 bits).
 // R x C is the tiled matrix (R = m, C = n for A; R = n, C = m for A').
 __global__ void k_tile(const uint16_t* __restrict__ A, int64_t m, int64_t n, int64_t ld, int trans, int64_t RB,
@@ -96,17 +109,19 @@ __global__ void k_tile(const uint16_t* __restrict__ A, int64_t m, int64_t n, int
 }
 
 // Probe operands, kept compressed in memory and expanded into MFMA operands in
-// registers by the pass: per k chunk kc, the bf16 scales of its 16 indices
-// (scl[16 kc + i]; zero past the end) and one sign byte per (half h, probe p):
+// registers by the pass: per k chunk kc, the two-term bf16 scales of its 16 indices
+// (scl[16 kc + i] = hi, slo[16 kc + i] = lo; zero past the end) and one sign byte per
+// (half h, probe p):
 // sgn[((2 kc + h) 32 + p % 32) NB + p / 32] holds in bit j the sign of probe p at
 // index 16 kc + 8 h + j, which is bit k*K + p of the side's Philox stream (the layout
 // of the library's sign words); zero for p >= K or past the end.  Per chunk that is
-// 32 + 64 NB bytes instead of the 1 KiB operand tile per 32 probes.
+// 64 + 64 NB bytes instead of two 1 KiB operand tiles per 32 probes.
 struct ProbeSide {
   const double* scale;  // e^x of the indices of this side (first step), or null: sign bytes only
   int64_t C, KC;        // indices, k chunks
   uint64_t ctrl;        // Philox key word: (batch << 34) | (t << 2) | side
-  uint16_t* scl;        // [KC * 16]
+  uint16_t* scl;        // [KC * 16] hi parts
+  uint16_t* slo;        // [KC * 16] lo parts
   uint8_t* sgn;         // [KC][2][32][NB]
   int64_t groups;       // workgroups of kProbeChunks chunks
 };
@@ -130,7 +145,11 @@ __device__ __forceinline__ void probe_group(const ProbeSide& P, int64_t grp, int
   }
   if (P.scale && threadIdx.x < kProbeChunks * kChunk) {
     const int64_t kk = kk0 + threadIdx.x;
-    if (kk < P.KC * kChunk) P.scl[kk] = kk < P.C ? bf16_rne(P.scale[kk]) : (uint16_t)0;
+    if (kk < P.KC * kChunk) {
+      const uint16_t hi = kk < P.C ? bf16_rne(P.scale[kk]) : (uint16_t)0;
+      P.scl[kk] = hi;
+      P.slo[kk] = kk < P.C ? bf16_lo(P.scale[kk], hi) : (uint16_t)0;
+    }
   }
   __syncthreads();
   const int nout = kProbeChunks * 64 * NB;
@@ -165,7 +184,8 @@ __global__ __launch_bounds__(256) void k_probe_build(ProbeSide P0, ProbeSide P1,
 
 struct Bf16Side {
   const u32x4* tiles;   // [RB][KC][64]
-  const uint16_t* scl;  // probe operands, compressed (see ProbeSide)
+  const uint16_t* scl;  // probe operands, compressed (see ProbeSide): hi, lo, signs
+  const uint16_t* slo;
   const uint8_t* sgn;
   int64_t R, RB, KC;
   int splits;           // k ranges per row block
@@ -173,7 +193,8 @@ struct Bf16Side {
   float* part;          // [splits][RB * 32][32 NB] partial products
   double* x;
   double* xbar;
-  uint16_t* scl_out;    // bf16 e^x of this side: the other pass's probe scales next step
+  uint16_t* scl_out;    // hi and lo of e^x of this side: the other pass's probe scales next step
+  uint16_t* slo_out;
   double target;
 };
 
@@ -183,7 +204,7 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) {
   return r;
 }
 
-// Probe operands of one chunk for lane l from its 8 scales (16 bytes) and sign bytes:
+// Probe operands of one chunk for lane l from its 8 scales (16 bytes, hi or lo) and sign bytes:
 // the sign of index j goes to bit 15 of slot j (slots 2i and 2i+1 share 32-bit word i).
 template <int NB>
 __device__ __forceinline__ void expand_probes(const u32x4& sc, uint32_t sg, u32x4 (&op)[NB]) {
@@ -203,32 +224,39 @@ __device__ __forceinline__ void expand_probes(const u32x4& sc, uint32_t sg, u32x
 template <int NB, int RW, int F>
 struct ChunkGroup {
   u32x4 a[F][RW];
-  u32x4 sc[F];    // bf16 scales of the lane's 8 indices
+  u32x4 sc[F];    // hi bf16 scales of the lane's 8 indices
+  u32x4 sl[F];    // lo bf16 scales
   uint32_t sg[F]; // sign bytes of the lane's NB probes
-  // ps: scales as 16-byte groups, offset by the lane's half; pg: sign bytes (NB per
-  // lane), offset by the lane
+  // ps, pl: hi and lo scales as 16-byte groups, offset by the lane's half; pg: sign bytes
+  // (NB per lane), offset by the lane
   __device__ __forceinline__ void load(const u32x4* const (&at)[RW], const u32x4* __restrict__ ps,
-                                       const uint8_t* __restrict__ pg, int64_t kc) {
+                                       const u32x4* __restrict__ pl, const uint8_t* __restrict__ pg, int64_t kc) {
 #pragma unroll
     for (int u = 0; u < F; ++u) {
 #pragma unroll
       for (int r = 0; r < RW; ++r) a[u][r] = __builtin_nontemporal_load(at[r] + (kc + u) * 64);
       sc[u] = ps[(kc + u) * 2];
+      sl[u] = pl[(kc + u) * 2];
       if (NB == 2) sg[u] = *(const uint16_t*)(pg + (kc + u) * 128);
       else sg[u] = pg[(kc + u) * 64];
     }
   }
+  // per chunk: the hi product, then the lo product, into the same FP32 accumulator
   __device__ __forceinline__ void mma(f32x16 (&acc)[RW][NB]) const {
 #pragma unroll
     for (int u = 0; u < F; ++u) {
-      u32x4 op[NB];
-      expand_probes<NB>(sc[u], sg[u], op);
+      u32x4 oh[NB], ol[NB];
+      expand_probes<NB>(sc[u], sg[u], oh);
+      expand_probes<NB>(sl[u], sg[u], ol);
 #pragma unroll
       for (int r = 0; r < RW; ++r)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u][r]), as_bf16x8(op[b]), acc[r][b], 0, 0,
+        for (int b = 0; b < NB; ++b) {
+          acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u][r]), as_bf16x8(oh[b]), acc[r][b], 0, 0,
                                                               0);
+          acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[u][r]), as_bf16x8(ol[b]), acc[r][b], 0, 0,
+                                                              0);
+        }
     }
   }
 };
@@ -252,26 +280,27 @@ __device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int sp
 #pragma unroll
   for (int r = 0; r < RW; ++r) at[r] = S.tiles + (rb0 + r < S.RB ? rb0 + r : S.RB - 1) * S.KC * 64 + lane;
   const u32x4* __restrict__ ps = (const u32x4*)S.scl + (lane >> 5);
+  const u32x4* __restrict__ pl = (const u32x4*)S.slo + (lane >> 5);
   const uint8_t* __restrict__ pg = S.sgn + lane * NB;
   // double-buffered groups: the loads of group g + 1 are issued before the products of g
   const int64_t ngroups = (kend - kbeg) / F;
   ChunkGroup<NB, RW, F> g0, g1;
   int64_t kc = kbeg;
-  if (ngroups > 0) g0.load(at, ps, pg, kc);
+  if (ngroups > 0) g0.load(at, ps, pl, pg, kc);
   for (int64_t g = 0; g < ngroups; g += 2) {
-    if (g + 1 < ngroups) g1.load(at, ps, pg, kc + F);
+    if (g + 1 < ngroups) g1.load(at, ps, pl, pg, kc + F);
     g0.mma(acc);
     if (g + 1 >= ngroups) {
       kc += F;
       break;
     }
-    if (g + 2 < ngroups) g0.load(at, ps, pg, kc + 2 * F);
+    if (g + 2 < ngroups) g0.load(at, ps, pl, pg, kc + 2 * F);
     g1.mma(acc);
     kc += 2 * F;
   }
   for (; kc < kend; ++kc) {
     ChunkGroup<NB, RW, 1> one;
-    one.load(at, ps, pg, kc);
+    one.load(at, ps, pl, pg, kc);
     one.mma(acc);
   }
   // accumulator layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + v%4, column l%32
@@ -351,7 +380,10 @@ __device__ __forceinline__ void bf16_update(const Bf16Side& S, int64_t r, int j,
     if (!sgd_update(ss, k, S.target, sc, x, xb)) atomicOr(flag, 1);
     S.x[r] = x;
     S.xbar[r] = xb;
-    S.scl_out[r] = bf16_rne(exp(x));
+    const double ex = exp(x);
+    const uint16_t hi = bf16_rne(ex);
+    S.scl_out[r] = hi;
+    S.slo_out[r] = bf16_lo(ex, hi);
   }
 }
 
@@ -470,7 +502,7 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   const int64_t RBv = ceil_div(n, kRows), KCv = ceil_div(m, kChunk);  // tiles of A'
   Bufs B;
   u32x4 *tu, *tv;
-  uint16_t *scu, *scv;
+  uint16_t *scu, *scv, *slu, *slv;
   uint8_t *sgu, *sgv;
   double *u, *ub, *v, *vb, *su, *sv;
   int* flag;
@@ -478,8 +510,10 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   MFE_CHECK(B.alloc(&tv, RBv * KCv * 64));
   // probe operands for the row pass (columns, side 0) and the column pass (rows, side 1)
   MFE_CHECK(B.alloc(&scu, KCu * kChunk));
+  MFE_CHECK(B.alloc(&slu, KCu * kChunk));
   MFE_CHECK(B.alloc(&sgu, KCu * 64 * NB));
   MFE_CHECK(B.alloc(&scv, KCv * kChunk));
+  MFE_CHECK(B.alloc(&slv, KCv * kChunk));
   MFE_CHECK(B.alloc(&sgv, KCv * 64 * NB));
   MFE_CHECK(B.alloc(&u, m));
   MFE_CHECK(B.alloc(&ub, m));
@@ -513,8 +547,8 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
   // later steps get their scales from the updates and their sign bytes from the update
   // launch of the step before
   if (p->steps > 0) {
-    ProbeSide P0{sv, n, KCu, stream_ctrl(bt, 1, 0), scu, sgu, pg_u};
-    ProbeSide P1{su, m, KCv, stream_ctrl(bt, 1, 1), scv, sgv, pg_v};
+    ProbeSide P0{sv, n, KCu, stream_ctrl(bt, 1, 0), scu, slu, sgu, pg_u};
+    ProbeSide P1{su, m, KCv, stream_ctrl(bt, 1, 1), scv, slv, sgv, pg_v};
     k_probe_build<<<dim3((unsigned)(pg_u + pg_v)), dim3(256), 0, st>>>(P0, P1, k, NB, p->seed);
   }
   for (int t = 1; t <= p->steps; ++t) {
@@ -524,10 +558,10 @@ int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, doubl
     sc.gamma = p->gamma;
     sc.M = p->box_M;
     const bool more = t < p->steps;
-    ProbeSide N0{nullptr, n, KCu, stream_ctrl(bt, (uint64_t)t + 1, 0), scu, sgu, more ? pg_u : 0};
-    ProbeSide N1{nullptr, m, KCv, stream_ctrl(bt, (uint64_t)t + 1, 1), scv, sgv, more ? pg_v : 0};
-    Bf16Side R{tu, scu, sgu, m, RBu, KCu, Su, groups_u, partu, u, ub, scv, p->alpha * p->alpha};
-    Bf16Side Cc{tv, scv, sgv, n, RBv, KCv, Sv, groups_v, partv, v, vb, scu, p->beta * p->beta};
+    ProbeSide N0{nullptr, n, KCu, stream_ctrl(bt, (uint64_t)t + 1, 0), scu, slu, sgu, more ? pg_u : 0};
+    ProbeSide N1{nullptr, m, KCv, stream_ctrl(bt, (uint64_t)t + 1, 1), scv, slv, sgv, more ? pg_v : 0};
+    Bf16Side R{tu, scu, slu, sgu, m, RBu, KCu, Su, groups_u, partu, u, ub, scv, slv, p->alpha * p->alpha};
+    Bf16Side Cc{tv, scv, slv, sgv, n, RBv, KCv, Sv, groups_v, partv, v, vb, scu, slu, p->beta * p->beta};
     if (NB == 1) launch_step<1>(R, Cc, k, sc, flag, N0, N1, p->seed, st);
     else launch_step<2>(R, Cc, k, sc, flag, N0, N1, p->seed, st);
   }

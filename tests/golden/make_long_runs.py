@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE.  This script calls only the FP64 oracle (`oracle/`) and the seeded
 input generators (`workloads/`); nothing here comes from the GPU library.  The GPU tests
-in tests/test_gpu_long_runs.py regenerate the same inputs from the same seeds and compare
-against these files.
+(tests/test_gpu_sparse.py, tests/test_gpu_bf16.py) regenerate the same inputs from the
+same seeds and compare against these files.
 
   c1_prefix.npz  the headline workload (CSR 1,000,000 x 500,000, 10 distinct uniform
                  columns per row, values N(0,1) e^(r_i + c_j), r, c ~ N(0, 2^2), generator
@@ -59,8 +59,7 @@ def make_c1(path):
 
     A1.equilibrate(csr.to_scipy(), al, be, c["gamma"], c["M"], max(c["checkpoints"]), k=c["k"],
                    seed=c["seed"], on_step=on_step)
-    np.savez(path, rows=ri.astype(np.int32), cols=ci.astype(np.int32),
-             checkpoints=np.array(c["checkpoints"], dtype=np.int32), **saved)
+    np.savez(path, stride=np.int32(STRIDE), checkpoints=np.array(c["checkpoints"], dtype=np.int32), **saved)
 
 
 def make_c3(path):

@@ -208,3 +208,4 @@ def test_training_set_argument_checks(lib):
                                      C.byref(cnt), None) == -1
     assert lib.mfe_plan_training_set(buf, 1, 4, None, None, 0.1, 10.0, buf, buf, 0, 0, None, None, None,
                                      C.byref(cnt), None) == -1
+
