@@ -149,6 +149,23 @@ int mfe_check_targets(int64_t m, int64_t n, double alpha, double beta, double* r
 int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
                     double* u_bar, double* v_bar);
 
+/* mfe_equilibrate for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): MFE_DENSE_F64 only,
+ * same kernels and results as mfe_equilibrate, but every workspace is carved from one
+ * static device array of 8 MiB (one per device, held until the process ends); no
+ * hipMalloc, hipFree or allocating library call, and no host-to-device copy or memset
+ * node (scratch that must start at zero is cleared by a kernel).  A run needs
+ * 256-byte-aligned pieces of 32 (m + n) bytes of iterates, averages and scales, the sign
+ * words (about (m + n) k / 8 bytes), and for the single-workgroup paths (m + n <= 1792) an
+ * m x n FP64 transposed copy of A (not for k = 1, m <= 200, n <= 128) and a chunk of
+ * staged sign words.  EDIM when that exceeds 8 MiB (nothing is run); otherwise the
+ * errors of mfe_equilibrate; EUNSUPPORTED for other kinds.  Calls that overlap on one
+ * device (other threads, or other streams before this call's final synchronisation)
+ * share the array and race; calls in sequence are independent.  Synchronises p->stream
+ * at the end (the status). */
+int mfe_equilibrate_noalloc(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
+                            double* u_bar, double* v_bar);
+
 /* Plans: preprocessing (CSR -> CSC transpose, sliced-ELL layouts for both products)
  * done once and reused.  count >= 1 CSR matrices are equilibrated together in one
  * launch per step (the batched path).

@@ -21,6 +21,7 @@ from ._ffi import (  # noqa: F401
     default_alpha_beta,
     draw_signs,
     equilibrate,
+    equilibrate_noalloc,
     last_error,
     last_timing,
     library_path,

@@ -99,6 +99,7 @@ def _lib():
         "mfe_mlp_train": [vp, vp, vp, i32, vp, vp, i64, i64, i32, C.c_float, u64, vp, vp],
         "mfe_warmstart_apply": [i64, vp, vp, dbl, vp, vp],
         "mfe_check_targets": [i64, i64, dbl, dbl, C.POINTER(dbl)],
+        "mfe_equilibrate_noalloc": [C.POINTER(_Matrix), C.POINTER(_Params), vp, vp, vp, vp],
         "mfe_probe_gather": [i64, i64, i32, C.POINTER(dbl), vp],
         "mfe_probe_stream": [i64, i32, C.POINTER(dbl), vp],
         "mfe_plan_training_set": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, i64, u64, vp, vp, vp, C.POINTER(i64),
@@ -302,6 +303,27 @@ def equilibrate(A, alpha=None, beta=None, gamma=0.1, M=10.0, steps=100, probes=1
     p = _params(alpha, beta, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream)
     _check(lib.mfe_equilibrate(C.byref(s), C.byref(p), _ptr(d), _ptr(e), _ptr(ub), _ptr(vb)))
     return dict(d=d, e=e, u_bar=ub, v_bar=vb)
+
+
+def equilibrate_noalloc(A, alpha=None, beta=None, gamma=0.1, M=10.0, steps=100, probes=1, seed=0, t0=0,
+                        batch=0, u0=None, v0=None, stream=None, out=None, device="cuda"):
+    """mfe_equilibrate_noalloc (dense FP64): the library allocates nothing; the outputs are
+    the caller's (`out` = dict(d, e, u_bar, v_bar) of float64 device tensors, made here
+    when not given)."""
+    lib = _lib()
+    if alpha is None or beta is None:
+        alpha, beta = default_alpha_beta(A.m, A.n)
+    if out is None:
+        out = dict(d=torch.empty(A.m, dtype=torch.float64, device=device),
+                   e=torch.empty(A.n, dtype=torch.float64, device=device),
+                   u_bar=torch.empty(A.m, dtype=torch.float64, device=device),
+                   v_bar=torch.empty(A.n, dtype=torch.float64, device=device))
+    s = A.struct()
+    p = _params(alpha, beta, gamma, M, steps, probes, seed, t0, batch, u0, v0, stream)
+    _check(lib.mfe_equilibrate_noalloc(C.byref(s), C.byref(p), _ptr(out["d"], torch.float64),
+                                       _ptr(out["e"], torch.float64), _ptr(out.get("u_bar"), torch.float64),
+                                       _ptr(out.get("v_bar"), torch.float64)))
+    return out
 
 
 class Plan:

@@ -237,6 +237,19 @@ int mfe_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, d
   }
 }
 
+int mfe_equilibrate_noalloc(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e, double* u_bar,
+                            double* v_bar) {
+  clear_error();
+  if (!A) return set_error(MFE_EINVAL, "matrix is NULL");
+  MFE_CHECK(check_params(p, true));
+  if (!d || !e) return set_error(MFE_EINVAL, "outputs d and e are required");
+  if (A->m <= 0 || A->n <= 0) return set_error(MFE_EDIM, "m and n must be positive");
+  if (A->kind != MFE_DENSE_F64)
+    return set_error(MFE_EUNSUPPORTED, "the allocation-free entry point takes MFE_DENSE_F64 matrices only");
+  MFE_CHECK(check_targets(A->m, A->n, p->alpha, p->beta, nullptr));
+  return dense_f64_equilibrate_noalloc(A, p, d, e, u_bar, v_bar);
+}
+
 int mfe_plan_lsqr(mfe_plan* plan, const double* b, const double* d, const double* e, double tol,
                   int32_t max_iter, int32_t check_every, double* x, mfe_lsqr_info* info, void* stream) {
   clear_error();

@@ -7,6 +7,8 @@ namespace mfe {
 
 int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
                           double* u_bar, double* v_bar);
+int dense_f64_equilibrate_noalloc(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
+                                  double* u_bar, double* v_bar);
 int dense_bf16_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
                            double* u_bar, double* v_bar);
 int operator_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,

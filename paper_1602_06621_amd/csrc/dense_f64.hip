@@ -15,10 +15,18 @@
 // FP64, calls apply() for A (E S) and A' (D W), and runs the square/step/project update
 // in its own kernels (the unfused path).
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "dense.h"
 #include "sparse.h"
+
+// Scratch of the allocation-free entry point (mfe_equilibrate_noalloc): every device the
+// library runs on holds its own copy until the process ends.  Its address differs per
+// device and reaches the host only through hipGetSymbolAddress; in host code the name
+// `scratch` is not a device address and is never passed to a kernel or a copy.
+static constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace mfe {
 namespace {
@@ -458,6 +466,7 @@ __global__ void k_transpose(const double* __restrict__ A, int64_t m, int64_t n, 
   AT[j * m + i] = A[i * ld + j];
 }
 
+// Device buffers from hipMalloc, freed when the run returns.
 struct Bufs {
   std::vector<void*> p;
   ~Bufs() {
@@ -474,15 +483,54 @@ struct Bufs {
   }
 };
 
+// Device buffers carved from one caller-provided region (256-byte aligned pieces); with
+// base == nullptr it only adds up the bytes the pieces need.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  template <class T>
+  int alloc(T** out, int64_t n) {
+    off = (off + 255) & ~(size_t)255;
+    const size_t b = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+    *out = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += b;
+    if (base && off > cap) return set_error(MFE_EDIM, "scratch of %zu bytes exceeded", cap);
+    return MFE_OK;
+  }
+};
+
+__global__ void k_zero_words(uint64_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// The two sign segments of a dense run and their block prefix (written on the device, so
+// that a run makes no host-to-device copy), and the run's status flag cleared.
+__global__ void k_sign_tables(SignSeg* __restrict__ segs, int64_t* __restrict__ prefix, SignSeg h0, SignSeg h1,
+                              int* __restrict__ flag) {
+  if (threadIdx.x != 0) return;
+  segs[0] = h0;
+  segs[1] = h1;
+  prefix[0] = 0;
+  prefix[1] = h0.nblocks;
+  prefix[2] = h0.nblocks + h1.nblocks;
+  *flag = 0;
+}
+
+void zero_words(uint64_t* p, int64_t n, hipStream_t st) {
+  if (n > 0) k_zero_words<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(p, n);
+}
+
 // Sign words of one matrix: side 0 (columns, n*k bits) and side 1 (rows, m*k bits) in
 // one slot; the slot is refilled every step.
 struct DenseSigns {
+  SignSeg h[2];
   SignSeg* segs = nullptr;
   int64_t* prefix = nullptr;
   uint64_t* words = nullptr;
-  int64_t nblocks = 0, off_rows = 0;
-  int setup(Bufs& B, int64_t m, int64_t n, int k, int64_t batch, hipStream_t st) {
-    SignSeg h[2];
+  int64_t nwords = 0, nblocks = 0, off_rows = 0;
+  template <class Alloc>
+  int alloc(Alloc& B, int64_t m, int64_t n, int k, int64_t batch) {
     h[0].ctrl_lo = ((uint64_t)batch << 34) | 0ull;
     h[0].nblocks = ceil_div(n * k, 256);
     h[0].word_off = 0;
@@ -491,13 +539,17 @@ struct DenseSigns {
     h[1].word_off = 4 * h[0].nblocks + 4;
     off_rows = h[1].word_off;
     nblocks = h[0].nblocks + h[1].nblocks;
-    const int64_t pre[3] = {0, h[0].nblocks, nblocks};
+    nwords = h[1].word_off + 4 * h[1].nblocks + 4;
     MFE_CHECK(B.alloc(&segs, 2));
     MFE_CHECK(B.alloc(&prefix, 3));
-    MFE_CHECK(B.alloc(&words, h[1].word_off + 4 * h[1].nblocks + 4));
-    MFE_HIP(hipMemsetAsync(words, 0, sizeof(uint64_t) * (h[1].word_off + 4 * h[1].nblocks + 4), st));
-    MFE_HIP(hipMemcpyAsync(segs, h, sizeof h, hipMemcpyHostToDevice, st));
-    MFE_HIP(hipMemcpyAsync(prefix, pre, sizeof pre, hipMemcpyHostToDevice, st));
+    MFE_CHECK(B.alloc(&words, nwords));
+    return MFE_OK;
+  }
+  // tables and the flag on the device, words cleared (no host copy, no memset node)
+  int setup(int* flag, hipStream_t st) const {
+    k_sign_tables<<<dim3(1), dim3(64), 0, st>>>(segs, prefix, h[0], h[1], flag);
+    zero_words(words, nwords, st);
+    MFE_HIP(hipGetLastError());
     return MFE_OK;
   }
   int draw(uint64_t seed, uint64_t step, hipStream_t st) const {
@@ -538,54 +590,67 @@ int finish(int* flag, hipStream_t st) {
   return MFE_OK;
 }
 
-}  // namespace
+// Everything one dense FP64 run uses on the device, allocated before any launch: the
+// iterates, averages and scales of both sides, the status flag, the sign words, and for
+// the persistent paths the transposed copy of A and the staged sign words of a chunk.
+struct DenseWork {
+  double *u, *ub, *v, *vb, *su[2], *sv[2];
+  int* flag;
+  DenseSigns S;
+  bool tiny = false, persistent = false;
+  int32_t nb0 = 0, nb1 = 0, wps = 0;
+  size_t lds = 0;
+  int chunk = 0;
+  double* AT = nullptr;
+  uint64_t* sw = nullptr;
 
-int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e, double* u_bar,
-                          double* v_bar) {
-  if (!A->data) return set_error(MFE_EINVAL, "dense data is NULL");
-  if (A->ld < A->n) return set_error(MFE_EDIM, "ld < n");
-  if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "dense FP64 path supports at most 64 probes per step");
+  template <class Alloc>
+  int alloc(Alloc& B, int64_t m, int64_t n, int k, int steps, int64_t batch) {
+    MFE_CHECK(B.alloc(&u, m));
+    MFE_CHECK(B.alloc(&ub, m));
+    MFE_CHECK(B.alloc(&v, n));
+    MFE_CHECK(B.alloc(&vb, n));
+    for (int i = 0; i < 2; ++i) {
+      MFE_CHECK(B.alloc(&su[i], m));
+      MFE_CHECK(B.alloc(&sv[i], n));
+    }
+    MFE_CHECK(B.alloc(&flag, 1));
+    MFE_CHECK(S.alloc(B, m, n, k, batch));
+    nb0 = (int32_t)ceil_div(n * k, 256);
+    nb1 = (int32_t)ceil_div(m * k, 256);
+    wps = 4 * (nb0 + nb1) + 8;
+    tiny = k == 1 && m <= kTinyWaves * kTinyRM && n <= 64 * kTinyCM && wps <= kTinyThreads;
+    lds = sizeof(double) * (size_t)(4 * (m + n)) + sizeof(uint64_t) * (size_t)(2 * wps);
+    persistent = tiny || (k <= 16 && m + n <= kPersistMaxDim && m * n * k <= kPersistMaxWork && lds <= 65536 &&
+                          wps <= kPersistMaxWords);
+    if (persistent && steps > 0) {
+      if (!tiny) MFE_CHECK(B.alloc(&AT, m * n));
+      chunk = std::min(steps, kPersistChunk);
+      MFE_CHECK(B.alloc(&sw, (int64_t)chunk * wps));
+    }
+    return MFE_OK;
+  }
+};
+
+// The launches of one dense FP64 run on buffers already in place (no allocation).
+int dense_f64_run(const DenseWork& w, const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
+                  double* u_bar, double* v_bar) {
   hipStream_t st = (hipStream_t)p->stream;
   const int64_t m = A->m, n = A->n;
   const int k = p->probes;
-  Bufs B;
-  double *u, *ub, *v, *vb, *su[2], *sv[2];
-  int* flag;
-  MFE_CHECK(B.alloc(&u, m));
-  MFE_CHECK(B.alloc(&ub, m));
-  MFE_CHECK(B.alloc(&v, n));
-  MFE_CHECK(B.alloc(&vb, n));
-  for (int i = 0; i < 2; ++i) {
-    MFE_CHECK(B.alloc(&su[i], m));
-    MFE_CHECK(B.alloc(&sv[i], n));
-  }
-  MFE_CHECK(B.alloc(&flag, 1));
-  DenseSigns S;
-  MFE_CHECK(S.setup(B, m, n, k, p->batch, st));
-  MFE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  k_dense_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, su[0], flag);
-  k_dense_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv[0], flag);
+  double *u = w.u, *ub = w.ub, *v = w.v, *vb = w.vb;
+  int* flag = w.flag;
+  MFE_CHECK(w.S.setup(flag, st));
+  k_dense_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, w.su[0], flag);
+  k_dense_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, w.sv[0], flag);
   const double* Ad = (const double*)A->data;
-  const int32_t nb0 = (int32_t)ceil_div(n * k, 256), nb1 = (int32_t)ceil_div(m * k, 256);
-  const int32_t wps = 4 * (nb0 + nb1) + 8;
-  const bool tiny = k == 1 && m <= kTinyWaves * kTinyRM && n <= 64 * kTinyCM && wps <= kTinyThreads;
-  const size_t lds = sizeof(double) * (size_t)(4 * (m + n)) + sizeof(uint64_t) * (size_t)(2 * wps);
-  const bool persistent =
-      tiny || (k <= 16 && m + n <= kPersistMaxDim && m * n * k <= kPersistMaxWork && lds <= 65536 &&
-               wps <= kPersistMaxWords);
-  if (persistent && p->steps > 0) {
-    double* AT = nullptr;
-    if (!tiny) {
-      MFE_CHECK(B.alloc(&AT, m * n));
-      k_transpose<<<dim3((unsigned)ceil_div(m * n, 256)), dim3(256), 0, st>>>(Ad, m, n, A->ld, AT);
-    }
-    const int chunk = std::min(p->steps, kPersistChunk);
-    uint64_t* sw;
-    MFE_CHECK(B.alloc(&sw, (int64_t)chunk * wps));
-    MFE_HIP(hipMemsetAsync(sw, 0, sizeof(uint64_t) * (size_t)chunk * wps, st));
+  if (w.persistent && p->steps > 0) {
+    if (!w.tiny)
+      k_transpose<<<dim3((unsigned)ceil_div(m * n, 256)), dim3(256), 0, st>>>(Ad, m, n, A->ld, w.AT);
+    zero_words(w.sw, (int64_t)w.chunk * w.wps, st);
     PersistArgs pa;
     pa.A = Ad;
-    pa.AT = AT;
+    pa.AT = w.AT;
     pa.m = m;
     pa.n = n;
     pa.ld = A->ld;
@@ -599,46 +664,106 @@ int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double
     pa.M = p->box_M;
     pa.tgt_row = p->alpha * p->alpha;
     pa.tgt_col = p->beta * p->beta;
-    pa.sw = sw;
-    pa.nb0 = nb0;
-    pa.wps = wps;
+    pa.sw = w.sw;
+    pa.nb0 = w.nb0;
+    pa.wps = w.wps;
     pa.flag = flag;
-    for (int t1 = 1; t1 <= p->steps; t1 += chunk) {
-      const int ns = std::min(chunk, p->steps - t1 + 1);
-      k_sign_chunk<<<dim3((unsigned)ceil_div((int64_t)ns * (nb0 + nb1), 256)), dim3(256), 0, st>>>(
-          sw, t1, ns, nb0, nb1, wps, p->seed, p->batch);
+    for (int t1 = 1; t1 <= p->steps; t1 += w.chunk) {
+      const int ns = std::min(w.chunk, p->steps - t1 + 1);
+      k_sign_chunk<<<dim3((unsigned)ceil_div((int64_t)ns * (w.nb0 + w.nb1), 256)), dim3(256), 0, st>>>(
+          w.sw, t1, ns, w.nb0, w.nb1, w.wps, p->seed, p->batch);
       pa.t_begin = (double)t1;
       pa.nsteps = ns;
       const dim3 g(1), b(kPersistThreads);
-      if (tiny) k_dense_tiny<<<g, dim3(kTinyThreads), 0, st>>>(pa);
-      else if (k <= 1) k_dense_persistent<1><<<g, b, lds, st>>>(pa);
-      else if (k <= 2) k_dense_persistent<2><<<g, b, lds, st>>>(pa);
-      else if (k <= 4) k_dense_persistent<4><<<g, b, lds, st>>>(pa);
-      else if (k <= 8) k_dense_persistent<8><<<g, b, lds, st>>>(pa);
-      else k_dense_persistent<16><<<g, b, lds, st>>>(pa);
+      if (w.tiny) k_dense_tiny<<<g, dim3(kTinyThreads), 0, st>>>(pa);
+      else if (k <= 1) k_dense_persistent<1><<<g, b, w.lds, st>>>(pa);
+      else if (k <= 2) k_dense_persistent<2><<<g, b, w.lds, st>>>(pa);
+      else if (k <= 4) k_dense_persistent<4><<<g, b, w.lds, st>>>(pa);
+      else if (k <= 8) k_dense_persistent<8><<<g, b, w.lds, st>>>(pa);
+      else k_dense_persistent<16><<<g, b, w.lds, st>>>(pa);
       MFE_HIP(hipGetLastError());
     }
   } else {
-  for (int t = 1; t <= p->steps; ++t) {
-    MFE_CHECK(S.draw(p->seed, (uint64_t)t, st));
-    const int cur = t & 1, prev = cur ^ 1;
-    DenseSide R{u, ub, sv[prev], su[cur], S.words, p->alpha * p->alpha};              // gathers s (side 0)
-    DenseSide C{v, vb, su[prev], sv[cur], S.words + S.off_rows, p->beta * p->beta};  // gathers w (side 1)
-    const StepScalars sc = scalars(p, t);
-    if (k <= 1) launch_dense_step<1>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else if (k <= 2) launch_dense_step<2>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else if (k <= 4) launch_dense_step<4>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else if (k <= 8) launch_dense_step<8>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else if (k <= 16) launch_dense_step<16>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else if (k <= 32) launch_dense_step<32>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-    else launch_dense_step<64>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
-  }
+    for (int t = 1; t <= p->steps; ++t) {
+      MFE_CHECK(w.S.draw(p->seed, (uint64_t)t, st));
+      const int cur = t & 1, prev = cur ^ 1;
+      DenseSide R{u, ub, w.sv[prev], w.su[cur], w.S.words, p->alpha * p->alpha};                 // gathers s (side 0)
+      DenseSide C{v, vb, w.su[prev], w.sv[cur], w.S.words + w.S.off_rows, p->beta * p->beta};  // gathers w (side 1)
+      const StepScalars sc = scalars(p, t);
+      if (k <= 1) launch_dense_step<1>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else if (k <= 2) launch_dense_step<2>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else if (k <= 4) launch_dense_step<4>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else if (k <= 8) launch_dense_step<8>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else if (k <= 16) launch_dense_step<16>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else if (k <= 32) launch_dense_step<32>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+      else launch_dense_step<64>(Ad, m, n, A->ld, R, C, k, sc, flag, st);
+    }
   }
   MFE_HIP(hipGetLastError());
   k_dense_output<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, ub, d, u_bar);
   k_dense_output<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, vb, e, v_bar);
   MFE_HIP(hipGetLastError());
   return finish(flag, st);
+}
+
+int dense_checks(const mfe_matrix* A, const mfe_equil_params* p) {
+  if (!A->data) return set_error(MFE_EINVAL, "dense data is NULL");
+  if (A->ld < A->n) return set_error(MFE_EDIM, "ld < n");
+  if (p->probes > 64) return set_error(MFE_EUNSUPPORTED, "dense FP64 path supports at most 64 probes per step");
+  return MFE_OK;
+}
+
+// ---- the allocation-free variant: the file-scope scratch array above, one per device
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(char** out) {
+  int dev = -1;
+  MFE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(MFE_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(MFE_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MFE_OK;
+}
+
+}  // namespace
+
+int dense_f64_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e, double* u_bar,
+                          double* v_bar) {
+  MFE_CHECK(dense_checks(A, p));
+  Bufs B;
+  DenseWork w;
+  MFE_CHECK(w.alloc(B, A->m, A->n, p->probes, p->steps, p->batch));
+  return dense_f64_run(w, A, p, d, e, u_bar, v_bar);
+}
+
+int dense_f64_equilibrate_noalloc(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e,
+                                  double* u_bar, double* v_bar) {
+  MFE_CHECK(dense_checks(A, p));
+  Arena need;
+  DenseWork w;
+  MFE_CHECK(w.alloc(need, A->m, A->n, p->probes, p->steps, p->batch));
+  if (need.off > kScratchBytes)
+    return set_error(MFE_EDIM,
+                     "a %lld x %lld run with %d probes needs %zu bytes of scratch; the allocation-free entry point "
+                     "has %zu (use mfe_equilibrate)",
+                     (long long)A->m, (long long)A->n, p->probes, need.off, kScratchBytes);
+  char* base = nullptr;
+  MFE_CHECK(scratch_for_current_device(&base));
+  Arena ar;
+  ar.base = base;
+  ar.cap = kScratchBytes;
+  MFE_CHECK(w.alloc(ar, A->m, A->n, p->probes, p->steps, p->batch));
+  return dense_f64_run(w, A, p, d, e, u_bar, v_bar);
 }
 
 int operator_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double* d, double* e, double* u_bar,
@@ -664,8 +789,8 @@ int operator_equilibrate(const mfe_matrix* A, const mfe_equil_params* p, double*
   MFE_CHECK(B.alloc(&X, n * k));
   MFE_CHECK(B.alloc(&flag, 1));
   DenseSigns S;
-  MFE_CHECK(S.setup(B, m, n, k, p->batch, st));
-  MFE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  MFE_CHECK(S.alloc(B, m, n, k, p->batch));
+  MFE_CHECK(S.setup(flag, st));
   k_dense_init<<<dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st>>>(m, p->u0, p->box_M, u, ub, su[0], flag);
   k_dense_init<<<dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st>>>(n, p->v0, p->box_M, v, vb, sv[0], flag);
   for (int t = 1; t <= p->steps; ++t) {

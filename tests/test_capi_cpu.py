@@ -209,3 +209,17 @@ def test_training_set_argument_checks(lib):
     assert lib.mfe_plan_training_set(buf, 1, 4, None, None, 0.1, 10.0, buf, buf, 0, 0, None, None, None,
                                      C.byref(cnt), None) == -1
 
+
+def test_noalloc_entry_point_refuses_on_host(lib):
+    """The allocation-free entry point takes dense FP64 only and refuses a run that needs
+    more than its 8 MiB scratch before any device work."""
+    s = _csr_struct(300000, 10)
+    dummy = C.c_void_p(16)
+    assert lib.mfe_equilibrate_noalloc(C.byref(s), C.byref(_params(alpha=(10 / 300000) ** 0.25,
+                                                                    beta=(300000 / 10) ** 0.25)),
+                                       dummy, dummy, None, None) == -6
+    s.kind, s.ld, s.data = 0, 10, C.c_void_p(16)
+    p = _params(alpha=(10 / 300000) ** 0.25, beta=(300000 / 10) ** 0.25)
+    assert lib.mfe_equilibrate_noalloc(C.byref(s), C.byref(p), dummy, dummy, None, None) == -2
+    assert "scratch" in lib.mfe_last_error().decode()
+    assert lib.mfe_equilibrate_noalloc(C.byref(s), C.byref(p), None, None, None, None) == -1
