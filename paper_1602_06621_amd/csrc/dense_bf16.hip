@@ -204,17 +204,30 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) {
   return r;
 }
 
-// Probe operands of one chunk for lane l from its 8 scales (16 bytes, hi or lo) and sign bytes:
-// the sign of index j goes to bit 15 of slot j (slots 2i and 2i+1 share 32-bit word i).
+// Sign masks of the probe operands: entry y (a sign byte) holds, for each index j < 8 of
+// the byte, bit 15 of slot j set when bit j of y is set (slots 2i and 2i+1 share 32-bit
+// word i).  XORed into the 16 bytes of 8 bf16 scales it gives the signed operand.  Kept in
+// LDS (4 KiB per workgroup) so that a chunk's operands cost one LDS read and eight XORs per
+// probe block instead of the bit shuffling.
+__device__ inline u32x4 sign_mask(uint32_t y) {
+  u32x4 m;
+  m.x = ((y & 1u) << 15) | (((y >> 1) & 1u) << 31);
+  m.y = (((y >> 2) & 1u) << 15) | (((y >> 3) & 1u) << 31);
+  m.z = (((y >> 4) & 1u) << 15) | (((y >> 5) & 1u) << 31);
+  m.w = (((y >> 6) & 1u) << 15) | (((y >> 7) & 1u) << 31);
+  return m;
+}
+
+// Probe operands of one chunk for lane l from its 8 hi and 8 lo scales (16 bytes each) and
+// its sign bytes (byte b: probe block b).
 template <int NB>
-__device__ __forceinline__ void expand_probes(const u32x4& sc, uint32_t sg, u32x4 (&op)[NB]) {
+__device__ __forceinline__ void expand_probes(const u32x4& sc, const u32x4& sl, uint32_t sg,
+                                              const u32x4* __restrict__ masks, u32x4 (&oh)[NB], u32x4 (&ol)[NB]) {
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const uint32_t y = sg >> (8 * b);
-    op[b].x = sc.x ^ ((y << 15) & 0x8000u) ^ ((y << 30) & 0x80000000u);
-    op[b].y = sc.y ^ ((y << 13) & 0x8000u) ^ ((y << 28) & 0x80000000u);
-    op[b].z = sc.z ^ ((y << 11) & 0x8000u) ^ ((y << 26) & 0x80000000u);
-    op[b].w = sc.w ^ ((y << 9) & 0x8000u) ^ ((y << 24) & 0x80000000u);
+    const u32x4 mk = masks[(sg >> (8 * b)) & 0xFFu];
+    oh[b] = sc ^ mk;
+    ol[b] = sl ^ mk;
   }
 }
 
@@ -242,12 +255,11 @@ struct ChunkGroup {
     }
   }
   // per chunk: the hi product, then the lo product, into the same FP32 accumulator
-  __device__ __forceinline__ void mma(f32x16 (&acc)[RW][NB]) const {
+  __device__ __forceinline__ void mma(f32x16 (&acc)[RW][NB], const u32x4* __restrict__ masks) const {
 #pragma unroll
     for (int u = 0; u < F; ++u) {
       u32x4 oh[NB], ol[NB];
-      expand_probes<NB>(sc[u], sg[u], oh);
-      expand_probes<NB>(sl[u], sg[u], ol);
+      expand_probes<NB>(sc[u], sl[u], sg[u], masks, oh, ol);
 #pragma unroll
       for (int r = 0; r < RW; ++r)
 #pragma unroll
@@ -262,7 +274,7 @@ struct ChunkGroup {
 };
 
 template <int NB, int RW, int F>
-__device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int split) {
+__device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int split, const u32x4* __restrict__ masks) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t rb0 = (grp * kWaves + wave) * RW;
   if (rb0 >= S.RB) return;
@@ -287,21 +299,22 @@ __device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int sp
   ChunkGroup<NB, RW, F> g0, g1;
   int64_t kc = kbeg;
   if (ngroups > 0) g0.load(at, ps, pl, pg, kc);
-  for (int64_t g = 0; g < ngroups; g += 2) {
-    if (g + 1 < ngroups) g1.load(at, ps, pl, pg, kc + F);
-    g0.mma(acc);
-    if (g + 1 >= ngroups) {
-      kc += F;
-      break;
-    }
+  int64_t g = 0;
+  for (; g + 2 <= ngroups; g += 2) {
+    g1.load(at, ps, pl, pg, kc + F);
+    g0.mma(acc, masks);
     if (g + 2 < ngroups) g0.load(at, ps, pl, pg, kc + 2 * F);
-    g1.mma(acc);
+    g1.mma(acc, masks);
     kc += 2 * F;
+  }
+  if (g < ngroups) {  // odd number of groups: the last one is in g0
+    g0.mma(acc, masks);
+    kc += F;
   }
   for (; kc < kend; ++kc) {
     ChunkGroup<NB, RW, 1> one;
     one.load(at, ps, pl, pg, kc);
-    one.mma(acc);
+    one.mma(acc, masks);
   }
   // accumulator layout: lane l, register v -> row 8 (v/4) + 4 (l/32) + v%4, column l%32
 #pragma unroll
@@ -321,10 +334,13 @@ __device__ __forceinline__ void bf16_pass(const Bf16Side& S, int64_t grp, int sp
 // Workgroup b < R.groups * R.splits belongs to the row pass.
 template <int NB, int RW, int F>
 __global__ __launch_bounds__(kWaves * 64) void k_bf16_pass(Bf16Side R, Bf16Side C) {
+  __shared__ u32x4 masks[256];
+  for (int y = threadIdx.x; y < 256; y += kWaves * 64) masks[y] = sign_mask((uint32_t)y);
+  __syncthreads();
   const int64_t nr = R.groups * R.splits;
   const int64_t b = blockIdx.x;
-  if (b < nr) bf16_pass<NB, RW, F>(R, b % R.groups, (int)(b / R.groups));
-  else bf16_pass<NB, RW, F>(C, (b - nr) % C.groups, (int)((b - nr) / C.groups));
+  if (b < nr) bf16_pass<NB, RW, F>(R, b % R.groups, (int)(b / R.groups), masks);
+  else bf16_pass<NB, RW, F>(C, (b - nr) % C.groups, (int)((b - nr) / C.groups), masks);
 }
 
 // Sum over the eight lanes of an aligned group (every lane gets the sum).
