@@ -32,12 +32,15 @@ struct LsqrScal {
   int iter;
 };
 
-// Sum of 256 doubles of a block, fixed order (tree in LDS).
+constexpr int kScal = 1024;  // threads of the single-workgroup scalar steps
+
+// Sum of the NT doubles of a block of NT threads, fixed order (tree in LDS).
+template <int NT = kRed>
 __device__ double block_sum(double v) {
-  __shared__ double sh[kRed];
+  __shared__ double sh[NT];
   sh[threadIdx.x] = v;
   __syncthreads();
-  for (int s = kRed / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
@@ -71,6 +74,22 @@ inline SliceMap slice_map(int64_t nslices) {
   return m;
 }
 
+// sum over slots [q0, q1) of a_q f(a_q) g[idx_q] for one lane's row (f = 1, or a_q when
+// SQ: the squared entries of the residual pass), in slot order.  One slot at a time:
+// batching the entry loads and the gathers (4 or 8 slots in flight per lane, with or
+// without non-temporal entry loads) was measured slower on the headline matrix (195-210
+// against 173 us per LSQR iteration).
+template <bool SQ>
+__device__ __forceinline__ double row_dot(const int2* __restrict__ e, int q0, int q1, const double* __restrict__ g) {
+  double acc = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    const int2 en = e[(int64_t)q * kSlice];
+    const double a = (double)__int_as_float(en.y);
+    acc += SQ ? a * a * g[en.x] : a * g[en.x];
+  }
+  return acc;
+}
+
 // Row sums sum_q a_q g[idx_q] of slice s for lane `lane`, returned in the group's first
 // wavefront (wsub = 0; 0 elsewhere and for s >= nslices).  Every thread of the workgroup
 // must call it (it has a barrier when P > 1).
@@ -84,11 +103,7 @@ __device__ double slice_row_sum(const SideDev& S, const double* __restrict__ g, 
     const int width = (int)((S.slice_off[s + 1] - base) / kSlice);
     const int chunk = (width + P - 1) / P;
     const int q0 = wsub * chunk, q1 = min(len, q0 + chunk);
-    const int2* e = S.ent + base + lane;
-    for (int q = q0; q < q1; ++q) {
-      const int2 en = e[(int64_t)q * kSlice];
-      acc += (double)__int_as_float(en.y) * g[en.x];
-    }
+    acc = row_dot<false>(S.ent + base + lane, q0, q1, g);
   }
   if (P == 1) return acc;
   part[wave][lane] = acc;
@@ -151,13 +166,7 @@ __global__ __launch_bounds__(kRed) void k_sell_rownorm(SideDev S, const double* 
     const int64_t s = r >> 6;
     const int lane = (int)(r & 63);
     const int len = S.len[r];
-    const int2* e = S.ent + S.slice_off[s] + lane;
-    double acc = 0.0;
-    for (int q = 0; q < len; ++q) {
-      const int2 en = e[(int64_t)q * kSlice];
-      const double a = (double)__int_as_float(en.y);
-      acc += a * a * g2[en.x];
-    }
+    const double acc = row_dot<true>(S.ent + S.slice_off[s] + lane, 0, len, g2);
     const double dev = sqrt((own2 ? own2[r] : 1.0) * acc) - target;
     all = dev * dev;
     if (len > 0) ne = all;
@@ -304,13 +313,15 @@ void reduce_long(const double* v, int64_t n, double* scratch, double* out, hipSt
 }
 
 // After the forward product: beta = ||p||, coefficients for the transposed product.
-// The partial sums of the forward pass are reduced here.
-__global__ __launch_bounds__(kRed) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
-                                                    int it = 0) {
-  if (it > 0 && threadIdx.x == 0) sc->iter = it;  // before any use below (same thread)
+// The partial sums of the forward pass are reduced here.  next_iter != 0 starts the next
+// iteration (the count is kept on the device, so that every iteration is the same
+// sequence of launches).
+__global__ __launch_bounds__(kScal) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
+                                                     int next_iter = 0) {
+  if (next_iter && threadIdx.x == 0) sc->iter += 1;  // before any use below (same thread)
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
-  const double t = block_sum(s);
+  for (int64_t i = threadIdx.x; i < n; i += kScal) s += partial[i];
+  const double t = block_sum<kScal>(s);
   if (threadIdx.x == 0) {
     const double beta = sqrt(t);
     sc->beta = beta;
@@ -323,11 +334,11 @@ __global__ __launch_bounds__(kRed) void k_scal_beta(const double* __restrict__ p
 
 // After the transposed product: alpha_{i+1} = ||q|| and the plane rotation.  init != 0
 // is the start of the method (alpha_1 v_1 = Abar' u_1, phibar = beta_1, rhobar = alpha_1).
-__global__ __launch_bounds__(kRed) void k_scal_alpha(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
-                                                     int init) {
+__global__ __launch_bounds__(kScal) void k_scal_alpha(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
+                                                      int init) {
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kRed) s += partial[i];
-  const double t = block_sum(s);
+  for (int64_t i = threadIdx.x; i < n; i += kScal) s += partial[i];
+  const double t = block_sum<kScal>(s);
   if (threadIdx.x == 0) {
     const double an = sqrt(t);
     sc->inv_alpha = an > 0.0 ? 1.0 / an : 0.0;
@@ -533,6 +544,18 @@ struct DenseOps : Ops {
 };
 
 // LSQR driver over any Ops (see the stopping rule in mfe.h).
+// A captured graph and its capture stream, released on every return path.
+struct GraphHolder {
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphHolder() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
              int32_t check_every, double* x_out, mfe_lsqr_info* info, hipStream_t st) {
   const int64_t nr = ops.rows(), nc = ops.cols();
@@ -569,10 +592,10 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);   // du = D u, gathered by the transposed product
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
   reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
-  k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
+  k_scal_beta<<<1, kScal, 0, st>>>(part, 1, sc);
   // v = E A' D u / beta_1 (previous v is zero)
   ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);
-  k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
+  k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
   k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
   MFE_HIP(hipGetLastError());
 
@@ -590,16 +613,39 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
     inf.stop_reason = 3;
     max_iter = 0;
   }
-  for (int it = 1; it <= max_iter; ++it) {
+  // One iteration: five launches with no host involvement.
+  auto iteration = [&](hipStream_t s) {
     // p = D A E v - alpha u  (u normalised), du = D p, partial ||p||^2
-    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);
-    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
+    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, s);
+    k_scal_beta<<<1, kScal, 0, s>>>(part, ops.fwd_blocks(), sc, 1);  // also counts the iteration
     // q = E A' D p / beta - beta v, partial ||q||^2
-    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);
-    k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
-    k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, s);
+    k_scal_alpha<<<1, kScal, 0, s>>>(part, ops.bwd_blocks(), sc, 0);
+    k_lsqr_update<<<upd_grid, 256, 0, s>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+  };
+  // The check_every iterations between two residual checks are captured once in a HIP
+  // graph and replayed (the launches are identical from one block to the next); a
+  // shorter last block runs eagerly.
+  GraphHolder G;
+  for (int it = 1; it <= max_iter;) {
+    const int block_end =
+        (int)std::min<int64_t>(max_iter, ((int64_t)(it - 1) / check_every + 1) * (int64_t)check_every);
+    const int nblk = block_end - it + 1;
+    if (nblk == check_every && check_every > 1) {
+      if (!G.exec) {
+        MFE_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        MFE_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < check_every; ++i) iteration(G.cap);
+        MFE_HIP(hipStreamEndCapture(G.cap, &G.graph));
+        MFE_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+      }
+      MFE_HIP(hipGraphLaunch(G.exec, st));
+    } else {
+      for (int i = 0; i < nblk; ++i) iteration(st);
+    }
     MFE_HIP(hipGetLastError());
-    if (it % check_every == 0 || it == max_iter) {
+    it = block_end + 1;
+    {
       // residual of the original system: A (E xbar) - b, reduced over the rows
       k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, w_tmp);
       ops.fwd(nullptr, w_tmp, nullptr, &sc->neg_one, bb, res, nullptr, part, st);
@@ -608,7 +654,7 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
       MFE_HIP(hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st));
       MFE_HIP(hipStreamSynchronize(st));
       const double rel = std::sqrt(h.res2) / bnorm;
-      inf.iters = h.breakdown > 0 ? h.breakdown : it;
+      inf.iters = h.breakdown > 0 ? h.breakdown : block_end;
       inf.rel_resid = rel;
       inf.normal_eq = h.normal_eq;
       if (rel <= tol) {
@@ -917,9 +963,9 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
   reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
-  k_scal_beta<<<1, kRed, 0, st>>>(part, 1, sc);
+  k_scal_beta<<<1, kScal, 0, st>>>(part, 1, sc);
   ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);  // alpha_1 v_1 = Abar' u_1
-  k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
+  k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
   k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
   k_record<<<1, 1, 0, st>>>(sc, hist, 0);
   MFE_HIP(hipGetLastError());
@@ -928,9 +974,9 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
     ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);  // beta u = Abar v - alpha u
-    k_scal_beta<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
+    k_scal_beta<<<1, kScal, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
     ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);  // alpha v = Abar' u - beta v
-    k_scal_alpha<<<1, kRed, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
+    k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
     k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
     k_record<<<1, 1, 0, st>>>(sc, hist, it);
     MFE_HIP(hipGetLastError());

@@ -41,8 +41,10 @@ __device__ __forceinline__ void accumulate(double (&acc)[KP], double t, uint64_t
 // Descriptor codecs.  Wide: {FP64 scale, 64 sign bits} (16 B).  Packed (8 B, KP <= 16 and
 // |x| <= 11): e^x has an unbiased binary exponent in [-16, 15], stored in 5 bits; the
 // low KP bits hold the probe signs and the mantissa keeps 52 - max(0, KP - 7) bits
-// (truncated: relative error below 2^-43 for KP = 16, exact for KP <= 7).  Halving the
-// gathered table keeps more of it in each XCD's L2, which sets the gather rate.
+// (rounded to nearest: relative error at most 2^-44 for KP = 16, exact for KP <= 7; a
+// carry out of the mantissa moves into the exponent, which stays in range because
+// e^11 < 2^16).  Halving the gathered table keeps more of it in each XCD's L2, which
+// sets the gather rate.
 template <int KP, bool PACKED>
 struct Codec;
 
@@ -73,17 +75,25 @@ struct Codec<KP, true> {
     scale = __longlong_as_double((long long)((ex << 52) | mant));
   }
   __device__ static inline T encode(double scale, uint64_t bits) {
-    const uint64_t u = (uint64_t)__double_as_longlong(scale);
+    uint64_t u = (uint64_t)__double_as_longlong(scale);
+    if constexpr (kDrop > 0) u += 1ull << (kDrop - 1);  // round half up on the dropped bits
     const uint64_t ex = ((u >> 52) & 0x7FFull) - 1007ull;
     const uint64_t mant = (u & ((1ull << 52) - 1ull)) >> kDrop;
     return (ex << 59) | (mant << KP) | bits;
   }
 };
 
-// Per-index state is touched once per step: streamed with non-temporal hints so that it
-// does not evict the gathered descriptor table from L2.
+// Non-temporal hints on the entry streams and the per-index state (1) or plain loads
+// and stores (0, the default).  Plain accesses were measured faster on the 1e6 x 5e5
+// headline (192.4 us per step with both hinted, 182.0 with plain entry loads, 179.7 with
+// both plain): the step's whole working set (about 210 MB) fits the 256 MB Infinity
+// Cache, which the hinted streams bypass, so without the hints the entries of step t+1
+// are partly served from it instead of HBM.
 #ifndef MFE_NT_STATE
-#define MFE_NT_STATE 1
+#define MFE_NT_STATE 0
+#endif
+#ifndef MFE_NT_ENT
+#define MFE_NT_ENT 0
 #endif
 template <class T>
 __device__ __forceinline__ T ld_stream(const T* p) {
@@ -124,7 +134,9 @@ __device__ __forceinline__ void gather_rows(const long long* __restrict__ e,
     long long en[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      en[u] = (q0 + u < q_end) ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice) : 0ll;
+      en[u] = (q0 + u < q_end) ? (MFE_NT_ENT ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice)
+                                             : e[(int64_t)(q0 + u) * kSlice])
+                               : 0ll;
     DT d[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u)

@@ -9,16 +9,15 @@ same seeds and compare against these files.
                  columns per row, values N(0,1) e^(r_i + c_j), r, c ~ N(0, 2^2), generator
                  seed 1001), Algorithm 1 (Section 3.2) with k = 16 probes per step,
                  gamma = 0.1, M = 10, alpha = (n/m)^(1/4), beta = (m/n)^(1/4), probe seed
-                 2001: u_bar and v_bar after 100 and after 200 steps, at every STRIDE-th
-                 row and column (original order).  The running average after T steps
-                 does not depend on how many steps follow, so these are the first 200
-                 steps of the 2000-step run.
+                 2001: u_bar and v_bar after 500, 1000 and 2000 steps (the benchmarked
+                 run), at every STRIDE-th row and column (original order).  The running
+                 average after T steps does not depend on how many steps follow.
   c3_bf16.npz    dense 16384 x 8192, sigma = 3, generator seed 1003, rounded to bf16
                  (round-to-nearest-even, once, from FP64); the oracle runs on the rounded
                  values in FP64.  Algorithm 1 with k = 64, gamma = 0.1, M = 10, probe
                  seed 2003, 500 steps: u_bar, v_bar in full.
 
-Usage: python tests/golden/make_long_runs.py [c1] [c3]      (c1: ~3 min, c3: ~5 min)
+Usage: python tests/golden/make_long_runs.py [c1] [c3]      (c1: ~40 min, c3: ~3 min)
 """
 from __future__ import annotations
 
@@ -37,7 +36,7 @@ from workloads import round_to_bf16, scaled_dense, scaled_sparse  # noqa: E402
 
 STRIDE = 13
 C1 = dict(m=1_000_000, n=500_000, nnz_row=10, sigma=2.0, gen_seed=1001, k=16, gamma=0.1, M=10.0,
-          seed=2001, checkpoints=(100, 200))
+          seed=2001, checkpoints=(500, 1000, 2000))
 C3 = dict(m=16384, n=8192, sigma=3.0, gen_seed=1003, k=64, gamma=0.1, M=10.0, seed=2003, steps=500)
 
 

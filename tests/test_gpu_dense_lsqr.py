@@ -284,6 +284,24 @@ def test_sparse_lsqr_matches_oracle(scaled):
     assert info["normal_eq"] == pytest.approx(io["normal_eq"], rel=1e-3)
 
 
+def test_lsqr_graph_blocks_equal_eager_iterations():
+    """Blocks of check_every iterations run as a replayed HIP graph, a shorter last block and
+    check_every = 1 run eagerly; the launches and their order are the same, so x is the
+    same bit for bit (several replays, with the residual checks' eager work between them),
+    sparse and dense."""
+    from paper_1602_06621_amd import lsqr
+
+    c = scaled_sparse(900, 500, 7, 0.7, 31)
+    A = c.to_scipy()
+    b, _ = rhs_noisy(A, 32, noise=1e-3)
+    rng = np.random.default_rng(33)
+    d, e = np.exp(rng.normal(0, 0.3, 900)), np.exp(rng.normal(0, 0.3, 500))
+    for mat in (_csr(c), _dense(A.toarray())):
+        xs = [lsqr(mat, _t(b), _t(d), _t(e), tol=0.0, max_iter=23, check_every=ce)[0] for ce in (1, 5, 23)]
+        torch.cuda.synchronize()
+        assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+
+
 def test_sparse_lsqr_converges_and_stops():
     """Stopping rule: relative residual or normal-equation test, checked every 10 steps."""
     from paper_1602_06621_amd import lsqr
