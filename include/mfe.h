@@ -315,7 +315,7 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
  * batched layouts).  Runs trial_steps steps (1..100000, eagerly, results discarded) of
  * every launch configuration with the run parameters p (probes, targets, seed) and keeps
  * the fastest in the plan for its later runs (the default configuration is timed first and
- * kept unless another is more than 1% faster).  Configurations: 4, 8 or 16 entry loads in
+ * kept unless another is more than 1% faster).  Configurations: 1, 2, 4, 8 or 16 entry loads in
  * flight per lane (16 only for p->probes <= 16); both directions of a step in one launch
  * (modes 2, 2: the default) or one launch per direction (mode 0); and, for a
  * single-matrix plan whose gathered table exceeds 6 MB, each such direction also in mode
@@ -330,7 +330,7 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
                       int32_t trial_steps, int32_t* chosen, double* best_step_ms, int32_t* n_candidates);
 
 /* Sets a plan's launch configuration directly (the values mfe_plan_autotune chooses):
- * loads_in_flight 4, 8 or 16; rows_mode / cols_mode both 2 (one launch per step, the
+ * loads_in_flight 1, 2, 4, 8 or 16; rows_mode / cols_mode both 2 (one launch per step, the
  * default), or each 0 or 1 (1 only for a direction with a two-part layout, see
  * mfe_plan_autotune).
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
@@ -413,9 +413,10 @@ int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_bloc
  * untimed launch), written to the host pointer ms.  They allocate and free their own
  * device buffers.  EINVAL for sizes or reps out of range, NULL ms. */
 
-/* `gathers` random 8-byte reads (hashed indices, 8 in flight per lane) from a table of
- * table_bytes bytes (>= 8). */
-int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, void* stream);
+/* `gathers` random 8-byte reads (hashed indices) from a table of table_bytes bytes (>= 8),
+ * in_flight (1, 2, 4 or 8) independent reads per lane at a time. */
+int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, int32_t reps, double* ms,
+                     void* stream);
 
 /* One read of a buffer of `bytes` bytes (>= 16) with 16-byte non-temporal loads. */
 int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream);

@@ -100,7 +100,7 @@ def _lib():
         "mfe_warmstart_apply": [i64, vp, vp, dbl, vp, vp],
         "mfe_check_targets": [i64, i64, dbl, dbl, C.POINTER(dbl)],
         "mfe_equilibrate_noalloc": [C.POINTER(_Matrix), C.POINTER(_Params), vp, vp, vp, vp],
-        "mfe_probe_gather": [i64, i64, i32, C.POINTER(dbl), vp],
+        "mfe_probe_gather": [i64, i64, i32, i32, C.POINTER(dbl), vp],
         "mfe_probe_stream": [i64, i32, C.POINTER(dbl), vp],
         "mfe_plan_training_set": [vp, u64, i32, vp, vp, dbl, dbl, vp, vp, i64, u64, vp, vp, vp, C.POINTER(i64),
                                   vp],
@@ -129,10 +129,12 @@ def check_targets(m: int, n: int, alpha: float, beta: float):
     return rel.value, (msg if msg.startswith("warning:") else "")
 
 
-def probe_gather(table_bytes: int, gathers: int, reps: int = 5, stream=None) -> float:
-    """Milliseconds per launch of `gathers` random 8-byte reads from a table of table_bytes."""
+def probe_gather(table_bytes: int, gathers: int, in_flight: int = 1, reps: int = 5, stream=None) -> float:
+    """Milliseconds per launch of `gathers` random 8-byte reads from a table of table_bytes,
+    in_flight (1, 2, 4 or 8) independent gathers per lane at a time."""
     ms = C.c_double()
-    _check(_lib().mfe_probe_gather(int(table_bytes), int(gathers), int(reps), C.byref(ms), _stream(stream)))
+    _check(_lib().mfe_probe_gather(int(table_bytes), int(gathers), int(in_flight), int(reps), C.byref(ms),
+                                   _stream(stream)))
     return ms.value
 
 
@@ -448,9 +450,9 @@ class Plan:
         return dict(loads_in_flight=chosen[0], rows_mode=chosen[1], cols_mode=chosen[2], step_ms=best.value,
                     candidates=n.value)
 
-    def set_tuning(self, loads_in_flight=8, rows_mode=2, cols_mode=2):
+    def set_tuning(self, loads_in_flight=1, rows_mode=2, cols_mode=2):
         """Launch configuration of the step kernels (see mfe_plan_set_tuning); the defaults
-        are the library's (8 loads in flight, both directions in one launch)."""
+        are the library's (one load in flight, both directions in one launch)."""
         _check(_lib().mfe_plan_set_tuning(self._h, int(loads_in_flight), int(rows_mode), int(cols_mode)))
 
     def last_timing(self):

@@ -362,8 +362,9 @@ int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_bloc
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode) {
   clear_error();
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
-  if (loads_in_flight != 4 && loads_in_flight != 8 && loads_in_flight != 16)
-    return set_error(MFE_EINVAL, "loads_in_flight must be 4, 8 or 16");
+  if (loads_in_flight != 1 && loads_in_flight != 2 && loads_in_flight != 4 && loads_in_flight != 8 &&
+      loads_in_flight != 16)
+    return set_error(MFE_EINVAL, "loads_in_flight must be 1, 2, 4, 8 or 16");
   const bool both = rows_mode == 2 && cols_mode == 2;
   if (!both && (rows_mode < 0 || rows_mode > 1 || cols_mode < 0 || cols_mode > 1))
     return set_error(MFE_EINVAL, "direction modes must be 0 or 1 each, or 2 for both (one launch per step)");

@@ -7,7 +7,7 @@
 //     much of it the L2 of each XCD holds), and
 //   * the rate of a plain streaming read (the entry streams).
 // These kernels measure both in isolation: the gather probe reads hashed indices (no
-// index stream) with eight gathers in flight per lane; the stream probe reads a buffer
+// index stream) with 1, 2, 4 or 8 gathers in flight per lane; the stream probe reads a buffer
 // once with 16-byte non-temporal loads.  Both fold what they read into one word per
 // thread so nothing is optimised away.
 #include "common.h"
@@ -18,7 +18,6 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kProbeThreads = 256;
-constexpr int kGatherBatch = 8;
 
 // 64-bit finaliser of MurmurHash3 (Appleby): a bijective mix, used to spread indices.
 __device__ inline uint64_t mix64(uint64_t x) {
@@ -36,24 +35,35 @@ __global__ void k_fill_table(uint64_t* __restrict__ t, int64_t n) {
 }
 
 // Thread g performs gathers g, g + G, g + 2G, ... (G = grid size) below `total`, in
-// batches of kGatherBatch independent loads.
+// batches of B independent loads.
+template <int B>
 __global__ __launch_bounds__(kProbeThreads) void k_gather_probe(const uint64_t* __restrict__ table, int64_t n,
                                                                 int64_t total, uint64_t salt,
                                                                 uint64_t* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t G = (int64_t)gridDim.x * blockDim.x;
   uint64_t acc = 0;
-  for (int64_t q0 = g; q0 < total; q0 += G * kGatherBatch) {
-    uint64_t v[kGatherBatch];
+  for (int64_t q0 = g; q0 < total; q0 += G * B) {
+    uint64_t v[B];
 #pragma unroll
-    for (int u = 0; u < kGatherBatch; ++u) {
+    for (int u = 0; u < B; ++u) {
       const int64_t q = q0 + (int64_t)u * G;
       v[u] = q < total ? table[mix64((uint64_t)q ^ salt) % (uint64_t)n] : 0ull;
     }
 #pragma unroll
-    for (int u = 0; u < kGatherBatch; ++u) acc ^= v[u];
+    for (int u = 0; u < B; ++u) acc ^= v[u];
   }
   out[g] = acc;
+}
+
+void launch_gather_probe(int in_flight, int blocks, const uint64_t* table, int64_t n, int64_t total, uint64_t salt,
+                         uint64_t* out, hipStream_t st) {
+  switch (in_flight) {
+    case 1: k_gather_probe<1><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
+    case 2: k_gather_probe<2><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
+    case 4: k_gather_probe<4><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
+    default: k_gather_probe<8><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
+  }
 }
 
 __global__ __launch_bounds__(kProbeThreads) void k_stream_probe(const u32x4* __restrict__ buf, int64_t n16,
@@ -93,7 +103,7 @@ struct EventPair {
 
 }  // namespace
 
-int probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, hipStream_t st) {
+int probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, int32_t reps, double* ms, hipStream_t st) {
   const int64_t n = table_bytes / 8;
   const int blocks = 2048;
   DevBuf tab, out;
@@ -104,11 +114,10 @@ int probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms,
   MFE_HIP(hipEventCreate(&ev.a));
   MFE_HIP(hipEventCreate(&ev.b));
   // one untimed launch warms the table into the caches, as the step's tables are
-  k_gather_probe<<<blocks, kProbeThreads, 0, st>>>((const uint64_t*)tab.p, n, gathers, 0, (uint64_t*)out.p);
+  launch_gather_probe(in_flight, blocks, (const uint64_t*)tab.p, n, gathers, 0, (uint64_t*)out.p, st);
   MFE_HIP(hipEventRecord(ev.a, st));
   for (int r = 0; r < reps; ++r)
-    k_gather_probe<<<blocks, kProbeThreads, 0, st>>>((const uint64_t*)tab.p, n, gathers, (uint64_t)r + 1,
-                                                     (uint64_t*)out.p);
+    launch_gather_probe(in_flight, blocks, (const uint64_t*)tab.p, n, gathers, (uint64_t)r + 1, (uint64_t*)out.p, st);
   MFE_HIP(hipGetLastError());
   MFE_HIP(hipEventRecord(ev.b, st));
   MFE_HIP(hipEventSynchronize(ev.b));
@@ -145,11 +154,14 @@ int probe_stream(int64_t bytes, int32_t reps, double* ms, hipStream_t st) {
 
 extern "C" {
 
-int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t reps, double* ms, void* stream) {
+int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, int32_t reps, double* ms,
+                     void* stream) {
   mfe::clear_error();
   if (table_bytes < 8 || gathers < 1 || reps < 1 || !ms)
     return mfe::set_error(MFE_EINVAL, "need table_bytes >= 8, gathers >= 1, reps >= 1 and ms");
-  return mfe::probe_gather(table_bytes, gathers, reps, ms, (hipStream_t)stream);
+  if (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8)
+    return mfe::set_error(MFE_EINVAL, "in_flight must be 1, 2, 4 or 8");
+  return mfe::probe_gather(table_bytes, gathers, in_flight, reps, ms, (hipStream_t)stream);
 }
 
 int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream) {

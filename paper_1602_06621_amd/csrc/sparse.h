@@ -21,10 +21,14 @@ namespace mfe {
 constexpr int kSlice = 64;       // rows per slice = wavefront size
 constexpr int kWindow = 4096;    // rows sorted together by length
 constexpr int kBlock = 256;      // threads per workgroup of the step kernel
+// Slots whose loads a lane issues together (1, 2, 4, 8 or 16; the autotuner may choose
+// another per plan).  One slot at a time -- the entry load, then its gather -- was
+// measured fastest on the 1e6 x 5e5 headline: 147 us per step against 173 (2), 177 (4),
+// 179 (8) and 187 (16), at the same occupancy for 1 and 8.
 #ifndef MFE_BATCH
-#define MFE_BATCH 8
+#define MFE_BATCH 1
 #endif
-constexpr int kBatch = MFE_BATCH;  // slots whose loads a lane issues together
+constexpr int kBatch = MFE_BATCH;
 
 struct SideLayout {
   int64_t norig = 0;   // original indices (sum over matrices)

@@ -283,7 +283,7 @@ __device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev
   double acc[KP];
 #pragma unroll
   for (int p = 0; p < KP; ++p) acc[p] = 0.0;
-  gather_rows<KP, PACKED, 8>(e, gather, q0, q1, acc);
+  gather_rows<KP, PACKED, kBatch>(e, gather, q0, q1, acc);
   if (w > 0) {
 #pragma unroll
     for (int p = 0; p < KP; ++p)
@@ -344,8 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_phase_both(PhaseArgs a, SideDev C, i
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev C, int64_t col_blocks) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, 8, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, 8, true>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
+  if (b < a.side_blocks) side_update<KP, PACKED, kBatch, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, kBatch, true>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
   else signgen_block(a.gen, b - a.side_blocks - col_blocks);
 }
 
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev 
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, 8, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  if (b < a.side_blocks) side_update<KP, PACKED, kBatch, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
   else signgen_block(a.gen, b - a.side_blocks);
 }
 
@@ -645,6 +645,10 @@ struct PhaseLauncher {
       else k_phase_split<KP, PACKED, false><<<grid, block, 0, st>>>(b, P);
     } else if (a.side.tgt || a.side.zout) {
       k_phase_var<KP, PACKED><<<dim3((unsigned)(a.side_blocks + a.gen_blocks)), dim3(kBlock), 0, st>>>(a);
+    } else if (nb <= 1) {
+      launch_phase<KP, PACKED, 1>(a, st);
+    } else if (nb <= 2) {
+      launch_phase<KP, PACKED, 2>(a, st);
     } else if (nb <= 4) {
       launch_phase<KP, PACKED, 4>(a, st);
     } else if constexpr (KP <= 16) {
@@ -662,6 +666,10 @@ struct BothLauncher {
     const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block(kBlock);
     if (a.side.tgt || a.side.zout || C.tgt || C.zout) {
       k_phase_both_var<KP, PACKED><<<grid, block, 0, st>>>(a, C, col_blocks);
+    } else if (nb <= 1) {
+      k_phase_both<KP, PACKED, 1><<<grid, block, 0, st>>>(a, C, col_blocks);
+    } else if (nb <= 2) {
+      k_phase_both<KP, PACKED, 2><<<grid, block, 0, st>>>(a, C, col_blocks);
     } else if (nb <= 4) {
       k_phase_both<KP, PACKED, 4><<<grid, block, 0, st>>>(a, C, col_blocks);
     } else if constexpr (KP <= 16) {
@@ -995,7 +1003,10 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   // The default configuration is timed first and kept unless another is more than 1%
   // faster, so the choice does not flip on timing noise.
   std::vector<Cand> cands;
-  for (int nb : {8, 4, 16}) {
+  std::vector<int> nbs{kBatch};
+  for (int nb : {1, 2, 4, 8, 16})
+    if (nb != kBatch) nbs.push_back(nb);
+  for (int nb : nbs) {
     if (nb == 16 && k > 16) continue;
     cands.push_back({nb, 2, 2});  // both directions in one launch
     for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
