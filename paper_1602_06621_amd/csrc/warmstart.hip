@@ -262,6 +262,99 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ param
   y[b] = out;
 }
 
+// Inference on the matrix cores (v_mfma_f32_32x32x2_f32, FP32 products and sums): a
+// wavefront evaluates 32 samples at a time as H1' = tanh(W1' X' + b1) (64 x 32, eight
+// MFMAs) and H2' = tanh(W2' H1' + b2) (64 x 32, 64 MFMAs), then y = w3' H2' + b3 across the
+// lanes.  Accumulator layout of a 32 x 32 block: lane l, register v holds row
+// 8 (v/4) + 4 (l/32) + v%4, column l%32.  The second product takes the first one's
+// accumulators as its B operand as they are -- step (t, v) pairs hidden unit
+// 32 t + 8 (v/4) + v%4 (lanes 0-31) with the one 4 above it (lanes 32-63) -- and each lane
+// holds the matching entries of W2 (64 per lane, loaded once per wavefront), so no data
+// moves between the layers.  The order of the 64-term sums differs from the per-sample
+// kernel's; both are FP32.  tanh is evaluated as 1 - 2 / (e^(2x) + 1) with the hardware
+// exponential and reciprocal (absolute error about 1e-7; the outputs feed a warm start).
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+__device__ inline float tanh_fast(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // e^(2x) = 2^(2x log2 e)
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ params, const float* __restrict__ X,
+                                                   int64_t count, float* __restrict__ y) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const float* W1 = params;            // [F][H]
+  const float* b1 = W1 + kF * kH;
+  const float* W2 = b1 + kH;           // [in][out]
+  const float* b2 = W2 + kH * kH;
+  const float* w3 = b2 + kH;
+  const float b3 = w3[kH];
+  const int col = lane & 31, half = lane >> 5;
+  // biases and w3 in LDS, read at the lane's accumulator rows; per-lane operands in
+  // registers: W1 as the A operand of step s, tile t, and W2 at step (t, v), output tile o
+  __shared__ float vb1[kH], vb2[kH], vw3[kH];
+  for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+    vb1[i] = b1[i];
+    vb2[i] = b2[i];
+    vw3[i] = w3[i];
+  }
+  __syncthreads();
+  float a1[2][4], a2[2][2][16];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a1[t][s] = W1[(2 * s + half) * kH + 32 * t + col];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int in = 32 * t + acc_row(v, lane);  // the hidden unit this lane brings to step (t, v)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) a2[o][t][v] = W2[in * kH + 32 * o + col];
+    }
+  const int64_t nblk = (count + 31) / 32;
+  for (int64_t blk = wave; blk < nblk; blk += nwaves) {  // the same trip count for all lanes of a wave
+    const int64_t smp = blk * 32 + col;
+    const bool live = smp < count;
+    float xb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) xb[s] = live ? X[smp * kF + 2 * s + half] : 0.f;
+    f32x16v h1[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) h1[t][v] = vb1[32 * t + acc_row(v, lane)];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) h1[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[t][s], xb[s], h1[t], 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) h1[t][v] = tanh_fast(h1[t][v]);
+    }
+    f32x16v h2[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) h2[o][v] = vb2[32 * o + acc_row(v, lane)];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) h2[o] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[o][t][v], h1[t][v], h2[o], 0, 0, 0);
+    float part = 0.f;
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) part = fmaf(tanh_fast(h2[o][v]), vw3[32 * o + acc_row(v, lane)], part);
+    // lanes l and l + 32 hold the two halves of sample l's hidden units
+    const float other = __shfl_xor(part, 32);
+    if (half == 0 && live) y[smp] = (part + other) + b3;
+  }
+}
+
 // Per-sample backward: gy = 2 (y - t)/B, gh2 = gy w3 (1 - h2^2), gh1 = (gh2 W2') (1 - h1^2).
 // Also the per-sample squared error for the loss.
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float* __restrict__ params, const float* __restrict__ y,
@@ -401,6 +494,14 @@ __global__ void k_training_samples(const int64_t* __restrict__ soff, const int64
 }
 
 }  // namespace
+
+// Inference grid: enough wavefronts to fill the device (blocks of 32 samples are shared
+// out grid-stride, so the per-wavefront weight loads are amortised).
+void launch_mlp_infer(const float* params, const float* X, int64_t count, float* y, hipStream_t st) {
+  if (count <= 0) return;
+  const int64_t waves = std::min<int64_t>((count + 31) / 32, 2048);
+  k_mlp_infer<<<(unsigned)ceil_div(waves, 4), 256, 0, st>>>(params, X, count, y);
+}
 
 // ---------------------------------------------------------------- drivers
 
@@ -596,8 +697,8 @@ int plan_warmstart(mfe_plan* p, const float* params, uint64_t seed, int32_t ks, 
   float* dv = cv.take<float>(p->N);
   MFE_CHECK(sketch_impl(p, seed, ks, alpha_b, beta_b, gamma, M, fr, fc, us, vs, st, ws + head_bytes, &bytes));
   if (learned) {
-    k_mlp_fwd<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(params, fr, nullptr, p->M, du, nullptr, nullptr);
-    k_mlp_fwd<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(params, fc, nullptr, p->N, dv, nullptr, nullptr);
+    launch_mlp_infer(params, fr, p->M, du, st);
+    launch_mlp_infer(params, fc, p->N, dv, st);
   }
   k_apply_delta<<<(unsigned)ceil_div(p->M, 256), 256, 0, st>>>(p->M, us, learned ? du : nullptr, M, u0);
   k_apply_delta<<<(unsigned)ceil_div(p->N, 256), 256, 0, st>>>(p->N, vs, learned ? dv : nullptr, M, v0);
@@ -669,7 +770,7 @@ int plan_training_set(mfe_plan* p, uint64_t seed, int32_t ks, const double* alph
 
 int mlp_forward(const float* params, const float* X, int64_t count, float* y, hipStream_t st) {
   if (count <= 0) return MFE_OK;
-  k_mlp_fwd<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(params, X, nullptr, count, y, nullptr, nullptr);
+  launch_mlp_infer(params, X, count, y, st);
   MFE_HIP(hipGetLastError());
   MFE_HIP(hipStreamSynchronize(st));
   return MFE_OK;
