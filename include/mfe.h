@@ -319,11 +319,13 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
  * flight per lane (16 only for p->probes <= 16); both directions of a step in one launch
  * (modes 2, 2: the default) or one launch per direction (mode 0); and, for a
  * single-matrix plan whose gathered table exceeds 6 MB, each such direction also in mode
- * 1 (two launches over the halves of the table, FP64 partial sums in between).  Every
+ * 1 (two launches over the halves of the table, FP64 partial sums in between); and the
+ * one-launch form also with the other stream-hint setting (see mfe_plan_set_tuning).  Every
  * configuration adds the same terms in the same order, so tuning never changes a result
  * bit.  (Plans whose directions have few slices, and plans with Section 6 settings, run
  * their own launch forms whatever the modes.)
- * chosen (host int32[3], nullable): loads in flight, mode of the rows, mode of the columns;
+ * chosen (host int32[4], nullable): loads in flight, mode of the rows, mode of the columns,
+ * stream hints (0 or 1);
  * best_step_ms, n_candidates: nullable.  Allocates two temporary device arrays.
  * EINVAL: plan NULL, invalid p (as mfe_plan_equilibrate), trial_steps out of range. */
 int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
@@ -332,10 +334,15 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
 /* Sets a plan's launch configuration directly (the values mfe_plan_autotune chooses):
  * loads_in_flight 1, 2, 4, 8 or 16; rows_mode / cols_mode both 2 (one launch per step, the
  * default), or each 0 or 1 (1 only for a direction with a two-part layout, see
- * mfe_plan_autotune).
+ * mfe_plan_autotune); stream_hints 1: the entry and per-index state streams use
+ * non-temporal loads and stores, 0: plain ones, -1 (the default): non-temporal when the
+ * streams of one step exceed 512 MiB (twice the last-level cache; 8 bytes per stored entry
+ * and direction plus ~64 bytes per row and column).  Descriptor gathers always use plain
+ * loads.  None of these changes a result bit.
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
  * direction without the layout. */
-int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode);
+int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode,
+                        int32_t stream_hints);
 
 /* ---- Chambolle-Cremers-Pock on the Lasso (Section 5.2), sparse plans ---------------- */
 

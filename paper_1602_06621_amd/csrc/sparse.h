@@ -29,6 +29,12 @@ constexpr int kBlock = 256;      // threads per workgroup of the step kernel
 #define MFE_BATCH 1
 #endif
 constexpr int kBatch = MFE_BATCH;
+// Streams (entries of both directions, per-index state) larger than this -- twice the
+// 256 MB last-level cache -- use non-temporal loads and stores by default: caching them
+// gains nothing and evicts the gathered descriptor tables.  Smaller plans keep plain
+// accesses, whose lines the last-level cache holds from one step to the next (measured
+// on the 1e6 x 5e5 headline, ~256 MB of streams: 147 us per step plain, slower hinted).
+constexpr int64_t kStreamHintBytes = 512ll << 20;
 
 struct SideLayout {
   int64_t norig = 0;   // original indices (sum over matrices)
@@ -100,6 +106,10 @@ struct SideDev {
   // buffer receiving each index's estimate z instead of the update.
   const double* tgt;
   double* zout;
+  // 1: the entry and state streams use non-temporal loads and stores (for working sets
+  // well beyond the 256 MB last-level cache, where keeping them would evict the gathered
+  // descriptor tables); 0: plain loads and stores
+  int nt;
 };
 
 // One side of a block-equilibrated plan (Section 6): indices [ptr[b], ptr[b+1]) of the
@@ -157,9 +167,12 @@ struct mfe_plan {
   // same bit for bit under every configuration): loads in flight per lane, and how the
   // directions (rows, columns) are launched: {2, 2} both directions of a step in one
   // launch (the default); otherwise one launch per direction (0), or two launches over
-  // the halves of its table for a direction with a two-part layout (1).
+  // the halves of its table for a direction with a two-part layout (1); and whether the
+  // entry and state streams bypass the caches (1), stay in them (0), or (-1) follow the
+  // plan's size (stream_hints).
   int32_t tune_batch = mfe::kBatch;
   int32_t tune_split[2] = {2, 2};
+  int32_t tune_nt = -1;
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -179,7 +192,7 @@ struct mfe_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  double graph_key[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double graph_key[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // ---- Section 6 variants
   // Symmetric plan (Algorithm 2): one square symmetric matrix; the row entries are also
   // stored with indices into the rows' own internal order, and a step is one launch.

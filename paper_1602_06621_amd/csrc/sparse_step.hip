@@ -83,48 +83,42 @@ struct Codec<KP, true> {
   }
 };
 
-// Non-temporal hints on the entry streams and the per-index state (1) or plain loads
-// and stores (0, the default).  Plain accesses were measured faster on the 1e6 x 5e5
-// headline (192.4 us per step with both hinted, 182.0 with plain entry loads, 179.7 with
-// both plain): the step's whole working set (about 210 MB) fits the 256 MB Infinity
-// Cache, which the hinted streams bypass, so without the hints the entries of step t+1
-// are partly served from it instead of HBM.
-#ifndef MFE_NT_STATE
-#define MFE_NT_STATE 0
-#endif
-#ifndef MFE_NT_ENT
-#define MFE_NT_ENT 0
-#endif
-template <class T>
+// Entry streams and per-index state are read and written with non-temporal hints (nt,
+// uniform over a launch, chosen per plan by stream_hints) or with plain accesses.  Plain
+// accesses are faster when the step's streams fit the 256 MB Infinity Cache, which the
+// hinted streams bypass (1e6 x 5e5 headline, ~250 MB: 192.4 us per step with both hinted,
+// 182.0 with plain entry loads, 179.7 with both plain, at 8 slots in flight), so that the
+// entries of step t+1 are partly served from it; a plan whose streams do not fit (512
+// matrices, 4.4 GB per step: 2.25 ms hinted against 2.33 ms plain) keeps them out of the
+// way of the gathered tables.
+// NT is a template parameter, and each kernel branches once on the plan's flag: a run-time
+// choice between a hinted and a plain load of the same address is merged by the compiler
+// into one plain load.
+template <bool NT, class T>
 __device__ __forceinline__ T ld_stream(const T* p) {
-#if MFE_NT_STATE
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
-template <class T>
+template <bool NT, class T>
 __device__ __forceinline__ void st_stream(T* p, T v) {
-#if MFE_NT_STATE
-  __builtin_nontemporal_store(v, p);
-#else
-  *p = v;
-#endif
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+template <bool NT>
 __device__ __forceinline__ void st_stream(Desc* p, Desc v) {
   u64x2 w;
   w.x = (unsigned long long)__double_as_longlong(v.scale);
   w.y = v.bits;
-  st_stream(reinterpret_cast<u64x2*>(p), w);
+  st_stream<NT>(reinterpret_cast<u64x2*>(p), w);
 }
 
 // Sums of the signed products of slots [q_beg, q_end) of one row into acc.  Batches of
 // NB slots: all entry loads of a batch are issued, then all descriptor gathers, then the
 // accumulation, so a wavefront keeps 2 x NB independent memory requests in flight
 // instead of one dependent load/gather pair per slot.
-template <int KP, bool PACKED, int NB>
+template <int KP, bool PACKED, int NB, bool NT>
 __device__ __forceinline__ void gather_rows(const long long* __restrict__ e,
                                             const typename Codec<KP, PACKED>::T* __restrict__ gather, int q_beg,
                                             int q_end, double (&acc)[KP]) {
@@ -134,9 +128,7 @@ __device__ __forceinline__ void gather_rows(const long long* __restrict__ e,
     long long en[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      en[u] = (q0 + u < q_end) ? (MFE_NT_ENT ? __builtin_nontemporal_load(e + (int64_t)(q0 + u) * kSlice)
-                                             : e[(int64_t)(q0 + u) * kSlice])
-                               : 0ll;
+      en[u] = (q0 + u < q_end) ? ld_stream<NT>(e + (int64_t)(q0 + u) * kSlice) : 0ll;
     DT d[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u)
@@ -157,7 +149,7 @@ __device__ __forceinline__ void gather_rows(const long long* __restrict__ e,
 // Update of internal index r from its k probe sums (a5-a7 and the next descriptor).
 // VAR (the Section 6 variant kernel): per-index target, or the estimate z written out for
 // the block update instead of the update itself.
-template <int KP, bool PACKED, bool VAR>
+template <int KP, bool PACKED, bool VAR, bool NT>
 __device__ __forceinline__ void finish_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                               const StepScalars& sc, int64_t r, int32_t li, int32_t mi,
                                               double x_old, double xbar_old, double tgt_r, const double (&acc)[KP],
@@ -178,7 +170,7 @@ __device__ __forceinline__ void finish_update(const SideDev& S, const MatDev* __
   if constexpr (VAR) {
     if (S.zout) {  // block side: the estimate goes to the block update
       if (!isfinite(z)) atomicOr(flag, 1);
-      st_stream(S.zout + r, z);
+      st_stream<NT>(S.zout + r, z);
       return;
     }
     if (S.tgt) tgt = tgt_r;
@@ -191,17 +183,17 @@ __device__ __forceinline__ void finish_update(const SideDev& S, const MatDev* __
     atomicOr(flag, 1);
     xn = 0.0;  // keep the descriptor encodable; the run reports MFE_ENONFINITE
   }
-  st_stream(S.x + r, xn);
-  st_stream(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
+  st_stream<NT>(S.x + r, xn);
+  st_stream<NT>(S.xbar + r, 2.0 * xn / (sc.tau + 2.0) + sc.tau * xbar_old / (sc.tau + 2.0));
   const int64_t wbase = S.is_row ? mt.sign_word_row : mt.sign_word_col;
-  st_stream(reinterpret_cast<DT*>(S.out) + r,
+  st_stream<NT>(reinterpret_cast<DT*>(S.out) + r,
             C::encode(exp(xn), extract_bits(S.next_signs + wbase, (int64_t)li * k, k)));
 }
 
 // One lane per row.  part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries
 // [0, len_lo) to the partial sums; 2 partial sums plus entries [len_lo, len), then the
 // update.
-template <int KP, bool PACKED, int NB, bool VAR = false>
+template <int KP, bool PACKED, int NB, bool VAR, bool NT>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
   using C = Codec<KP, PACKED>;
@@ -212,36 +204,36 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   const int lane = (int)(threadIdx.x & 63);
   const int mode = S.part_mode;  // uniform over the launch
   const bool partial_out = mode == 1;
-  const int len = ld_stream(S.len + r);
-  const int split = mode != 0 ? ld_stream(S.len_lo + r) : 0;
+  const int len = ld_stream<NT>(S.len + r);
+  const int split = mode != 0 ? ld_stream<NT>(S.len_lo + r) : 0;
   const int q_beg = mode == 2 ? split : 0;
   const int q_end = mode == 1 ? split : len;
   // The epilogue's operands are loaded before the gather loop so their latency overlaps it.
   int32_t li = 0, mi = 0;
   double x_old = 0.0, xbar_old = 0.0, tgt_r = 0.0;
   if (!partial_out) {
-    li = ld_stream(S.orig + r);
-    x_old = ld_stream(S.x + r);
-    if (!VAR || !S.zout) xbar_old = ld_stream(S.xbar + r);
+    li = ld_stream<NT>(S.orig + r);
+    x_old = ld_stream<NT>(S.x + r);
+    if (!VAR || !S.zout) xbar_old = ld_stream<NT>(S.xbar + r);
     mi = S.slice_mat[s];
     if constexpr (VAR) {
-      if (S.tgt) tgt_r = ld_stream(S.tgt + r);
+      if (S.tgt) tgt_r = ld_stream<NT>(S.tgt + r);
     }
   }
   const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
   const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
   double acc[KP];
 #pragma unroll
-  for (int p = 0; p < KP; ++p) acc[p] = (mode == 2 && p < k) ? ld_stream(S.part + (int64_t)p * S.nint + r) : 0.0;
-  gather_rows<KP, PACKED, NB>(e, gather, q_beg, q_end, acc);
+  for (int p = 0; p < KP; ++p) acc[p] = (mode == 2 && p < k) ? ld_stream<NT>(S.part + (int64_t)p * S.nint + r) : 0.0;
+  gather_rows<KP, PACKED, NB, NT>(e, gather, q_beg, q_end, acc);
   if (partial_out) {
 #pragma unroll
     for (int p = 0; p < KP; ++p)
-      if (p < k) st_stream(S.part + (int64_t)p * S.nint + r, acc[p]);
+      if (p < k) st_stream<NT>(S.part + (int64_t)p * S.nint + r, acc[p]);
     return;
   }
   if (li < 0) return;
-  finish_update<KP, PACKED, VAR>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
+  finish_update<KP, PACKED, VAR, NT>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
 }
 
 // Long rows in few slices: a workgroup of P wavefronts per slice, wavefront w walking
@@ -253,7 +245,7 @@ constexpr int split_max() {
   return 1 + 65536 / (KP * kSlice * 8) < 16 ? 1 + 65536 / (KP * kSlice * 8) : 16;
 }
 
-template <int KP, bool PACKED, bool VAR>
+template <int KP, bool PACKED, bool VAR, bool NT>
 __device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                                   const StepScalars& sc, int64_t s, int P, int* flag) {
   using C = Codec<KP, PACKED>;
@@ -262,16 +254,16 @@ __device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev
   __shared__ double part[(PM > 1 ? PM - 1 : 1) * KP * kSlice];
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t r = s * kSlice + lane;
-  const int len = ld_stream(S.len + r);
+  const int len = ld_stream<NT>(S.len + r);
   int32_t li = 0, mi = 0;
   double x_old = 0.0, xbar_old = 0.0, tgt_r = 0.0;
   if (w == 0) {
-    li = ld_stream(S.orig + r);
-    x_old = ld_stream(S.x + r);
-    if (!VAR || !S.zout) xbar_old = ld_stream(S.xbar + r);
+    li = ld_stream<NT>(S.orig + r);
+    x_old = ld_stream<NT>(S.x + r);
+    if (!VAR || !S.zout) xbar_old = ld_stream<NT>(S.xbar + r);
     mi = S.slice_mat[s];
     if constexpr (VAR) {
-      if (S.tgt) tgt_r = ld_stream(S.tgt + r);
+      if (S.tgt) tgt_r = ld_stream<NT>(S.tgt + r);
     }
   }
   const int64_t base = S.slice_off[s];
@@ -283,7 +275,7 @@ __device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev
   double acc[KP];
 #pragma unroll
   for (int p = 0; p < KP; ++p) acc[p] = 0.0;
-  gather_rows<KP, PACKED, kBatch>(e, gather, q0, q1, acc);
+  gather_rows<KP, PACKED, kBatch, NT>(e, gather, q0, q1, acc);
   if (w > 0) {
 #pragma unroll
     for (int p = 0; p < KP; ++p)
@@ -297,7 +289,7 @@ __device__ __forceinline__ void side_update_split(const SideDev& S, const MatDev
       if (p < k) acc[p] += part[((i - 1) * KP + p) * kSlice + lane];
   }
   if (li < 0) return;
-  finish_update<KP, PACKED, VAR>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
+  finish_update<KP, PACKED, VAR, NT>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
 }
 
 __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk, int64_t bsize = kBlock) {
@@ -324,37 +316,45 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk,
 template <int KP, bool PACKED, int NB>
 __global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, NB>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else signgen_block(a.gen, b - a.side_blocks);
+  if (b >= a.side_blocks) signgen_block(a.gen, b - a.side_blocks);
+  else if (a.side.nt) side_update<KP, PACKED, NB, false, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else side_update<KP, PACKED, NB, false, false>(a.side, a.mats, a.k, a.sc, b, a.flag);
 }
 
 // Both directions of one step in one launch (row workgroups, then column workgroups,
 // then the sign words): for plans too small to fill the device with one direction.  The
 // directions read the other's descriptors of step t-1 and write their own of step t, so
 // they are independent within a step.
+template <int KP, bool PACKED, int NB, bool VAR, bool NT>
+__device__ __forceinline__ void phase_both(const PhaseArgs& a, const SideDev& C, int64_t b) {
+  if (b < a.side_blocks) side_update<KP, PACKED, NB, VAR, NT>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else side_update<KP, PACKED, NB, VAR, NT>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
+}
+
 template <int KP, bool PACKED, int NB>
 __global__ __launch_bounds__(kBlock) void k_phase_both(PhaseArgs a, SideDev C, int64_t col_blocks) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, NB>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, NB>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
-  else signgen_block(a.gen, b - a.side_blocks - col_blocks);
+  if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks);
+  else if (a.side.nt) phase_both<KP, PACKED, NB, false, true>(a, C, b);
+  else phase_both<KP, PACKED, NB, false, false>(a, C, b);
 }
 
 // The same with the Section 6 variant update (per-index targets, block sides).
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev C, int64_t col_blocks) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, kBatch, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else if (b < a.side_blocks + col_blocks) side_update<KP, PACKED, kBatch, true>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
-  else signgen_block(a.gen, b - a.side_blocks - col_blocks);
+  if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks);
+  else if (a.side.nt) phase_both<KP, PACKED, kBatch, true, true>(a, C, b);
+  else phase_both<KP, PACKED, kBatch, true, false>(a, C, b);
 }
 
 // The same for the Section 6 variants (per-index targets, block sides, symmetric plans).
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_var(PhaseArgs a) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update<KP, PACKED, kBatch, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else signgen_block(a.gen, b - a.side_blocks);
+  if (b >= a.side_blocks) signgen_block(a.gen, b - a.side_blocks);
+  else if (a.side.nt) side_update<KP, PACKED, kBatch, true, true>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else side_update<KP, PACKED, kBatch, true, false>(a.side, a.mats, a.k, a.sc, b, a.flag);
 }
 
 __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_block(g, blockIdx.x); }
@@ -364,8 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_bloc
 template <int KP, bool PACKED, bool VAR>
 __global__ __launch_bounds__(kSlice * split_max<KP>()) void k_phase_split(PhaseArgs a, int P) {
   const int64_t b = blockIdx.x;
-  if (b < a.side_blocks) side_update_split<KP, PACKED, VAR>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
-  else signgen_block(a.gen, b - a.side_blocks, (int64_t)blockDim.x);
+  if (b >= a.side_blocks) signgen_block(a.gen, b - a.side_blocks, (int64_t)blockDim.x);
+  else if (a.side.nt) side_update_split<KP, PACKED, VAR, true>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
+  else side_update_split<KP, PACKED, VAR, false>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
 }
 
 // Lane groups of the block kernels: G lanes (a power of two, 1..64, chosen from the
@@ -576,6 +577,15 @@ SignGenDev make_gen(const mfe_plan* p, uint64_t seed, uint64_t step, uint64_t* o
   return g;
 }
 
+// Whether a run's entry and state streams use non-temporal accesses: the plan's tuning,
+// else by the size of the streams one step moves (8-byte entries of both directions, and
+// about 64 bytes of state, descriptors and layout per internal index).
+int stream_hints(const mfe_plan* p) {
+  if (p->tune_nt >= 0) return p->tune_nt;
+  const int64_t bytes = 8 * (p->rows.nent + p->cols.nent) + 64 * (p->rows.nint + p->cols.nint);
+  return bytes > kStreamHintBytes ? 1 : 0;
+}
+
 SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gather, void* out,
                   const uint64_t* next_signs, int is_row) {
   SideDev S;
@@ -596,6 +606,7 @@ SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gath
   S.part = nullptr;
   S.tgt = nullptr;
   S.zout = nullptr;
+  S.nt = 0;
   return S;
 }
 
@@ -826,6 +837,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   const int split_rows = p->rows.len_lo && !p->symmetric && p->tune_split[0] == 1 ? 1 : 0;  // 1: two launches
   const int split_cols = p->cols.len_lo && p->tune_split[1] == 1 ? 1 : 0;
   const int nb = p->tune_batch;
+  const int nt = stream_hints(p);
   for (int i = 0; i < 2; ++i) {
     const bool need = (i == 0 ? split_rows : split_cols) != 0;
     if (need && !p->part[i]) {
@@ -850,6 +862,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     }
     a.side.part_mode = mode;
     a.side.part = p->part[rows ? 0 : 1];
+    a.side.nt = nt;
     const int si = rows ? 0 : 1;
     if (blocked[si]) a.side.zout = p->blk[si].z;
     else a.side.tgt = p->tgt_int[si];
@@ -910,15 +923,15 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   };
 
   // The step loop runs either as 2T (or more) launches or as one cached HIP graph of
-  // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning)).
+  // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning, hints)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
-    const double key[12] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+    const double key[13] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
                             (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
                             (double)nb, (double)p->tune_split[0], (double)p->tune_split[1],
-                            (double)p->variant_epoch};
+                            (double)p->variant_epoch, (double)nt};
     bool hit = p->graph_exec != nullptr;
-    for (int i = 0; i < 12 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    for (int i = 0; i < 13 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     if (!hit) {
       if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -929,7 +942,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-      for (int i = 0; i < 12; ++i) p->graph_key[i] = key[i];
+      for (int i = 0; i < 13; ++i) p->graph_key[i] = key[i];
     }
     if (st == nullptr) {
       // graphs are replayed on the plan's own stream, ordered after the default stream
@@ -998,7 +1011,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   if (k < 1 || k > p->max_probes)
     return set_error(MFE_EINVAL, "probes = %d outside 1..%d (the plan's max_probes)", k, p->max_probes);
   struct Cand {
-    int nb, sr, sc;
+    int nb, sr, sc, nt;
   };
   // The default configuration is timed first and kept unless another is more than 1%
   // faster, so the choice does not flip on timing noise.
@@ -1006,11 +1019,18 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   std::vector<int> nbs{kBatch};
   for (int nb : {1, 2, 4, 8, 16})
     if (nb != kBatch) nbs.push_back(nb);
+  // Stream hints: the plan's size-based default for every form, and the other setting for
+  // the one-launch form.
+  const int32_t keep_nt = p->tune_nt;
+  p->tune_nt = -1;
+  const int nt0 = stream_hints(p);
+  p->tune_nt = keep_nt;
   for (int nb : nbs) {
     if (nb == 16 && k > 16) continue;
-    cands.push_back({nb, 2, 2});  // both directions in one launch
+    cands.push_back({nb, 2, 2, nt0});  // both directions in one launch
     for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
-      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc});
+      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc, nt0});
+    cands.push_back({nb, 2, 2, 1 - nt0});
   }
   double *d = nullptr, *e = nullptr;
   MFE_CHECK(ensure(&d, p->M));
@@ -1032,6 +1052,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
     p->tune_batch = cands[i].nb;
     p->tune_split[0] = cands[i].sr;
     p->tune_split[1] = cands[i].sc;
+    p->tune_nt = cands[i].nt;
     double t = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code objects
       const int rc = plan_run(p, &trial, alpha_b, beta_b, 0, d, e, nullptr, nullptr);
@@ -1039,6 +1060,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
         p->tune_batch = keep_batch;
         p->tune_split[0] = keep_sr;
         p->tune_split[1] = keep_sc;
+        p->tune_nt = keep_nt;
         return rc;
       }
       t = p->last_step_ms;
@@ -1051,10 +1073,12 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   p->tune_batch = cands[best_i].nb;
   p->tune_split[0] = cands[best_i].sr;
   p->tune_split[1] = cands[best_i].sc;
+  p->tune_nt = cands[best_i].nt;
   if (chosen) {
     chosen[0] = p->tune_batch;
     chosen[1] = p->tune_split[0];
     chosen[2] = p->tune_split[1];
+    chosen[3] = p->tune_nt;
   }
   if (best_step_ms) *best_step_ms = best;
   if (n_candidates) *n_candidates = (int32_t)cands.size();

@@ -533,7 +533,10 @@ def test_set_tuning_rejects_missing_layout():
             plan.set_tuning(8, 1, 0)
         with pytest.raises(MfeError):
             plan.set_tuning(5, 0, 0)
+        with pytest.raises(MfeError):
+            plan.set_tuning(1, 2, 2, 2)
         plan.set_tuning(16, 0, 0)
+        plan.set_tuning(1, 2, 2, 1)
 
 
 def test_autotune_keeps_results_bitwise():
@@ -552,9 +555,11 @@ def test_autotune_keeps_results_bitwise():
             choice = plan.autotune(None, None, 0.1, 10.0, k, 5, trial_steps=5)
             _say("autotune", choice)
             assert choice["loads_in_flight"] in (1, 2, 4, 8, 16)
-            # 1, 2, 4, 8, 16 loads x (one launch per step, one per direction, and for the
-            # single matrix its column direction's two-part form)
-            assert choice["candidates"] == (15 if len(group) == 1 else 10)
+            assert choice["stream_hints"] in (0, 1)
+            # 1, 2, 4, 8, 16 loads x (one launch per step with either stream-hint setting,
+            # one launch per direction, and for the single matrix its column direction's
+            # two-part form)
+            assert choice["candidates"] == (20 if len(group) == 1 else 15)
             b = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=True)
             b = {key: v.clone() for key, v in b.items()}
             c = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=False)
