@@ -53,6 +53,10 @@ struct SideLayout {
   // the table per launch.
   int64_t split_at = -1;          // -1: no two-part layout
   int32_t* len_lo = nullptr;      // [nint]
+  // Launch order of the slices: wavefront w of a step launch takes slice sched[w].  Each
+  // matrix's slices in order of decreasing width (stored entries per lane), so that the
+  // longest run first and the last wavefronts of a launch are short ones.
+  int32_t* sched = nullptr;       // [nslices]
 };
 
 // Gathered-table size (at 8 bytes per index) above which a plan builds the two-part
@@ -106,6 +110,7 @@ struct SideDev {
   // buffer receiving each index's estimate z instead of the update.
   const double* tgt;
   double* zout;
+  const int32_t* sched;       // slice taken by each wavefront (null: slice = wavefront)
   // 1: the entry and state streams use non-temporal loads and stores (for working sets
   // well beyond the 256 MB last-level cache, where keeping them would evict the gathered
   // descriptor tables); 0: plain loads and stores

@@ -198,9 +198,10 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
                                             const StepScalars& sc, int64_t blk, int* flag) {
   using C = Codec<KP, PACKED>;
   using DT = typename C::T;
-  const int64_t r = blk * kBlock + threadIdx.x;
-  if (r >= S.nint) return;  // nint is a multiple of 64: whole wavefronts leave together
-  const int64_t s = r >> 6;
+  const int64_t wv = blk * (kBlock / kSlice) + (threadIdx.x >> 6);  // wavefront of the launch
+  if (wv * kSlice >= S.nint) return;  // whole wavefronts leave together
+  const int64_t s = S.sched ? (int64_t)S.sched[wv] : wv;
+  const int64_t r = s * kSlice + (threadIdx.x & 63);
   const int lane = (int)(threadIdx.x & 63);
   const int mode = S.part_mode;  // uniform over the launch
   const bool partial_out = mode == 1;
@@ -364,9 +365,13 @@ __global__ __launch_bounds__(kBlock) void k_signgen(SignGenDev g) { signgen_bloc
 template <int KP, bool PACKED, bool VAR>
 __global__ __launch_bounds__(kSlice * split_max<KP>()) void k_phase_split(PhaseArgs a, int P) {
   const int64_t b = blockIdx.x;
-  if (b >= a.side_blocks) signgen_block(a.gen, b - a.side_blocks, (int64_t)blockDim.x);
-  else if (a.side.nt) side_update_split<KP, PACKED, VAR, true>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
-  else side_update_split<KP, PACKED, VAR, false>(a.side, a.mats, a.k, a.sc, b, P, a.flag);
+  if (b >= a.side_blocks) {
+    signgen_block(a.gen, b - a.side_blocks, (int64_t)blockDim.x);
+    return;
+  }
+  const int64_t s = a.side.sched ? (int64_t)a.side.sched[b] : b;
+  if (a.side.nt) side_update_split<KP, PACKED, VAR, true>(a.side, a.mats, a.k, a.sc, s, P, a.flag);
+  else side_update_split<KP, PACKED, VAR, false>(a.side, a.mats, a.k, a.sc, s, P, a.flag);
 }
 
 // Lane groups of the block kernels: G lanes (a power of two, 1..64, chosen from the
@@ -606,6 +611,7 @@ SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gath
   S.part = nullptr;
   S.tgt = nullptr;
   S.zout = nullptr;
+  S.sched = L.sched;
   S.nt = 0;
   return S;
 }
