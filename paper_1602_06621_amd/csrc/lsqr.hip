@@ -19,20 +19,24 @@ namespace {
 constexpr int kRed = 256;  // threads of the product / reduction kernels
 
 // Device scalars of one LSQR run.
+// The bidiagonalisation vectors are kept unnormalised: the row vector p = beta u and the
+// column vector q = alpha v, so that no pass over them is needed to divide by a norm; the
+// products take the normalisations in their coefficients:
+//   p_{i+1} = D A E q_i / alpha_i - (alpha_i / beta_i) p_i        (= beta_{i+1} u_{i+1})
+//   q_{i+1} = E A' D p_{i+1} / beta_{i+1} - (beta_{i+1} / alpha_i) q_i  (= alpha_{i+1} v_{i+1})
 struct LsqrScal {
   double alpha, beta;          // current alpha_i, beta_{i+1}
   double rhobar, phibar;       // rotation state
   double phi_rho, theta_rho;   // update coefficients of x and w
   double anorm2;               // Frobenius estimate of ||Abar||^2
   double normal_eq;            // ||Abar' r|| / (||Abar|| ||r||) estimate
-  double neg_alpha, neg_beta, inv_beta, inv_alpha;
+  double inv_beta, inv_alpha;  // 1 / beta, 1 / alpha (0 when the norm is 0)
+  double coef_p, coef_q;       // -alpha_i / beta_i and -beta_{i+1} / alpha_i above
   double bnorm2, res2;         // ||b||^2 and ||A x - b||^2 at the last check
   double neg_one;
   int breakdown;               // iteration at which alpha or beta became 0 (0: none)
   int iter;
 };
-
-constexpr int kScal = 1024;  // threads of the single-workgroup scalar steps
 
 // Sum of the NT doubles of a block of NT threads, fixed order (tree in LDS).
 template <int NT = kRed>
@@ -47,6 +51,51 @@ __device__ double block_sum(double v) {
   const double r = sh[0];
   __syncthreads();
   return r;
+}
+
+// beta_{i+1} = ||p_{i+1}|| (t = ||p_{i+1}||^2).  next_iter != 0 starts the next iteration
+// (the count is kept on the device, so that every iteration is the same launches).
+__device__ void beta_step(LsqrScal* sc, double t, int next_iter) {
+  if (next_iter) sc->iter += 1;
+  const double beta = sqrt(t);
+  sc->beta = beta;
+  sc->anorm2 += sc->alpha * sc->alpha + beta * beta;
+  sc->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+  sc->coef_q = -beta * sc->inv_alpha;
+  if (beta == 0.0 && sc->breakdown == 0) sc->breakdown = sc->iter;
+}
+
+// alpha_{i+1} = ||q_{i+1}|| (t = its square) and the plane rotation.  init != 0 is the
+// start of the method (alpha_1 v_1 = Abar' u_1, phibar = beta_1, rhobar = alpha_1).
+__device__ void alpha_step(LsqrScal* sc, double t, int init) {
+  const double an = sqrt(t);
+  sc->inv_alpha = an > 0.0 ? 1.0 / an : 0.0;
+  sc->coef_p = -an * sc->inv_beta;
+  if (init) {
+    sc->phibar = sc->beta;
+    sc->rhobar = an;
+    sc->alpha = an;
+    sc->anorm2 = 0.0;
+    if (an == 0.0 && sc->breakdown == 0) sc->breakdown = -1;
+    return;
+  }
+  if (sc->breakdown == 0 || sc->breakdown == sc->iter) {
+    const double beta = sc->beta;
+    const double rho = hypot(sc->rhobar, beta);
+    const double c = sc->rhobar / rho, sn = beta / rho;
+    const double theta = sn * an;
+    sc->rhobar = -c * an;
+    const double phi = c * sc->phibar;
+    sc->phibar = sn * sc->phibar;
+    sc->phi_rho = phi / rho;
+    sc->theta_rho = theta / rho;
+    sc->normal_eq = an * fabs(c) / sqrt(sc->anorm2);
+    if (an == 0.0) sc->breakdown = sc->iter;
+  } else {
+    sc->phi_rho = 0.0;  // after a breakdown x stays fixed
+    sc->theta_rho = 0.0;
+  }
+  sc->alpha = an;
 }
 
 // ---------------------------------------------------------------- sliced products
@@ -90,6 +139,12 @@ __device__ __forceinline__ double row_dot(const int2* __restrict__ e, int q0, in
   return acc;
 }
 
+// Slice taken by slice slot i of a launch (the layout's longest-first order when it has
+// one); slots past the last slice stay out of range.
+__device__ __forceinline__ int64_t launch_slice(const SideDev& S, int64_t i, int64_t nslices) {
+  return (S.sched && i < nslices) ? (int64_t)S.sched[i] : i;
+}
+
 // Row sums sum_q a_q g[idx_q] of slice s for lane `lane`, returned in the group's first
 // wavefront (wsub = 0; 0 elsewhere and for s >= nslices).  Every thread of the workgroup
 // must call it (it has a barrier when P > 1).
@@ -129,7 +184,7 @@ __global__ __launch_bounds__(kSlice * kMaxSplit) void k_sell_product(SideDev S, 
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int wsub = wave % sm.P;
   const int64_t nslices = S.nint / kSlice;
-  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const int64_t s = launch_slice(S, (int64_t)blockIdx.x * sm.G + wave / sm.P, nslices);
   const double acc = slice_row_sum(S, g, s, nslices, sm.P, wave, wsub, lane);
   double contrib = 0.0;
   if (wsub == 0 && s < nslices) {
@@ -312,98 +367,46 @@ void reduce_long(const double* v, int64_t n, double* scratch, double* out, hipSt
   k_reduce<<<1, kRed, 0, st>>>(scratch, nb, out);
 }
 
-// After the forward product: beta = ||p||, coefficients for the transposed product.
-// The partial sums of the forward pass are reduced here.  next_iter != 0 starts the next
-// iteration (the count is kept on the device, so that every iteration is the same
-// sequence of launches).
-__global__ __launch_bounds__(kScal) void k_scal_beta(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
-                                                     int next_iter = 0) {
-  if (next_iter && threadIdx.x == 0) sc->iter += 1;  // before any use below (same thread)
+// The scalar step after a product, over that product's n per-workgroup partial sums of
+// y^2 (one workgroup, fixed order): kind 1 the beta step (flag: count a new iteration),
+// kind 2 the alpha step and rotation (flag: the start of the method).  A separate launch:
+// folding it into the product's last workgroup needs a device-scope release per
+// workgroup, which writes back the L2 of every XCD and measured 362 us per iteration
+// against 150.
+constexpr int kScal = 1024;
+__global__ __launch_bounds__(kScal) void k_scal_step(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
+                                                     int kind, int flag) {
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += kScal) s += partial[i];
   const double t = block_sum<kScal>(s);
   if (threadIdx.x == 0) {
-    const double beta = sqrt(t);
-    sc->beta = beta;
-    sc->anorm2 += sc->alpha * sc->alpha + beta * beta;
-    sc->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
-    sc->neg_beta = -beta;
-    if (beta == 0.0 && sc->breakdown == 0) sc->breakdown = sc->iter;
+    if (kind == 1) beta_step(sc, t, flag);
+    else alpha_step(sc, t, flag);
   }
 }
 
-// After the transposed product: alpha_{i+1} = ||q|| and the plane rotation.  init != 0
-// is the start of the method (alpha_1 v_1 = Abar' u_1, phibar = beta_1, rhobar = alpha_1).
-__global__ __launch_bounds__(kScal) void k_scal_alpha(const double* __restrict__ partial, int64_t n, LsqrScal* sc,
-                                                      int init) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kScal) s += partial[i];
-  const double t = block_sum<kScal>(s);
-  if (threadIdx.x == 0) {
-    const double an = sqrt(t);
-    sc->inv_alpha = an > 0.0 ? 1.0 / an : 0.0;
-    if (init) {
-      sc->phibar = sc->beta;
-      sc->rhobar = an;
-      sc->alpha = an;
-      sc->neg_alpha = -an;
-      sc->anorm2 = 0.0;
-      if (an == 0.0 && sc->breakdown == 0) sc->breakdown = -1;
-      return;
-    }
-    if (sc->breakdown == 0 || sc->breakdown == sc->iter) {
-      const double beta = sc->beta;
-      const double rho = hypot(sc->rhobar, beta);
-      const double c = sc->rhobar / rho, sn = beta / rho;
-      const double theta = sn * an;
-      sc->rhobar = -c * an;
-      const double phi = c * sc->phibar;
-      sc->phibar = sn * sc->phibar;
-      sc->phi_rho = phi / rho;
-      sc->theta_rho = theta / rho;
-      sc->normal_eq = an * fabs(c) / sqrt(sc->anorm2);
-      if (an == 0.0) sc->breakdown = sc->iter;
-    } else {
-      sc->phi_rho = 0.0;  // after a breakdown x stays fixed
-      sc->theta_rho = 0.0;
-    }
-    sc->alpha = an;
-    sc->neg_alpha = -an;
-  }
-}
-
-// Elementwise: v = q / alpha; x += phi/rho w; w = v - theta/rho w; ev = escale v
-// (column direction), and u = p / beta (row direction).  init: w = v, x = 0.
-__global__ void k_lsqr_update(int64_t ncol, int64_t nrow, const LsqrScal* __restrict__ sc, int init,
-                              double* __restrict__ v, double* __restrict__ w, double* __restrict__ x,
-                              double* __restrict__ ev, const double* __restrict__ escale, double* __restrict__ u,
-                              const int32_t* __restrict__ col_valid) {
+// Elementwise over the columns, after the alpha step: v_{i+1} = q_{i+1} / alpha_{i+1},
+// x += phi/rho w; w = v_{i+1} - theta/rho w.  init: w = v_1, x = 0.
+__global__ void k_lsqr_update(int64_t ncol, const LsqrScal* __restrict__ sc, int init, const double* __restrict__ q,
+                              double* __restrict__ w, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool frozen = sc->breakdown != 0 && sc->breakdown != sc->iter && !init;
-  if (i < ncol) {
-    if (frozen) return;
-    const double vi = v[i] * sc->inv_alpha;
-    if (init) {
-      w[i] = vi;
-      x[i] = 0.0;
-    } else {
-      const double wi = w[i];
-      x[i] += sc->phi_rho * wi;
-      w[i] = vi - sc->theta_rho * wi;
-    }
-    v[i] = vi;
-    ev[i] = (col_valid && col_valid[i] < 0) ? 0.0 : (escale ? escale[i] : 1.0) * vi;
-  } else if (i < ncol + nrow) {
-    if (frozen) return;
-    const int64_t r = i - ncol;
-    u[r] *= sc->inv_beta;
+  if (i >= ncol || frozen) return;
+  const double vi = q[i] * sc->inv_alpha;
+  if (init) {
+    w[i] = vi;
+    x[i] = 0.0;
+  } else {
+    const double wi = w[i];
+    x[i] += sc->phi_rho * wi;
+    w[i] = vi - sc->theta_rho * wi;
   }
 }
 
 __global__ void k_scal_init(LsqrScal* sc) {
   LsqrScal z;
   z.alpha = z.beta = z.rhobar = z.phibar = z.phi_rho = z.theta_rho = 0.0;
-  z.anorm2 = z.normal_eq = z.neg_alpha = z.neg_beta = 0.0;
+  z.anorm2 = z.normal_eq = z.coef_p = z.coef_q = 0.0;
   z.inv_beta = z.inv_alpha = 1.0;
   z.bnorm2 = z.res2 = 0.0;
   z.neg_one = -1.0;
@@ -465,6 +468,7 @@ struct SellOps : Ops {
     R.orig = p->rows.orig;
     R.ent = p->rows.ent;
     R.nint = p->rows.nint;
+    R.sched = p->rows.sched;
     R.is_row = 1;
     C.slice_off = p->cols.slice_off;
     C.slice_mat = p->cols.slice_mat;
@@ -472,6 +476,7 @@ struct SellOps : Ops {
     C.orig = p->cols.orig;
     C.ent = p->cols.ent;
     C.nint = p->cols.nint;
+    C.sched = p->cols.sched;
     C.is_row = 0;
     MR = slice_map(p->rows.nslices);
     MC = slice_map(p->cols.nslices);
@@ -582,21 +587,20 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
   ops.to_op(true, d, 1.0, 0, dd, st);
   ops.to_op(false, e, 1.0, 0, ee, st);
   k_scal_init<<<1, 1, 0, st>>>(sc);
-  const unsigned upd_grid = (unsigned)ceil_div(nc + nr, 256);
+  const unsigned upd_grid = (unsigned)ceil_div(nc, 256);
   const unsigned row_grid = (unsigned)ceil_div(nr, 256);
   // ||b||^2 for the relative residual of the original system
   k_mul<<<row_grid, 256, 0, st>>>(nr, bb, bb, res);
   reduce_long(res, nr, part, &sc->bnorm2, st);
-  // start: beta_1 u_1 = D b, alpha_1 v_1 = Abar' u_1
-  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);   // u = D b (normalised by k_lsqr_update)
-  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);   // du = D u, gathered by the transposed product
+  // start: p_1 = D b (= beta_1 u_1), q_1 = E A' D p_1 / beta_1 (= alpha_1 v_1)
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);   // p_1
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);   // D p_1, gathered by the transposed product
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
   reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
-  k_scal_beta<<<1, kScal, 0, st>>>(part, 1, sc);
-  // v = E A' D u / beta_1 (previous v is zero)
-  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);
-  k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
-  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
+  k_scal_step<<<1, kScal, 0, st>>>(part, 1, sc, 1, 0);
+  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, ev, part, st);
+  k_scal_step<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 2, 1);
+  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, sc, 1, v, w, x);
   MFE_HIP(hipGetLastError());
 
   LsqrScal h;
@@ -615,13 +619,15 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
   }
   // One iteration: five launches with no host involvement.
   auto iteration = [&](hipStream_t s) {
-    // p = D A E v - alpha u  (u normalised), du = D p, partial ||p||^2
-    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, s);
-    k_scal_beta<<<1, kScal, 0, s>>>(part, ops.fwd_blocks(), sc, 1);  // also counts the iteration
-    // q = E A' D p / beta - beta v, partial ||q||^2
-    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, s);
-    k_scal_alpha<<<1, kScal, 0, s>>>(part, ops.bwd_blocks(), sc, 0);
-    k_lsqr_update<<<upd_grid, 256, 0, s>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+    // p_{i+1} = D A (E q_i) / alpha_i - (alpha_i / beta_i) p_i, du = D p_{i+1}; then beta
+    // (and the iteration count)
+    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, s);
+    k_scal_step<<<1, kScal, 0, s>>>(part, ops.fwd_blocks(), sc, 1, 1);
+    // q_{i+1} = E A' du / beta_{i+1} - (beta_{i+1} / alpha_i) q_i, ev = E q_{i+1}; then
+    // alpha and the rotation; then x and w
+    ops.bwd(ee, du, &sc->inv_beta, &sc->coef_q, v, v, ev, part, s);
+    k_scal_step<<<1, kScal, 0, s>>>(part, ops.bwd_blocks(), sc, 2, 0);
+    k_lsqr_update<<<upd_grid, 256, 0, s>>>(nc, sc, 0, v, w, x);
   };
   // The check_every iterations between two residual checks are captured once in a HIP
   // graph and replayed (the launches are identical from one block to the next); a
@@ -845,7 +851,7 @@ __global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_dual(SideDev S, Slic
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int wsub = wave % sm.P;
   const int64_t nslices = S.nint / kSlice;
-  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const int64_t s = launch_slice(S, (int64_t)blockIdx.x * sm.G + wave / sm.P, nslices);
   const double acc = slice_row_sum(S, gx, s, nslices, sm.P, wave, wsub, lane);
   if (wsub != 0 || s >= nslices) return;
   const int64_t r = s * kSlice + lane;
@@ -866,7 +872,7 @@ __global__ __launch_bounds__(kSlice * kMaxSplit) void k_ccp_primal(SideDev S, Sl
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int wsub = wave % sm.P;
   const int64_t nslices = S.nint / kSlice;
-  const int64_t s = (int64_t)blockIdx.x * sm.G + wave / sm.P;
+  const int64_t s = launch_slice(S, (int64_t)blockIdx.x * sm.G + wave / sm.P, nslices);
   const double acc = slice_row_sum(S, gy, s, nslices, sm.P, wave, wsub, lane);
   if (wsub != 0 || s >= nslices) return;
   const int64_t c = s * kSlice + lane;
@@ -942,42 +948,41 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   const int64_t nr = ops.rows(), nc = ops.cols();
   const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks()) + ceil_div(nr, kRed) + 1;
   Work W;
-  double *bb, *u, *du, *v, *w, *x, *ev, *res, *part, *hist;
+  double *bb, *u, *du, *v, *ev, *res, *part, *hist;
   LsqrScal* sc;
   MFE_CHECK(W.alloc(&bb, nr));
   MFE_CHECK(W.alloc(&u, nr));
   MFE_CHECK(W.alloc(&du, nr));
   MFE_CHECK(W.alloc(&res, nr));
   MFE_CHECK(W.alloc(&v, nc));
-  MFE_CHECK(W.alloc(&w, nc));
-  MFE_CHECK(W.alloc(&x, nc));
   MFE_CHECK(W.alloc(&ev, nc));
   MFE_CHECK(W.alloc(&part, pb));
   MFE_CHECK(W.alloc(&hist, 2 * ((int64_t)max_iter + 1)));
   MFE_CHECK(W.alloc(&sc, 1));
-  for (double* z : {v, w, x, ev}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nc, st));
-  const unsigned row_grid = (unsigned)ceil_div(nr, 256), upd_grid = (unsigned)ceil_div(nc + nr, 256);
+  for (double* z : {v, ev}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nc, st));
+  const unsigned row_grid = (unsigned)ceil_div(nr, 256);
   k_fill_valid<<<row_grid, 256, 0, st>>>(nr, ops.R.orig, 1.0, bb);
   k_scal_init<<<1, 1, 0, st>>>(sc);
-  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);  // beta_1 u_1 = D 1
+  k_mul<<<row_grid, 256, 0, st>>>(nr, dd, bb, u);  // p_1 = D 1 (= beta_1 u_1)
   k_mul<<<row_grid, 256, 0, st>>>(nr, dd, u, du);
   k_mul<<<row_grid, 256, 0, st>>>(nr, u, u, res);
   reduce_long(res, nr, part + ceil_div(nr, kRed), part, st);
-  k_scal_beta<<<1, kScal, 0, st>>>(part, 1, sc);
-  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, nullptr, part, st);  // alpha_1 v_1 = Abar' u_1
-  k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 1);
-  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 1, v, w, x, ev, ee, u, ops.col_valid());
+  k_scal_step<<<1, kScal, 0, st>>>(part, 1, sc, 1, 0);
+  // q_1 = E A' D p_1 / beta_1 (= alpha_1 v_1), then alpha_1
+  ops.bwd(ee, du, &sc->inv_beta, nullptr, nullptr, v, ev, part, st);
+  k_scal_step<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 2, 1);
   k_record<<<1, 1, 0, st>>>(sc, hist, 0);
   MFE_HIP(hipGetLastError());
   std::vector<double> h;
   double est = 0.0, prev = -1.0;
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    ops.fwd(dd, ev, nullptr, &sc->neg_alpha, u, u, du, part, st);  // beta u = Abar v - alpha u
-    k_scal_beta<<<1, kScal, 0, st>>>(part, ops.fwd_blocks(), sc, it);  // also sets the iteration
-    ops.bwd(ee, du, &sc->inv_beta, &sc->neg_beta, v, v, nullptr, part, st);  // alpha v = Abar' u - beta v
-    k_scal_alpha<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 0);
-    k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, nr, sc, 0, v, w, x, ev, ee, u, ops.col_valid());
+    // beta u = Abar v - alpha u, then beta (and the iteration count)
+    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, st);
+    k_scal_step<<<1, kScal, 0, st>>>(part, ops.fwd_blocks(), sc, 1, 1);
+    // alpha v = Abar' u - beta v, then alpha
+    ops.bwd(ee, du, &sc->inv_beta, &sc->coef_q, v, v, ev, part, st);
+    k_scal_step<<<1, kScal, 0, st>>>(part, ops.bwd_blocks(), sc, 2, 0);
     k_record<<<1, 1, 0, st>>>(sc, hist, it);
     MFE_HIP(hipGetLastError());
     if (it % 5 != 0 && it != max_iter) continue;
