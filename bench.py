@@ -47,7 +47,7 @@ GEN_SEED, PROBE_SEED = 1001, 2001
 # plain 512 MiB copy; TRAFFIC_SOURCE names the profile summary they were read from.  None
 # when the kernel has changed since the counters were taken.
 HEADLINE_KERNEL = "k_phase_both<16,true,1>"
-TRAFFIC_BYTES_PER_STEP = (597.1 + 36.3) * 1e6
+TRAFFIC_BYTES_PER_STEP = (516.8 + 36.3) * 1e6
 TRAFFIC_SOURCE = "profiles/k_phase_csr_1e6x5e5_k16.md (FETCH_SIZE x 1.861 + WRITE_SIZE x 0.931 per launch)"
 
 
@@ -97,20 +97,25 @@ def bf16_algorithmic(m, n, k):
 
 def measure_ceilings(mfe, m, n, nnz, stream_bytes=1 << 30):
     """The two rates the sparse step is bounded by, measured on this GPU in this run: a
-    plain streaming read (1 GiB, 16-byte non-temporal loads) and random 8-byte gathers
-    from tables of the headline's descriptor-table sizes (n x 8 B gathered by the row
+    plain streaming read (1 GiB, 16-byte non-temporal loads) and 8-byte gathers from
+    tables of the headline's descriptor-table sizes (n x 8 B gathered by the row
     direction, m x 8 B by the column direction), nnz gathers each, as each direction
-    makes per step."""
+    makes per step.  The gathers are measured two ways: uniformly random (1 or 8 in
+    flight per lane), and as the step makes them -- each lane reading the sorted indices
+    of one row (nnz / m per row for the row direction, nnz / n per column for the column
+    direction) one at a time; the sorted form sets the floor."""
     stream_ms = mfe.probe_stream(stream_bytes, reps=5)
     gm = {}
-    for fl in (1, 8):  # gathers in flight per lane; the faster sets the ceiling
+    for fl in (1, 8):  # gathers in flight per lane
         gm[fl] = (mfe.probe_gather(8 * n, nnz, fl, reps=5),   # the row direction's table
                   mfe.probe_gather(8 * m, nnz, fl, reps=5))   # the column direction's table
-    best = min(gm, key=lambda f: sum(gm[f]))
-    return {"stream_read_gbs": stream_bytes / (stream_ms / 1e3) / 1e9,
-            "gather_ms": {f"{fl} in flight": {f"{8 * n / 2**20:.1f} MiB": gm[fl][0], f"{8 * m / 2**20:.1f} MiB": gm[fl][1]}
-                          for fl in gm},
-            "gathers_each": nnz, "gather_floor_ms": sum(gm[best]), "gather_floor_in_flight": best}
+    lr, lc = max(1, round(nnz / m)), max(1, round(nnz / n))
+    gs = (mfe.probe_gather_sorted(8 * n, nnz, lr, reps=5), mfe.probe_gather_sorted(8 * m, nnz, lc, reps=5))
+    mib = (f"{8 * n / 2**20:.1f} MiB", f"{8 * m / 2**20:.1f} MiB")
+    out = {"gather_ms": {f"{fl} in flight": dict(zip(mib, gm[fl])) for fl in gm}}
+    out["gather_ms"][f"sorted rows of {lr} / {lc}"] = dict(zip(mib, gs))
+    return {"stream_read_gbs": stream_bytes / (stream_ms / 1e3) / 1e9, **out,
+            "gathers_each": nnz, "gather_floor_ms": sum(gs), "gather_floor": f"sorted rows of {lr} / {lc}"}
 
 
 def load_lib():
@@ -371,12 +376,22 @@ def bench_lsqr(mfe, plan, csr, out):
     bt = torch.tensor(b, device="cuda:0")
     res = {}
     ones = torch.ones(csr.m, dtype=torch.float64, device="cuda:0")
-    for name, d, e in (("d_e", out["d"], out["e"]), ("col_only", ones, out["e"]), ("plain", None, None)):
+    # the equilibrated run converges in tens of iterations: its stopping rule is checked
+    # every 5 iterations; the two slow arms every 25
+    for name, d, e, every in (("d_e", out["d"], out["e"], 5), ("col_only", ones, out["e"], 25),
+                              ("plain", None, None, 25)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = plan.lsqr(bt, d, e, tol=1e-6, max_iter=3000, check_every=25)
+        x, info = plan.lsqr(bt, d, e, tol=1e-6, max_iter=3000, check_every=every)
         torch.cuda.synchronize()
-        res[name] = dict(info, seconds=time.perf_counter() - t0)
+        res[name] = dict(info, seconds=time.perf_counter() - t0, check_every=every)
+    # time per iteration: 400 iterations (tolerance 0, one check at the end), call included
+    plan.lsqr(bt, out["d"], out["e"], tol=0.0, max_iter=400, check_every=400)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.lsqr(bt, out["d"], out["e"], tol=0.0, max_iter=400, check_every=400)
+    torch.cuda.synchronize()
+    res["us_per_iter_400"] = (time.perf_counter() - t0) / 400 * 1e6
     return {"workload": "LSQR on the headline matrix, b = A x* + 1e-3 N(0,1), tol 1e-6, max 3000 iterations",
             **res}
 

@@ -320,12 +320,13 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
  * (modes 2, 2: the default) or one launch per direction (mode 0); and, for a
  * single-matrix plan whose gathered table exceeds 6 MB, each such direction also in mode
  * 1 (two launches over the halves of the table, FP64 partial sums in between); and the
- * one-launch form also with the other stream-hint setting (see mfe_plan_set_tuning).  Every
+ * one-launch form also with the other stream-hint setting and with each fixed slice
+ * order (see mfe_plan_set_tuning).  Every
  * configuration adds the same terms in the same order, so tuning never changes a result
  * bit.  (Plans whose directions have few slices, and plans with Section 6 settings, run
  * their own launch forms whatever the modes.)
- * chosen (host int32[4], nullable): loads in flight, mode of the rows, mode of the columns,
- * stream hints (0 or 1);
+ * chosen (host int32[5], nullable): loads in flight, mode of the rows, mode of the columns,
+ * stream hints (0 or 1), slice order (-1, 0 or 1);
  * best_step_ms, n_candidates: nullable.  Allocates two temporary device arrays.
  * EINVAL: plan NULL, invalid p (as mfe_plan_equilibrate), trial_steps out of range. */
 int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
@@ -338,11 +339,15 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
  * non-temporal loads and stores, 0: plain ones, -1 (the default): non-temporal when the
  * streams of one step exceed 512 MiB (twice the last-level cache; 8 bytes per stored entry
  * and direction plus ~64 bytes per row and column).  Descriptor gathers always use plain
- * loads.  None of these changes a result bit.
+ * loads.  slice_order 1: the wavefronts of a step launch take each matrix's slices (64 rows
+ * or columns) in order of decreasing width, which keeps the end of a launch of several
+ * rounds of workgroups from running the device half empty; 0: in storage order; -1 (the
+ * default): 1 when the one-launch step has more workgroups than five per compute unit or
+ * a direction runs one slice per workgroup, else 0.  None of these changes a result bit.
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
  * direction without the layout. */
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode,
-                        int32_t stream_hints);
+                        int32_t stream_hints, int32_t slice_order);
 
 /* ---- Chambolle-Cremers-Pock on the Lasso (Section 5.2), sparse plans ---------------- */
 
@@ -424,6 +429,14 @@ int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_bloc
  * in_flight (1, 2, 4 or 8) independent reads per lane at a time. */
 int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, int32_t reps, double* ms,
                      void* stream);
+
+/* `gathers` 8-byte reads from a table of table_bytes bytes (8 .. 32 GiB - 8) in rows of
+ * per_row (5, 10, 20 or 40): each thread takes one row of per_row hashed indices, sorts
+ * them increasing and reads them one at a time, as a lane of the sparse step walks the
+ * sorted entries of one row (the lanes at the same slot then read the same part of the
+ * table). */
+int mfe_probe_gather_sorted(int64_t table_bytes, int64_t gathers, int32_t per_row, int32_t reps, double* ms,
+                            void* stream);
 
 /* One read of a buffer of `bytes` bytes (>= 16) with 16-byte non-temporal loads. */
 int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream);

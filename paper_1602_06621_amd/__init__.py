@@ -31,6 +31,7 @@ from ._ffi import (  # noqa: F401
     mlp_sizes,
     mlp_train,
     probe_gather,
+    probe_gather_sorted,
     probe_stream,
     residual,
     version,

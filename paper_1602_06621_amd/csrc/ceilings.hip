@@ -7,9 +7,12 @@
 //     much of it the L2 of each XCD holds), and
 //   * the rate of a plain streaming read (the entry streams).
 // These kernels measure both in isolation: the gather probe reads hashed indices (no
-// index stream) with 1, 2, 4 or 8 gathers in flight per lane; the stream probe reads a buffer
-// once with 16-byte non-temporal loads.  Both fold what they read into one word per
-// thread so nothing is optimised away.
+// index stream) with 1, 2, 4 or 8 gathers in flight per lane; the sorted gather probe
+// gives each thread the L indices of one row of a uniformly random sparse matrix, in
+// increasing order, gathered one at a time (the step's pattern: a lane walks one row's
+// sorted entries, so the lanes at the same slot gather from the same part of the table);
+// the stream probe reads a buffer once with 16-byte non-temporal loads.  All fold what
+// they read into one word per thread so nothing is optimised away.
 #include "common.h"
 
 namespace mfe {
@@ -63,6 +66,46 @@ void launch_gather_probe(int in_flight, int blocks, const uint64_t* table, int64
     case 2: k_gather_probe<2><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
     case 4: k_gather_probe<4><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
     default: k_gather_probe<8><<<blocks, kProbeThreads, 0, st>>>(table, n, total, salt, out); break;
+  }
+}
+
+// Thread g gathers the L hashed indices of "row" g (row g < rows), sorted increasing, one
+// at a time: each index depends on the value gathered before it (plus a term that is
+// almost surely zero, the sum clamped into the table) so the loads cannot overlap.
+template <int L>
+__global__ __launch_bounds__(kProbeThreads) void k_gather_sorted(const uint64_t* __restrict__ table, uint32_t n,
+                                                                 int64_t rows, uint64_t salt,
+                                                                 uint64_t* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= rows) return;
+  uint32_t idx[L];
+#pragma unroll
+  for (int q = 0; q < L; ++q) idx[q] = (uint32_t)(mix64(((uint64_t)g * L + q) ^ salt) % n);
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+#pragma unroll
+    for (int j = 0; j < L - 1 - i; ++j) {
+      const uint32_t a = idx[j], b = idx[j + 1];
+      idx[j] = a < b ? a : b;
+      idx[j + 1] = a < b ? b : a;
+    }
+  uint64_t acc = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const uint32_t j = min(idx[q] + (uint32_t)(acc == 0x5bd1e9955bd1e995ull), n - 1u);
+    acc += table[j] * (uint64_t)(q + 1);
+  }
+  out[g] = acc;
+}
+
+void launch_gather_sorted(int L, const uint64_t* table, uint32_t n, int64_t rows, uint64_t salt, uint64_t* out,
+                          hipStream_t st) {
+  const unsigned blocks = (unsigned)ceil_div(rows, kProbeThreads);
+  switch (L) {
+    case 5: k_gather_sorted<5><<<blocks, kProbeThreads, 0, st>>>(table, n, rows, salt, out); break;
+    case 10: k_gather_sorted<10><<<blocks, kProbeThreads, 0, st>>>(table, n, rows, salt, out); break;
+    case 20: k_gather_sorted<20><<<blocks, kProbeThreads, 0, st>>>(table, n, rows, salt, out); break;
+    default: k_gather_sorted<40><<<blocks, kProbeThreads, 0, st>>>(table, n, rows, salt, out); break;
   }
 }
 
@@ -127,6 +170,30 @@ int probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, int32_
   return MFE_OK;
 }
 
+int probe_gather_sorted(int64_t table_bytes, int64_t gathers, int32_t per_row, int32_t reps, double* ms,
+                        hipStream_t st) {
+  const int64_t n = table_bytes / 8;
+  const int64_t rows = ceil_div(gathers, per_row);
+  DevBuf tab, out;
+  MFE_HIP(hipMalloc(&tab.p, sizeof(uint64_t) * (size_t)n));
+  MFE_HIP(hipMalloc(&out.p, sizeof(uint64_t) * (size_t)rows));
+  k_fill_table<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((uint64_t*)tab.p, n);
+  EventPair ev;
+  MFE_HIP(hipEventCreate(&ev.a));
+  MFE_HIP(hipEventCreate(&ev.b));
+  launch_gather_sorted(per_row, (const uint64_t*)tab.p, (uint32_t)n, rows, 0, (uint64_t*)out.p, st);
+  MFE_HIP(hipEventRecord(ev.a, st));
+  for (int r = 0; r < reps; ++r)
+    launch_gather_sorted(per_row, (const uint64_t*)tab.p, (uint32_t)n, rows, (uint64_t)r + 1, (uint64_t*)out.p, st);
+  MFE_HIP(hipGetLastError());
+  MFE_HIP(hipEventRecord(ev.b, st));
+  MFE_HIP(hipEventSynchronize(ev.b));
+  float t = 0.f;
+  MFE_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+  *ms = (double)t / reps;
+  return MFE_OK;
+}
+
 int probe_stream(int64_t bytes, int32_t reps, double* ms, hipStream_t st) {
   const int64_t n16 = bytes / 16;
   const int blocks = 8192;
@@ -162,6 +229,16 @@ int mfe_probe_gather(int64_t table_bytes, int64_t gathers, int32_t in_flight, in
   if (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8)
     return mfe::set_error(MFE_EINVAL, "in_flight must be 1, 2, 4 or 8");
   return mfe::probe_gather(table_bytes, gathers, in_flight, reps, ms, (hipStream_t)stream);
+}
+
+int mfe_probe_gather_sorted(int64_t table_bytes, int64_t gathers, int32_t per_row, int32_t reps, double* ms,
+                            void* stream) {
+  mfe::clear_error();
+  if (table_bytes < 8 || table_bytes > (8ll << 32) - 8 || gathers < 1 || reps < 1 || !ms)
+    return mfe::set_error(MFE_EINVAL, "need 8 <= table_bytes < 32 GiB, gathers >= 1, reps >= 1 and ms");
+  if (per_row != 5 && per_row != 10 && per_row != 20 && per_row != 40)
+    return mfe::set_error(MFE_EINVAL, "per_row must be 5, 10, 20 or 40");
+  return mfe::probe_gather_sorted(table_bytes, gathers, per_row, reps, ms, (hipStream_t)stream);
 }
 
 int mfe_probe_stream(int64_t bytes, int32_t reps, double* ms, void* stream) {

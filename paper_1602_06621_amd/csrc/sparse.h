@@ -174,10 +174,12 @@ struct mfe_plan {
   // launch (the default); otherwise one launch per direction (0), or two launches over
   // the halves of its table for a direction with a two-part layout (1); and whether the
   // entry and state streams bypass the caches (1), stay in them (0), or (-1) follow the
-  // plan's size (stream_hints).
+  // plan's size (stream_hints); and whether wavefronts take the slices in the layout's
+  // longest-first order (1), in grid order (0), or (-1) as slice_schedule decides.
   int32_t tune_batch = mfe::kBatch;
   int32_t tune_split[2] = {2, 2};
   int32_t tune_nt = -1;
+  int32_t tune_sched = -1;
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -197,7 +199,7 @@ struct mfe_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  double graph_key[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double graph_key[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // ---- Section 6 variants
   // Symmetric plan (Algorithm 2): one square symmetric matrix; the row entries are also
   // stored with indices into the rows' own internal order, and a step is one launch.

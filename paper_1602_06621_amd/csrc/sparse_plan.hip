@@ -230,7 +230,8 @@ int bits_for(uint64_t v) {
 // width: the 500,000 columns of the 1e6 x 5e5 headline (Poisson widths around 20) filled
 // 1.5 rounds of the device's workgroup slots, and the half-full second round left the
 // device under 90% occupied for the last ~65 us of a step.  Keeping each matrix's slices
-// together keeps the gathers of consecutive workgroups within one matrix's table.
+// together keeps the gathers of consecutive workgroups within one matrix's table.  Step
+// launches use it as the plan's tuning says (slice_schedule).
 int build_slice_schedule(SideLayout& L, hipStream_t st) {
   std::vector<int64_t> off(L.nslices + 1);
   std::vector<int32_t> smat(L.nslices);

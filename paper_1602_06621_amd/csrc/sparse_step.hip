@@ -591,6 +591,23 @@ int stream_hints(const mfe_plan* p) {
   return bytes > kStreamHintBytes ? 1 : 0;
 }
 
+// Whether a run's step launches take the slices in the layout's longest-first order: the
+// plan's tuning, else when the order has a tail to shorten -- the one-launch step has more
+// workgroups than one round of the device's resident workgroups (about 5 per CU), or a
+// direction runs the split kernels (one slice per workgroup).  Measured, µs per step: 1e6
+// x 5e5 headline (5,861 workgroups) 130.8 with the order against 148.7 without; 5e4 x
+// 2.5e4 (split kernels) 31.5 against 33.1; 2e5 x 1e5 with U{8..16} entries per row (1,173
+// workgroups, one round) 42.1 against 40.2.
+int slice_schedule(const mfe_plan* p, int64_t row_blocks, int64_t col_blocks, bool split) {
+  if (p->tune_sched >= 0) return p->tune_sched;
+  if (split) return 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return row_blocks + col_blocks > 5ll * cus ? 1 : 0;
+}
+
 SideDev make_side(const SideLayout& L, double* x, double* xbar, const void* gather, void* out,
                   const uint64_t* next_signs, int is_row) {
   SideDev S;
@@ -844,6 +861,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   const int split_cols = p->cols.len_lo && p->tune_split[1] == 1 ? 1 : 0;
   const int nb = p->tune_batch;
   const int nt = stream_hints(p);
+  int sched = 1;  // slice order (slice_schedule), set below
   for (int i = 0; i < 2; ++i) {
     const bool need = (i == 0 ? split_rows : split_cols) != 0;
     if (need && !p->part[i]) {
@@ -869,6 +887,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     a.side.part_mode = mode;
     a.side.part = p->part[rows ? 0 : 1];
     a.side.nt = nt;
+    if (!sched) a.side.sched = nullptr;
     const int si = rows ? 0 : 1;
     if (blocked[si]) a.side.zout = p->blk[si].z;
     else a.side.tgt = p->tgt_int[si];
@@ -896,6 +915,11 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   // Both directions in one launch (tuning modes 2 / 2) where neither needs another form;
   // block sides then run their block launches after it.
   const bool fused = p->tune_split[0] == 2 && p->tune_split[1] == 2 && !p->symmetric;
+  {
+    // the launch shapes phase_args chooses: split kernels below 1024 slices
+    const bool split = p->rows.nslices < 1024 || (!p->symmetric && p->cols.nslices < 1024);
+    sched = slice_schedule(p, ceil_div(nr, kBlock), p->symmetric ? 0 : ceil_div(nc, kBlock), split);
+  }
   auto launch_step = [&](int t, hipStream_t s) {
     if (fused) {
       const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
@@ -929,15 +953,16 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   };
 
   // The step loop runs either as 2T (or more) launches or as one cached HIP graph of
-  // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning, hints)).
+  // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning, hints,
+  // slice order)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
-    const double key[13] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+    const double key[14] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
                             (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
                             (double)nb, (double)p->tune_split[0], (double)p->tune_split[1],
-                            (double)p->variant_epoch, (double)nt};
+                            (double)p->variant_epoch, (double)nt, (double)sched};
     bool hit = p->graph_exec != nullptr;
-    for (int i = 0; i < 13 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    for (int i = 0; i < 14 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     if (!hit) {
       if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -948,7 +973,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-      for (int i = 0; i < 13; ++i) p->graph_key[i] = key[i];
+      for (int i = 0; i < 14; ++i) p->graph_key[i] = key[i];
     }
     if (st == nullptr) {
       // graphs are replayed on the plan's own stream, ordered after the default stream
@@ -1017,7 +1042,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   if (k < 1 || k > p->max_probes)
     return set_error(MFE_EINVAL, "probes = %d outside 1..%d (the plan's max_probes)", k, p->max_probes);
   struct Cand {
-    int nb, sr, sc, nt;
+    int nb, sr, sc, nt, sched;
   };
   // The default configuration is timed first and kept unless another is more than 1%
   // faster, so the choice does not flip on timing noise.
@@ -1027,16 +1052,20 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
     if (nb != kBatch) nbs.push_back(nb);
   // Stream hints: the plan's size-based default for every form, and the other setting for
   // the one-launch form.
-  const int32_t keep_nt = p->tune_nt;
+  // Slice order: the default rule (-1) for every form, and both fixed orders for the
+  // one-launch form.
+  const int32_t keep_nt = p->tune_nt, keep_sched = p->tune_sched;
   p->tune_nt = -1;
   const int nt0 = stream_hints(p);
   p->tune_nt = keep_nt;
   for (int nb : nbs) {
     if (nb == 16 && k > 16) continue;
-    cands.push_back({nb, 2, 2, nt0});  // both directions in one launch
+    cands.push_back({nb, 2, 2, nt0, -1});  // both directions in one launch
     for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
-      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc, nt0});
-    cands.push_back({nb, 2, 2, 1 - nt0});
+      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc, nt0, -1});
+    cands.push_back({nb, 2, 2, 1 - nt0, -1});
+    cands.push_back({nb, 2, 2, nt0, 0});
+    cands.push_back({nb, 2, 2, nt0, 1});
   }
   double *d = nullptr, *e = nullptr;
   MFE_CHECK(ensure(&d, p->M));
@@ -1059,6 +1088,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
     p->tune_split[0] = cands[i].sr;
     p->tune_split[1] = cands[i].sc;
     p->tune_nt = cands[i].nt;
+    p->tune_sched = cands[i].sched;
     double t = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code objects
       const int rc = plan_run(p, &trial, alpha_b, beta_b, 0, d, e, nullptr, nullptr);
@@ -1067,6 +1097,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
         p->tune_split[0] = keep_sr;
         p->tune_split[1] = keep_sc;
         p->tune_nt = keep_nt;
+        p->tune_sched = keep_sched;
         return rc;
       }
       t = p->last_step_ms;
@@ -1080,11 +1111,13 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   p->tune_split[0] = cands[best_i].sr;
   p->tune_split[1] = cands[best_i].sc;
   p->tune_nt = cands[best_i].nt;
+  p->tune_sched = cands[best_i].sched;
   if (chosen) {
     chosen[0] = p->tune_batch;
     chosen[1] = p->tune_split[0];
     chosen[2] = p->tune_split[1];
     chosen[3] = p->tune_nt;
+    chosen[4] = p->tune_sched;
   }
   if (best_step_ms) *best_step_ms = best;
   if (n_candidates) *n_candidates = (int32_t)cands.size();

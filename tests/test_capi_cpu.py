@@ -125,7 +125,20 @@ def test_autotune_argument_checks(lib):
 
 
 def test_set_tuning_argument_checks(lib):
-    assert lib.mfe_plan_set_tuning(None, 8, 0, 0, -1) == -1
+    assert lib.mfe_plan_set_tuning(None, 8, 0, 0, -1, -1) == -1
+
+
+def test_probe_argument_checks(lib):
+    """The ceiling probes refuse sizes, load counts and row lengths they do not support
+    before allocating anything."""
+    ms = C.c_double()
+    assert lib.mfe_probe_gather(4, 10, 1, 1, C.byref(ms), None) == -1
+    assert lib.mfe_probe_gather(1024, 10, 3, 1, C.byref(ms), None) == -1
+    assert lib.mfe_probe_gather_sorted(1024, 10, 7, 1, C.byref(ms), None) == -1
+    assert lib.mfe_probe_gather_sorted(1024, 0, 10, 1, C.byref(ms), None) == -1
+    assert lib.mfe_probe_gather_sorted(8 << 32, 10, 10, 1, C.byref(ms), None) == -1
+    assert lib.mfe_probe_gather_sorted(1024, 10, 10, 1, None, None) == -1
+    assert lib.mfe_probe_stream(8, 1, C.byref(ms), None) == -1
 
 
 def test_variant_argument_checks(lib):

@@ -535,8 +535,11 @@ def test_set_tuning_rejects_missing_layout():
             plan.set_tuning(5, 0, 0)
         with pytest.raises(MfeError):
             plan.set_tuning(1, 2, 2, 2)
+        with pytest.raises(MfeError):
+            plan.set_tuning(1, 2, 2, -1, 2)
         plan.set_tuning(16, 0, 0)
         plan.set_tuning(1, 2, 2, 1)
+        plan.set_tuning(1, 2, 2, -1, 0)
 
 
 def test_autotune_keeps_results_bitwise():
@@ -556,16 +559,36 @@ def test_autotune_keeps_results_bitwise():
             _say("autotune", choice)
             assert choice["loads_in_flight"] in (1, 2, 4, 8, 16)
             assert choice["stream_hints"] in (0, 1)
-            # 1, 2, 4, 8, 16 loads x (one launch per step with either stream-hint setting,
-            # one launch per direction, and for the single matrix its column direction's
-            # two-part form)
-            assert choice["candidates"] == (20 if len(group) == 1 else 15)
+            assert choice["slice_order"] in (-1, 0, 1)
+            # 1, 2, 4, 8, 16 loads x (one launch per step with either stream-hint setting
+            # and with each fixed slice order, one launch per direction, and for the single
+            # matrix its column direction's two-part form)
+            assert choice["candidates"] == (30 if len(group) == 1 else 25)
             b = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=True)
             b = {key: v.clone() for key, v in b.items()}
             c = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=False)
             for key in ("u_bar", "v_bar"):
                 assert torch.equal(b[key], c[key])
                 assert torch.equal(a[key], b[key])
+
+
+def test_slice_order_bitwise_equal():
+    """The longest-first slice order only changes which wavefront takes which slice: runs
+    with either fixed order (and the default rule) give the same results bit for bit,
+    through the one-launch step and through the split kernels of a small plan."""
+    from paper_1602_06621_amd import Plan
+
+    for csr, k in ((scaled_sparse(140_000, 70_000, poisson_lengths(140_000, 9.0, 70_000, 41), 2.0, 42), 16),
+                   (scaled_sparse(3000, 1100, poisson_lengths(3000, 7.0, 1100, 43), 2.0, 44), 8)):
+        with Plan([_gpu(csr)], max_probes=k) as plan:
+            out = {}
+            for order in (-1, 0, 1):
+                plan.set_tuning(1, 2, 2, -1, order)
+                g = plan.equilibrate(None, None, 0.1, 10.0, 40, k, 3, use_graph=True)
+                out[order] = {key: v.clone() for key, v in g.items()}
+        for key in ("u_bar", "v_bar"):
+            assert torch.equal(out[0][key], out[1][key])
+            assert torch.equal(out[-1][key], out[1][key])
 
 
 def test_mismatched_targets_run_with_a_warning():
