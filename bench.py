@@ -47,7 +47,7 @@ GEN_SEED, PROBE_SEED = 1001, 2001
 # plain 512 MiB copy; TRAFFIC_SOURCE names the profile summary they were read from.  None
 # when the kernel has changed since the counters were taken.
 HEADLINE_KERNEL = "k_phase_both<16,true,1>"
-TRAFFIC_BYTES_PER_STEP = (516.8 + 36.3) * 1e6
+TRAFFIC_BYTES_PER_STEP = (543.2 + 40.3) * 1e6
 TRAFFIC_SOURCE = "profiles/k_phase_csr_1e6x5e5_k16.md (FETCH_SIZE x 1.861 + WRITE_SIZE x 0.931 per launch)"
 
 

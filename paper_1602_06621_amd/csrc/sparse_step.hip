@@ -312,6 +312,19 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk,
   o[3] = w.x[3];
 }
 
+// Minimum waves per SIMD the one-launch step kernel is compiled for.  One slot in flight
+// with at most 16 probes: 8 (64 VGPRs, 12 bytes spilled), which keeps eight workgroups per
+// CU resident instead of five (85 VGPRs): 131.3 -> 126.1 us per step on the 1e6 x 5e5
+// headline (131 at six waves); the 2e5 x 1e5 warm-start matrix is unchanged (40.2 us).
+// The same bound on the single-direction and Section 6 kernels made them slower (the
+// symmetric product 75.8 -> 83.5 us, per-index targets 132.7 -> 140.2 us: 28-44 bytes
+// spilled), so they keep the compiler's choice, as do other probe counts and loads in
+// flight (more accumulators or loads).
+template <int KP, int NB>
+constexpr int step_waves() {
+  return (KP <= 16 && NB == 1) ? 8 : 1;
+}
+
 // One direction of one step; extra workgroups past side_blocks draw the sign words
 // of step t+2 (the row launch carries them).
 template <int KP, bool PACKED, int NB>
@@ -333,7 +346,8 @@ __device__ __forceinline__ void phase_both(const PhaseArgs& a, const SideDev& C,
 }
 
 template <int KP, bool PACKED, int NB>
-__global__ __launch_bounds__(kBlock) void k_phase_both(PhaseArgs a, SideDev C, int64_t col_blocks) {
+__global__ __launch_bounds__(kBlock, (step_waves<KP, NB>())) void k_phase_both(PhaseArgs a, SideDev C,
+                                                                            int64_t col_blocks) {
   const int64_t b = blockIdx.x;
   if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks);
   else if (a.side.nt) phase_both<KP, PACKED, NB, false, true>(a, C, b);
