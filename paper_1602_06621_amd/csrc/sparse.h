@@ -24,7 +24,8 @@ constexpr int kBlock = 256;      // threads per workgroup of the step kernel
 // Slots whose loads a lane issues together (1, 2, 4, 8 or 16; the autotuner may choose
 // another per plan).  One slot at a time -- the entry load, then its gather -- was
 // measured fastest on the 1e6 x 5e5 headline: 147 us per step against 173 (2), 177 (4),
-// 179 (8) and 187 (16), at the same occupancy for 1 and 8.
+// 179 (8) and 187 (16), at the same occupancy for 1 and 8 (grid order, five resident
+// workgroups per CU); with the current kernel, 126.7 against 145.4 (2).
 #ifndef MFE_BATCH
 #define MFE_BATCH 1
 #endif
@@ -33,7 +34,7 @@ constexpr int kBatch = MFE_BATCH;
 // 256 MB last-level cache -- use non-temporal loads and stores by default: caching them
 // gains nothing and evicts the gathered descriptor tables.  Smaller plans keep plain
 // accesses, whose lines the last-level cache holds from one step to the next (measured
-// on the 1e6 x 5e5 headline, ~256 MB of streams: 147 us per step plain, slower hinted).
+// on the 1e6 x 5e5 headline, ~256 MB of streams: 126.7 us per step plain, 161.5 hinted).
 constexpr int64_t kStreamHintBytes = 512ll << 20;
 
 struct SideLayout {
