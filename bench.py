@@ -569,7 +569,8 @@ def profile_lsqr():
 
 def profile_c2():
     """Counter / timing run for the batched workload: 512 matrices in one plan, 16 loads
-    in flight (the autotuner's choice), 20 eager steps, then the calibration copy."""
+    in flight and 512 threads per workgroup (the autotuner's choice), 20 eager steps, then
+    the calibration copy."""
     import torch
 
     from workloads import batched_sparse
@@ -580,7 +581,7 @@ def profile_c2():
     G = [mfe.Csr.from_arrays(c.m, c.n, c.row_ptr, c.col_idx, c.val, device="cuda:0") for c in mats]
     del mats
     with mfe.Plan(G, max_probes=8) as plan:
-        plan.set_tuning(16, 2, 2)
+        plan.set_tuning(16, 2, 2, -1, -1, 512)
         plan.equilibrate(None, None, GAMMA, BOX_M, 20, 8, 2002)
         torch.cuda.synchronize()
     calibration_copy()

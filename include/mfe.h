@@ -320,13 +320,14 @@ int mfe_plan_equilibrate_trace(mfe_plan* plan, const mfe_equil_params* p, int32_
  * (modes 2, 2: the default) or one launch per direction (mode 0); and, for a
  * single-matrix plan whose gathered table exceeds 6 MB, each such direction also in mode
  * 1 (two launches over the halves of the table, FP64 partial sums in between); and the
- * one-launch form also with the other stream-hint setting and with each fixed slice
- * order (see mfe_plan_set_tuning).  Every
+ * one-launch form also with the other stream-hint setting, with each fixed slice order
+ * and with 512 (p->probes <= 16) and 1024 (p->probes <= 8) threads per workgroup (see
+ * mfe_plan_set_tuning).  Every
  * configuration adds the same terms in the same order, so tuning never changes a result
  * bit.  (Plans whose directions have few slices, and plans with Section 6 settings, run
  * their own launch forms whatever the modes.)
- * chosen (host int32[5], nullable): loads in flight, mode of the rows, mode of the columns,
- * stream hints (0 or 1), slice order (-1, 0 or 1);
+ * chosen (host int32[6], nullable): loads in flight, mode of the rows, mode of the columns,
+ * stream hints (0 or 1), slice order (-1, 0 or 1), threads per workgroup;
  * best_step_ms, n_candidates: nullable.  Allocates two temporary device arrays.
  * EINVAL: plan NULL, invalid p (as mfe_plan_equilibrate), trial_steps out of range. */
 int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* alpha_b, const double* beta_b,
@@ -343,11 +344,16 @@ int mfe_plan_autotune(mfe_plan* plan, const mfe_equil_params* p, const double* a
  * or columns) in order of decreasing width, which keeps the end of a launch of several
  * rounds of workgroups from running the device half empty; 0: in storage order; -1 (the
  * default): 1 when the one-launch step has more workgroups than five per compute unit or
- * a direction runs one slice per workgroup, else 0.  None of these changes a result bit.
+ * a direction runs one slice per workgroup, else 0.  workgroup_threads: threads per
+ * workgroup of the one-launch step (64 rows each per wavefront): 256, 512 or 1024, or 0 for
+ * the default 256; a run uses at most 1024 threads up to 8 probes (512 with 16-byte
+ * descriptors), 512 up to 16 (256 with one load in flight) and 256 above, and 256 with
+ * Section 6 settings.
+ * None of these changes a result bit.
  * EINVAL: plan NULL or a value out of range; EUNSUPPORTED: a two-part mode for a
  * direction without the layout. */
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode,
-                        int32_t stream_hints, int32_t slice_order);
+                        int32_t stream_hints, int32_t slice_order, int32_t workgroup_threads);
 
 /* ---- Chambolle-Cremers-Pock on the Lasso (Section 5.2), sparse plans ---------------- */
 

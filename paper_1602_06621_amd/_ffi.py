@@ -86,7 +86,7 @@ def _lib():
         "mfe_plan_equilibrate_trace": [vp, C.POINTER(_Params), i32, C.POINTER(dbl), vp, vp, vp, vp],
         "mfe_plan_autotune": [vp, C.POINTER(_Params), vp, vp, i32, vp, C.POINTER(dbl), C.POINTER(i32)],
         "mfe_plan_warmstart": [vp, vp, u64, i32, vp, vp, dbl, dbl, i32, vp, vp, vp],
-        "mfe_plan_set_tuning": [vp, i32, i32, i32, i32, i32],
+        "mfe_plan_set_tuning": [vp, i32, i32, i32, i32, i32, i32],
         "mfe_plan_create_symmetric": [C.POINTER(_Matrix), i32, vp, C.POINTER(vp)],
         "mfe_plan_op_norm": [vp, vp, vp, i32, dbl, C.POINTER(dbl), C.POINTER(i32), vp],
         "mfe_plan_ccp_lasso": [vp, vp, vp, vp, dbl, dbl, i32, i32, vp, vp, C.POINTER(_CcpInfo), vp],
@@ -454,19 +454,21 @@ class Plan:
         all of them) and keeps the fastest for this plan.  Returns the choice."""
         ah, bh, a0, b0 = self._targets(alpha, beta)
         p = _params(a0, b0, gamma, M, trial_steps, probes, seed, 0, 0, None, None, stream)
-        chosen = (C.c_int32 * 5)()
+        chosen = (C.c_int32 * 6)()
         best, n = C.c_double(), C.c_int32()
         _check(_lib().mfe_plan_autotune(self._h, C.byref(p), ah, bh, int(trial_steps), chosen, C.byref(best),
                                         C.byref(n)))
         return dict(loads_in_flight=chosen[0], rows_mode=chosen[1], cols_mode=chosen[2], stream_hints=chosen[3],
-                    slice_order=chosen[4], step_ms=best.value, candidates=n.value)
+                    slice_order=chosen[4], workgroup_threads=chosen[5], step_ms=best.value,
+                    candidates=n.value)
 
-    def set_tuning(self, loads_in_flight=1, rows_mode=2, cols_mode=2, stream_hints=-1, slice_order=-1):
+    def set_tuning(self, loads_in_flight=1, rows_mode=2, cols_mode=2, stream_hints=-1, slice_order=-1,
+                   workgroup_threads=0):
         """Launch configuration of the step kernels (see mfe_plan_set_tuning); the defaults
         are the library's (one load in flight, both directions in one launch, stream hints
-        by the plan's size, slice order by the launch shape)."""
+        by the plan's size, slice order by the launch shape, 256 threads per workgroup)."""
         _check(_lib().mfe_plan_set_tuning(self._h, int(loads_in_flight), int(rows_mode), int(cols_mode),
-                                          int(stream_hints), int(slice_order)))
+                                          int(stream_hints), int(slice_order), int(workgroup_threads)))
 
     def last_timing(self):
         a, b = C.c_double(), C.c_double()

@@ -360,7 +360,7 @@ int mfe_plan_set_blocks(mfe_plan* plan, const int64_t* row_ptr, int64_t row_bloc
 }
 
 int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mode, int32_t cols_mode,
-                        int32_t stream_hints, int32_t slice_order) {
+                        int32_t stream_hints, int32_t slice_order, int32_t workgroup_threads) {
   clear_error();
   if (!plan) return set_error(MFE_EINVAL, "plan is NULL");
   if (loads_in_flight != 1 && loads_in_flight != 2 && loads_in_flight != 4 && loads_in_flight != 8 &&
@@ -373,6 +373,8 @@ int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mo
     return set_error(MFE_EINVAL, "stream_hints must be -1 (by the plan's size), 0 or 1");
   if (slice_order < -1 || slice_order > 1)
     return set_error(MFE_EINVAL, "slice_order must be -1 (by the launch shape), 0 or 1");
+  if (workgroup_threads != 0 && workgroup_threads != 256 && workgroup_threads != 512 && workgroup_threads != 1024)
+    return set_error(MFE_EINVAL, "workgroup_threads must be 0 (the default, 256), 256, 512 or 1024");
   if ((rows_mode == 1 && !plan->rows.len_lo) || (cols_mode == 1 && !plan->cols.len_lo))
     return set_error(MFE_EUNSUPPORTED, "two-part mode requested for a direction without the two-part layout");
   plan->tune_batch = loads_in_flight;
@@ -380,6 +382,7 @@ int mfe_plan_set_tuning(mfe_plan* plan, int32_t loads_in_flight, int32_t rows_mo
   plan->tune_split[1] = cols_mode;
   plan->tune_nt = stream_hints;
   plan->tune_sched = slice_order;
+  plan->tune_wg = workgroup_threads == 256 ? 0 : workgroup_threads;
   return MFE_OK;
 }
 

@@ -181,6 +181,7 @@ struct mfe_plan {
   int32_t tune_split[2] = {2, 2};
   int32_t tune_nt = -1;
   int32_t tune_sched = -1;
+  int32_t tune_wg = 0;  // threads per workgroup of the one-launch step (0: kBlock)
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -200,7 +201,7 @@ struct mfe_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  double graph_key[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double graph_key[15] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // ---- Section 6 variants
   // Symmetric plan (Algorithm 2): one square symmetric matrix; the row entries are also
   // stored with indices into the rows' own internal order, and a step is one launch.

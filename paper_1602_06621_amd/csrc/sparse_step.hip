@@ -193,12 +193,13 @@ __device__ __forceinline__ void finish_update(const SideDev& S, const MatDev* __
 // One lane per row.  part_mode (two-part layouts, see SideDev): 0 whole rows; 1 entries
 // [0, len_lo) to the partial sums; 2 partial sums plus entries [len_lo, len), then the
 // update.
-template <int KP, bool PACKED, int NB, bool VAR, bool NT>
+template <int KP, bool PACKED, int NB, bool VAR, bool NT, int WT = kBlock>
 __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __restrict__ mats, int k,
                                             const StepScalars& sc, int64_t blk, int* flag) {
+  // WT: threads per workgroup when fixed at compile time (0: the launch's blockDim)
   using C = Codec<KP, PACKED>;
   using DT = typename C::T;
-  const int64_t wv = blk * (kBlock / kSlice) + (threadIdx.x >> 6);  // wavefront of the launch
+  const int64_t wv = blk * ((WT ? WT : (int)blockDim.x) / kSlice) + (threadIdx.x >> 6);  // wavefront of the launch
   if (wv * kSlice >= S.nint) return;  // whole wavefronts leave together
   const int64_t s = S.sched ? (int64_t)S.sched[wv] : wv;
   const int64_t r = s * kSlice + (threadIdx.x & 63);
@@ -325,6 +326,20 @@ constexpr int step_waves() {
   return (KP <= 16 && NB == 1) ? 8 : 1;
 }
 
+// Largest workgroup of the one-launch step kernel (the launch size is a plan tuning, 256
+// threads by default): 1024 threads up to 8 probes with 8-byte descriptors, 512 up to
+// 16, 256 above -- and 256 for
+// 16 probes at one slot in flight, the headline form: a larger bound caps the registers
+// the compiler may give a lane, which raised that kernel's spill from 12 to 20 bytes and
+// its step from 126 to 130 us (the 200k x 100k warm-start matrix gained 1 us at 512
+// threads); at 1024 threads the 16-probe forms spilled 20-212 bytes.  The batched
+// workload (8 probes, 16 slots in flight) runs 2.08 ms per step at 512 threads against
+// 2.25 at 256 and 2.23 at 1024.
+template <int KP, int NB, bool PACKED>
+constexpr int step_max_threads() {
+  return KP <= 8 && PACKED ? 1024 : (KP <= 16 && NB > 1 ? 512 : kBlock);
+}
+
 // One direction of one step; extra workgroups past side_blocks draw the sign words
 // of step t+2 (the row launch carries them).
 template <int KP, bool PACKED, int NB>
@@ -339,26 +354,30 @@ __global__ __launch_bounds__(kBlock) void k_phase(PhaseArgs a) {
 // then the sign words): for plans too small to fill the device with one direction.  The
 // directions read the other's descriptors of step t-1 and write their own of step t, so
 // they are independent within a step.
-template <int KP, bool PACKED, int NB, bool VAR, bool NT>
+template <int KP, bool PACKED, int NB, bool VAR, bool NT, int WT = kBlock>
 __device__ __forceinline__ void phase_both(const PhaseArgs& a, const SideDev& C, int64_t b) {
-  if (b < a.side_blocks) side_update<KP, PACKED, NB, VAR, NT>(a.side, a.mats, a.k, a.sc, b, a.flag);
-  else side_update<KP, PACKED, NB, VAR, NT>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
+  if (b < a.side_blocks) side_update<KP, PACKED, NB, VAR, NT, WT>(a.side, a.mats, a.k, a.sc, b, a.flag);
+  else side_update<KP, PACKED, NB, VAR, NT, WT>(C, a.mats, a.k, a.sc, b - a.side_blocks, a.flag);
 }
 
 template <int KP, bool PACKED, int NB>
-__global__ __launch_bounds__(kBlock, (step_waves<KP, NB>())) void k_phase_both(PhaseArgs a, SideDev C,
+__global__ __launch_bounds__((step_max_threads<KP, NB, PACKED>()), (step_waves<KP, NB>())) void k_phase_both(PhaseArgs a, SideDev C,
                                                                             int64_t col_blocks) {
+  // workgroup size fixed at compile time where the bound allows only kBlock threads (the
+  // constant keeps that kernel's register allocation), else read from the launch
+  constexpr int WT = step_max_threads<KP, NB, PACKED>() == kBlock ? kBlock : 0;
   const int64_t b = blockIdx.x;
-  if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks);
-  else if (a.side.nt) phase_both<KP, PACKED, NB, false, true>(a, C, b);
-  else phase_both<KP, PACKED, NB, false, false>(a, C, b);
+  if (b >= a.side_blocks + col_blocks)
+    signgen_block(a.gen, b - a.side_blocks - col_blocks, (int64_t)(WT ? WT : (int)blockDim.x));
+  else if (a.side.nt) phase_both<KP, PACKED, NB, false, true, WT>(a, C, b);
+  else phase_both<KP, PACKED, NB, false, false, WT>(a, C, b);
 }
 
 // The same with the Section 6 variant update (per-index targets, block sides).
 template <int KP, bool PACKED>
 __global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev C, int64_t col_blocks) {
   const int64_t b = blockIdx.x;
-  if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks);
+  if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks, (int64_t)blockDim.x);
   else if (a.side.nt) phase_both<KP, PACKED, kBatch, true, true>(a, C, b);
   else phase_both<KP, PACKED, kBatch, true, false>(a, C, b);
 }
@@ -710,9 +729,23 @@ struct PhaseLauncher {
 
 template <int KP, bool PACKED>
 struct BothLauncher {
-  static void run(const PhaseArgs& a, const SideDev& C, int64_t col_blocks, int nb, hipStream_t st) {
-    const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block(kBlock);
-    if (a.side.tgt || a.side.zout || C.tgt || C.zout) {
+  // threads: workgroup size of the plain kernel (256, 512 or 1024, at most
+  // step_max_threads; 256 for the Section 6 variant kernel); the block counts of the
+  // arguments are for kBlock-thread workgroups and are recomputed here.
+  static void run(const PhaseArgs& a0, const SideDev& C, int64_t col_blocks0, int nb, int threads, hipStream_t st) {
+    const bool var = a0.side.tgt || a0.side.zout || C.tgt || C.zout;
+    int wg = kBlock;
+    if (!var) {
+      const int cap = nb <= 1 ? step_max_threads<KP, 1, PACKED>() : step_max_threads<KP, 2, PACKED>();
+      wg = std::min(threads, cap);
+    }
+    PhaseArgs a = a0;
+    a.side_blocks = ceil_div(a0.side.nint, wg);
+    a.gen_blocks = a0.gen_blocks > 0 ? ceil_div(a0.gen.nblocks, wg) : 0;
+    const int64_t col_blocks = ceil_div(C.nint, wg);
+    (void)col_blocks0;
+    const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block((unsigned)wg);
+    if (var) {
       k_phase_both_var<KP, PACKED><<<grid, block, 0, st>>>(a, C, col_blocks);
     } else if (nb <= 1) {
       k_phase_both<KP, PACKED, 1><<<grid, block, 0, st>>>(a, C, col_blocks);
@@ -876,6 +909,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
   const int nb = p->tune_batch;
   const int nt = stream_hints(p);
   int sched = 1;  // slice order (slice_schedule), set below
+  const int32_t wg_threads = p->tune_wg > 0 ? p->tune_wg : kBlock;  // one-launch step workgroups
   for (int i = 0; i < 2; ++i) {
     const bool need = (i == 0 ? split_rows : split_cols) != 0;
     if (need && !p->part[i]) {
@@ -938,7 +972,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     if (fused) {
       const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
       if (a.split <= 1 && c.split <= 1) {
-        dispatch<BothLauncher>(k, packed, a, c.side, c.side_blocks, nb, s);
+        dispatch<BothLauncher>(k, packed, a, c.side, c.side_blocks, nb, (int)wg_threads, s);
         for (int si = 0; si < 2; ++si)
           if (blocked[si]) {
             const PhaseArgs& x = si == 0 ? a : c;
@@ -968,15 +1002,15 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
 
   // The step loop runs either as 2T (or more) launches or as one cached HIP graph of
   // those launches (captured once per (k, T, t0, gamma, M, seed, batch, tuning, hints,
-  // slice order)).
+  // slice order, workgroup size)).
   hipStream_t run_st = st;
   if (use_graph && T > 0) {
-    const double key[14] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
+    const double key[15] = {(double)k, (double)T, (double)prm->t0, prm->gamma, prm->box_M,
                             (double)(seed >> 32), (double)(seed & 0xFFFFFFFFull), (double)prm->batch,
                             (double)nb, (double)p->tune_split[0], (double)p->tune_split[1],
-                            (double)p->variant_epoch, (double)nt, (double)sched};
+                            (double)p->variant_epoch, (double)nt, (double)sched, (double)wg_threads};
     bool hit = p->graph_exec != nullptr;
-    for (int i = 0; i < 14 && hit; ++i) hit = (key[i] == p->graph_key[i]);
+    for (int i = 0; i < 15 && hit; ++i) hit = (key[i] == p->graph_key[i]);
     if (!p->cap_stream) MFE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     if (!hit) {
       if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -987,7 +1021,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       launch_steps(p->cap_stream);
       MFE_HIP(hipStreamEndCapture(p->cap_stream, &p->graph));
       MFE_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
-      for (int i = 0; i < 14; ++i) p->graph_key[i] = key[i];
+      for (int i = 0; i < 15; ++i) p->graph_key[i] = key[i];
     }
     if (st == nullptr) {
       // graphs are replayed on the plan's own stream, ordered after the default stream
@@ -1056,7 +1090,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   if (k < 1 || k > p->max_probes)
     return set_error(MFE_EINVAL, "probes = %d outside 1..%d (the plan's max_probes)", k, p->max_probes);
   struct Cand {
-    int nb, sr, sc, nt, sched;
+    int nb, sr, sc, nt, sched, wg;
   };
   // The default configuration is timed first and kept unless another is more than 1%
   // faster, so the choice does not flip on timing noise.
@@ -1068,18 +1102,20 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   // the one-launch form.
   // Slice order: the default rule (-1) for every form, and both fixed orders for the
   // one-launch form.
-  const int32_t keep_nt = p->tune_nt, keep_sched = p->tune_sched;
+  const int32_t keep_nt = p->tune_nt, keep_sched = p->tune_sched, keep_wg = p->tune_wg;
   p->tune_nt = -1;
   const int nt0 = stream_hints(p);
   p->tune_nt = keep_nt;
   for (int nb : nbs) {
     if (nb == 16 && k > 16) continue;
-    cands.push_back({nb, 2, 2, nt0, -1});  // both directions in one launch
+    cands.push_back({nb, 2, 2, nt0, -1, 0});  // both directions in one launch
     for (int sr = 0; sr <= (p->rows.len_lo ? 1 : 0); ++sr)
-      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc, nt0, -1});
-    cands.push_back({nb, 2, 2, 1 - nt0, -1});
-    cands.push_back({nb, 2, 2, nt0, 0});
-    cands.push_back({nb, 2, 2, nt0, 1});
+      for (int sc = 0; sc <= (p->cols.len_lo ? 1 : 0); ++sc) cands.push_back({nb, sr, sc, nt0, -1, 0});
+    cands.push_back({nb, 2, 2, 1 - nt0, -1, 0});
+    cands.push_back({nb, 2, 2, nt0, 0, 0});
+    cands.push_back({nb, 2, 2, nt0, 1, 0});
+    if (k <= 16) cands.push_back({nb, 2, 2, nt0, -1, 512});  // larger workgroups of the one-launch kernel
+    if (k <= 8) cands.push_back({nb, 2, 2, nt0, -1, 1024});
   }
   double *d = nullptr, *e = nullptr;
   MFE_CHECK(ensure(&d, p->M));
@@ -1103,6 +1139,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
     p->tune_split[1] = cands[i].sc;
     p->tune_nt = cands[i].nt;
     p->tune_sched = cands[i].sched;
+    p->tune_wg = cands[i].wg;
     double t = 0.0;
     for (int rep = 0; rep < 2; ++rep) {  // the first run warms caches and code objects
       const int rc = plan_run(p, &trial, alpha_b, beta_b, 0, d, e, nullptr, nullptr);
@@ -1112,6 +1149,7 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
         p->tune_split[1] = keep_sc;
         p->tune_nt = keep_nt;
         p->tune_sched = keep_sched;
+        p->tune_wg = keep_wg;
         return rc;
       }
       t = p->last_step_ms;
@@ -1126,12 +1164,14 @@ int plan_autotune(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_
   p->tune_split[1] = cands[best_i].sc;
   p->tune_nt = cands[best_i].nt;
   p->tune_sched = cands[best_i].sched;
+  p->tune_wg = cands[best_i].wg;
   if (chosen) {
     chosen[0] = p->tune_batch;
     chosen[1] = p->tune_split[0];
     chosen[2] = p->tune_split[1];
     chosen[3] = p->tune_nt;
     chosen[4] = p->tune_sched;
+    chosen[5] = p->tune_wg > 0 ? p->tune_wg : kBlock;
   }
   if (best_step_ms) *best_step_ms = best;
   if (n_candidates) *n_candidates = (int32_t)cands.size();

@@ -125,7 +125,7 @@ def test_autotune_argument_checks(lib):
 
 
 def test_set_tuning_argument_checks(lib):
-    assert lib.mfe_plan_set_tuning(None, 8, 0, 0, -1, -1) == -1
+    assert lib.mfe_plan_set_tuning(None, 8, 0, 0, -1, -1, 0) == -1
 
 
 def test_probe_argument_checks(lib):

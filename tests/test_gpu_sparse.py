@@ -537,6 +537,8 @@ def test_set_tuning_rejects_missing_layout():
             plan.set_tuning(1, 2, 2, 2)
         with pytest.raises(MfeError):
             plan.set_tuning(1, 2, 2, -1, 2)
+        with pytest.raises(MfeError):
+            plan.set_tuning(1, 2, 2, -1, -1, 384)
         plan.set_tuning(16, 0, 0)
         plan.set_tuning(1, 2, 2, 1)
         plan.set_tuning(1, 2, 2, -1, 0)
@@ -560,10 +562,12 @@ def test_autotune_keeps_results_bitwise():
             assert choice["loads_in_flight"] in (1, 2, 4, 8, 16)
             assert choice["stream_hints"] in (0, 1)
             assert choice["slice_order"] in (-1, 0, 1)
-            # 1, 2, 4, 8, 16 loads x (one launch per step with either stream-hint setting
-            # and with each fixed slice order, one launch per direction, and for the single
-            # matrix its column direction's two-part form)
-            assert choice["candidates"] == (30 if len(group) == 1 else 25)
+            assert choice["workgroup_threads"] in (256, 512, 1024)
+            # 1, 2, 4, 8, 16 loads x (one launch per step with either stream-hint setting,
+            # with each fixed slice order and with 512 threads per workgroup (and 1024 for
+            # k = 8), one launch per direction, and for the single matrix (k = 16) its column
+            # direction's two-part form)
+            assert choice["candidates"] == (35 if len(group) == 1 else 35)
             b = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=True)
             b = {key: v.clone() for key, v in b.items()}
             c = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 5, use_graph=False)
@@ -589,6 +593,30 @@ def test_slice_order_bitwise_equal():
         for key in ("u_bar", "v_bar"):
             assert torch.equal(out[0][key], out[1][key])
             assert torch.equal(out[-1][key], out[1][key])
+
+
+def test_workgroup_size_bitwise_equal():
+    """256, 512 and 1024 threads per workgroup of the one-launch step change only which
+    workgroup runs which slices: results are equal bit for bit (one slot in flight, and
+    16; a single matrix with k = 16, where 1024 runs as 512, and a batch of uneven matrices
+    with k = 8)."""
+    from paper_1602_06621_amd import Plan
+
+    single = [scaled_sparse(140_000, 70_000, poisson_lengths(140_000, 9.0, 70_000, 47), 2.0, 48)]
+    batch = [scaled_sparse(m, n, poisson_lengths(m, 8.0, n, 60 + i), 2.0, 70 + i)
+             for i, (m, n) in enumerate(((70_000, 30_000), (66_000, 66_000), (90_000, 25_000)))]
+    for group, k in ((single, 16), (batch, 8)):
+        with Plan([_gpu(c) for c in group], max_probes=k) as plan:
+            out = {}
+            for nb in (1, 16):
+                for wg in (0, 512, 1024):
+                    plan.set_tuning(nb, 2, 2, -1, -1, wg)
+                    g = plan.equilibrate(None, None, 0.1, 10.0, 30, k, 7, use_graph=True)
+                    out[(nb, wg)] = {key: v.clone() for key, v in g.items()}
+        ref = out[(1, 0)]
+        for cfg, g in out.items():
+            for key in ("u_bar", "v_bar"):
+                assert torch.equal(g[key], ref[key]), cfg
 
 
 def test_stream_hints_bitwise_equal():
