@@ -730,9 +730,10 @@ struct PhaseLauncher {
 template <int KP, bool PACKED>
 struct BothLauncher {
   // threads: workgroup size of the plain kernel (256, 512 or 1024, at most
-  // step_max_threads; 256 for the Section 6 variant kernel); the block counts of the
-  // arguments are for kBlock-thread workgroups and are recomputed here.
-  static void run(const PhaseArgs& a0, const SideDev& C, int64_t col_blocks0, int nb, int threads, hipStream_t st) {
+  // step_max_threads; 256 for the Section 6 variant kernel); the row and sign-word block
+  // counts of a0 are for kBlock-thread workgroups and are recomputed here, with the
+  // column block count.
+  static void run(const PhaseArgs& a0, const SideDev& C, int nb, int threads, hipStream_t st) {
     const bool var = a0.side.tgt || a0.side.zout || C.tgt || C.zout;
     int wg = kBlock;
     if (!var) {
@@ -743,7 +744,6 @@ struct BothLauncher {
     a.side_blocks = ceil_div(a0.side.nint, wg);
     a.gen_blocks = a0.gen_blocks > 0 ? ceil_div(a0.gen.nblocks, wg) : 0;
     const int64_t col_blocks = ceil_div(C.nint, wg);
-    (void)col_blocks0;
     const dim3 grid((unsigned)(a.side_blocks + col_blocks + a.gen_blocks)), block((unsigned)wg);
     if (var) {
       k_phase_both_var<KP, PACKED><<<grid, block, 0, st>>>(a, C, col_blocks);
@@ -972,7 +972,7 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
     if (fused) {
       const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
       if (a.split <= 1 && c.split <= 1) {
-        dispatch<BothLauncher>(k, packed, a, c.side, c.side_blocks, nb, (int)wg_threads, s);
+        dispatch<BothLauncher>(k, packed, a, c.side, nb, (int)wg_threads, s);
         for (int si = 0; si < 2; ++si)
           if (blocked[si]) {
             const PhaseArgs& x = si == 0 ? a : c;
