@@ -98,6 +98,34 @@ __device__ void alpha_step(LsqrScal* sc, double t, int init) {
   sc->alpha = an;
 }
 
+// x += phi/rho w; w = v_{i+1} - theta/rho w for column i, with v_{i+1} = q_{i+1} / alpha_{i+1}
+// (init: w = v_1, x = 0); nothing after a breakdown of an earlier iteration.
+__device__ __forceinline__ void lsqr_update_at(const LsqrScal* __restrict__ sc, int init, const double* __restrict__ q,
+                                               double* __restrict__ w, double* __restrict__ x, int64_t i) {
+  const bool frozen = sc->breakdown != 0 && sc->breakdown != sc->iter && !init;
+  if (frozen) return;
+  const double vi = q[i] * sc->inv_alpha;
+  if (init) {
+    w[i] = vi;
+    x[i] = 0.0;
+  } else {
+    const double wi = w[i];
+    x[i] += sc->phi_rho * wi;
+    w[i] = vi - sc->theta_rho * wi;
+  }
+}
+
+// The x / w update of the previous iteration, run by extra workgroups of the next
+// iteration's row product (n = 0: none).  That launch reads and writes none of q, w, x,
+// and the update's coefficients come from the alpha step before it.
+struct TailUpdate {
+  const LsqrScal* sc;
+  const double* q;
+  double* w;
+  double* x;
+  int64_t n;
+};
+
 // ---------------------------------------------------------------- sliced products
 //
 // A workgroup holds G groups of P wavefronts; group j takes slice G blockIdx + j (64
@@ -179,8 +207,14 @@ __global__ __launch_bounds__(kSlice * kMaxSplit) void k_sell_product(SideDev S, 
                                                                      const double* coef,
                                                                      const double* __restrict__ yprev,
                                                                      double* __restrict__ y, double* __restrict__ gout,
-                                                                     double* __restrict__ partial) {
+                                                                     double* __restrict__ partial, int64_t pblocks,
+                                                                     TailUpdate tu) {
   __shared__ double gsum[kMaxSplit];
+  if ((int64_t)blockIdx.x >= pblocks) {  // whole workgroups past the product: the tail update
+    const int64_t i = ((int64_t)blockIdx.x - pblocks) * blockDim.x + threadIdx.x;
+    if (i < tu.n) lsqr_update_at(tu.sc, 0, tu.q, tu.w, tu.x, i);
+    return;
+  }
   const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int wsub = wave % sm.P;
   const int64_t nslices = S.nint / kSlice;
@@ -390,17 +424,18 @@ __global__ __launch_bounds__(kScal) void k_scal_step(const double* __restrict__ 
 __global__ void k_lsqr_update(int64_t ncol, const LsqrScal* __restrict__ sc, int init, const double* __restrict__ q,
                               double* __restrict__ w, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool frozen = sc->breakdown != 0 && sc->breakdown != sc->iter && !init;
-  if (i >= ncol || frozen) return;
-  const double vi = q[i] * sc->inv_alpha;
-  if (init) {
-    w[i] = vi;
-    x[i] = 0.0;
-  } else {
-    const double wi = w[i];
-    x[i] += sc->phi_rho * wi;
-    w[i] = vi - sc->theta_rho * wi;
-  }
+  if (i < ncol) lsqr_update_at(sc, init, q, w, x, i);
+}
+
+// y = escale (x + phi/rho w): the solution with the pending update of the last iteration
+// (the one the next row product would apply), for the residual checks.
+__global__ void k_x_pending(int64_t ncol, const LsqrScal* __restrict__ sc, const double* __restrict__ escale,
+                            const double* __restrict__ x, const double* __restrict__ w, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  const bool frozen = sc->breakdown != 0 && sc->breakdown != sc->iter;
+  const double xi = frozen ? x[i] : x[i] + sc->phi_rho * w[i];
+  y[i] = (escale ? escale[i] : 1.0) * xi;
 }
 
 __global__ void k_scal_init(LsqrScal* sc) {
@@ -439,7 +474,8 @@ struct Work {
   }
 };
 
-// Products y = sout * inv * (A or A') g + coef * yprev, with partial sums of y^2.
+// Products y = sout * inv * (A or A') g + coef * yprev, with partial sums of y^2; the row
+// product also runs a pending LSQR x / w update (TailUpdate) in the same stream order.
 struct Ops {
   virtual ~Ops() {}
   virtual int64_t rows() const = 0;  // length of row-direction vectors
@@ -447,7 +483,7 @@ struct Ops {
   virtual int64_t fwd_blocks() const = 0;
   virtual int64_t bwd_blocks() const = 0;
   virtual void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev,
-                   double* y, double* gout, double* partial, hipStream_t st) const = 0;
+                   double* y, double* gout, double* partial, const TailUpdate& tu, hipStream_t st) const = 0;
   virtual void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev,
                    double* y, double* gout, double* partial, hipStream_t st) const = 0;
   // original <-> operator order
@@ -487,14 +523,17 @@ struct SellOps : Ops {
   int64_t fwd_blocks() const override { return ceil_div(p->rows.nslices, MR.G); }
   int64_t bwd_blocks() const override { return ceil_div(p->cols.nslices, MC.G); }
   void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
-           double* gout, double* partial, hipStream_t st) const override {
-    k_sell_product<<<dim3((unsigned)fwd_blocks()), dim3(kSlice * MR.P * MR.G), 0, st>>>(R, MR, sout, g, inv, coef,
-                                                                                          yprev, y, gout, partial);
+           double* gout, double* partial, const TailUpdate& tu, hipStream_t st) const override {
+    const int threads = kSlice * MR.P * MR.G;
+    const int64_t pb = fwd_blocks(), tb = ceil_div(tu.n, threads);
+    k_sell_product<<<dim3((unsigned)(pb + tb)), dim3(threads), 0, st>>>(R, MR, sout, g, inv, coef, yprev, y, gout,
+                                                                        partial, pb, tu);
   }
   void bwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
            double* gout, double* partial, hipStream_t st) const override {
     k_sell_product<<<dim3((unsigned)bwd_blocks()), dim3(kSlice * MC.P * MC.G), 0, st>>>(C, MC, sout, g, inv, coef,
-                                                                                          yprev, y, gout, partial);
+                                                                                          yprev, y, gout, partial,
+                                                                                          bwd_blocks(), TailUpdate{});
   }
   void to_op(bool row, const double* src, double fill, int op, double* dst, hipStream_t st) const override {
     const SideDev& S = row ? R : C;
@@ -529,7 +568,9 @@ struct DenseOps : Ops {
   int64_t fwd_blocks() const override { return ceil_div(m, kRed / 64); }
   int64_t bwd_blocks() const override { return ceil_div(n, kRed); }
   void fwd(const double* sout, const double* g, const double* inv, const double* coef, const double* yprev, double* y,
-           double* gout, double* partial, hipStream_t st) const override {
+           double* gout, double* partial, const TailUpdate& tu, hipStream_t st) const override {
+    if (tu.n > 0)
+      k_lsqr_update<<<dim3((unsigned)ceil_div(tu.n, 256)), dim3(256), 0, st>>>(tu.n, tu.sc, 0, tu.q, tu.w, tu.x);
     k_dense_fwd<<<dim3((unsigned)fwd_blocks()), dim3(kRed), 0, st>>>(A, m, n, ld, sout, g, inv, coef, yprev, y, gout,
                                                                      partial);
   }
@@ -617,17 +658,20 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
     inf.stop_reason = 3;
     max_iter = 0;
   }
-  // One iteration: five launches with no host involvement.
+  // One iteration: four launches with no host involvement.  The x / w update of an
+  // iteration runs in the next iteration's row product (at the first iteration its
+  // coefficients are zero and it rewrites w = v_1); the residual checks read x with the
+  // pending update added, and the last one is applied after the loop.
+  const TailUpdate tail{sc, v, w, x, nc};
   auto iteration = [&](hipStream_t s) {
-    // p_{i+1} = D A (E q_i) / alpha_i - (alpha_i / beta_i) p_i, du = D p_{i+1}; then beta
-    // (and the iteration count)
-    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, s);
+    // p_{i+1} = D A (E q_i) / alpha_i - (alpha_i / beta_i) p_i, du = D p_{i+1} (and the
+    // previous iteration's x / w update); then beta and the iteration count
+    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, tail, s);
     k_scal_step<<<1, kScal, 0, s>>>(part, ops.fwd_blocks(), sc, 1, 1);
     // q_{i+1} = E A' du / beta_{i+1} - (beta_{i+1} / alpha_i) q_i, ev = E q_{i+1}; then
-    // alpha and the rotation; then x and w
+    // alpha and the rotation
     ops.bwd(ee, du, &sc->inv_beta, &sc->coef_q, v, v, ev, part, s);
     k_scal_step<<<1, kScal, 0, s>>>(part, ops.bwd_blocks(), sc, 2, 0);
-    k_lsqr_update<<<upd_grid, 256, 0, s>>>(nc, sc, 0, v, w, x);
   };
   // The check_every iterations between two residual checks are captured once in a HIP
   // graph and replayed (the launches are identical from one block to the next); a
@@ -653,8 +697,8 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
     it = block_end + 1;
     {
       // residual of the original system: A (E xbar) - b, reduced over the rows
-      k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, w_tmp);
-      ops.fwd(nullptr, w_tmp, nullptr, &sc->neg_one, bb, res, nullptr, part, st);
+      k_x_pending<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, sc, ee, x, w, w_tmp);
+      ops.fwd(nullptr, w_tmp, nullptr, &sc->neg_one, bb, res, nullptr, part, TailUpdate{}, st);
       k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), &sc->res2);
       MFE_HIP(hipGetLastError());
       MFE_HIP(hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st));
@@ -677,6 +721,7 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
       }
     }
   }
+  k_lsqr_update<<<upd_grid, 256, 0, st>>>(nc, sc, 0, v, w, x);  // the last iteration's update
   ops.from_op(false, x, ee, x_out, st);
   MFE_HIP(hipGetLastError());
   MFE_HIP(hipStreamSynchronize(st));
@@ -978,7 +1023,7 @@ int run_op_norm(const SellOps& ops, const double* dd, const double* ee, int32_t 
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
     // beta u = Abar v - alpha u, then beta (and the iteration count)
-    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, st);
+    ops.fwd(dd, ev, &sc->inv_alpha, &sc->coef_p, u, u, du, part, TailUpdate{}, st);
     k_scal_step<<<1, kScal, 0, st>>>(part, ops.fwd_blocks(), sc, 1, 1);
     // alpha v = Abar' u - beta v, then alpha
     ops.bwd(ee, du, &sc->inv_beta, &sc->coef_q, v, v, ev, part, st);
@@ -1067,7 +1112,7 @@ int plan_ccp_lasso(mfe_plan* p, const double* b, const double* d, const double* 
   // f(x) at x = E xbar: ||A x - b||^2 / sqrt(lam) + sqrt(lam) ||x||_1
   auto objective = [&](double* out) -> int {
     k_mul<<<dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, st>>>(nc, ee, x, wx);
-    ops.fwd(nullptr, wx, nullptr, neg1, bb, res, nullptr, part, st);
+    ops.fwd(nullptr, wx, nullptr, neg1, bb, res, nullptr, part, TailUpdate{}, st);
     k_reduce<<<1, kRed, 0, st>>>(part, ops.fwd_blocks(), obj);
     k_l1_partial<<<cg, kRed, 0, st>>>(nc, ee, x, part);
     k_reduce<<<1, kRed, 0, st>>>(part, cg, obj + 1);
