@@ -532,7 +532,10 @@ def profile_c3():
 
 def profile_c4():
     """Timing run for the warm start on the 200,000 x 100,000 evaluation matrix: ten calls
-    of the one-call warm start (sketch, network, clip) with an untrained network."""
+    of the one-call warm start (sketch, network, clip) with an untrained network; then 200
+    Adam steps of the network's training on 4096-sample batches of a seeded synthetic set
+    (262,144 samples of 8 features)."""
+    import numpy as np
     import torch
 
     from paper_1602_06621_amd import warmstart as W
@@ -547,6 +550,11 @@ def profile_c4():
         for _ in range(10):
             plan.warm_start(params, 5)
         torch.cuda.synchronize()
+    g = np.random.default_rng(0)
+    X = torch.tensor(g.normal(0, 1, (262_144, 8)), dtype=torch.float32, device="cuda:0")
+    t = torch.tensor(g.normal(0, 1, 262_144), dtype=torch.float32, device="cuda:0")
+    W.train(X, t, iters=200, batch=4096, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
     print(json.dumps({"profile": "c4 done"}), flush=True)
 
 
