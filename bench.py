@@ -376,6 +376,9 @@ def bench_lsqr(mfe, plan, csr, out):
     bt = torch.tensor(b, device="cuda:0")
     res = {}
     ones = torch.ones(csr.m, dtype=torch.float64, device="cuda:0")
+    # the plan's LSQR vectors and captured iteration block are made by a first, untimed
+    # call (one-time, like the plan's preprocessing)
+    plan.lsqr(bt, out["d"], out["e"], tol=0.0, max_iter=5, check_every=5)
     # the equilibrated run converges in tens of iterations: its stopping rule is checked
     # every 5 iterations; the two slow arms every 25
     for name, d, e, every in (("d_e", out["d"], out["e"], 5), ("col_only", ones, out["e"], 25),
@@ -392,7 +395,8 @@ def bench_lsqr(mfe, plan, csr, out):
     plan.lsqr(bt, out["d"], out["e"], tol=0.0, max_iter=400, check_every=400)
     torch.cuda.synchronize()
     res["us_per_iter_400"] = (time.perf_counter() - t0) / 400 * 1e6
-    return {"workload": "LSQR on the headline matrix, b = A x* + 1e-3 N(0,1), tol 1e-6, max 3000 iterations",
+    return {"workload": "LSQR on the headline matrix, b = A x* + 1e-3 N(0,1), tol 1e-6, max 3000 iterations; "
+                        "the plan's LSQR workspace made by an untimed first call",
             **res}
 
 

@@ -205,7 +205,12 @@ int mfe_lsqr(const mfe_matrix* A, const double* b, const double* d, const double
              double tol, int32_t max_iter, int32_t check_every, double* x,
              mfe_lsqr_info* info, void* stream);
 
-/* Same on a single-matrix plan (reuses its preprocessing). */
+/* Same on a single-matrix plan (reuses its preprocessing).  The plan keeps the run's
+ * device vectors and its captured iteration block (a HIP graph of up to 25 iterations)
+ * from the first call until mfe_plan_destroy, so later calls allocate nothing and
+ * capture again only when the captured block length min(check_every, 25) changes; calls
+ * on one plan must not overlap (other threads, or other streams before a call's final
+ * synchronisation). */
 int mfe_plan_lsqr(mfe_plan* plan, const double* b, const double* d, const double* e,
                   double tol, int32_t max_iter, int32_t check_every, double* x,
                   mfe_lsqr_info* info, void* stream);

@@ -595,33 +595,93 @@ struct GraphHolder {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  ~GraphHolder() {
+  int iters = 0;  // iterations in the captured block
+  void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
+    exec = nullptr;
+    graph = nullptr;
+    cap = nullptr;
+    iters = 0;
+  }
+  ~GraphHolder() { reset(); }
+};
+
+// Device vectors of one LSQR run (rows nr, columns nc, pb reduction partials).
+struct LsqrBufs {
+  double *bb, *dd, *ee, *u, *du, *v, *w, *x, *ev, *res, *part, *w_tmp;
+  LsqrScal* sc;
+  int alloc(Work& W, int64_t nr, int64_t nc, int64_t pb) {
+    MFE_CHECK(W.alloc(&w_tmp, nc));
+    MFE_CHECK(W.alloc(&bb, nr));
+    MFE_CHECK(W.alloc(&dd, nr));
+    MFE_CHECK(W.alloc(&ee, nc));
+    MFE_CHECK(W.alloc(&u, nr));
+    MFE_CHECK(W.alloc(&du, nr));
+    MFE_CHECK(W.alloc(&v, nc));
+    MFE_CHECK(W.alloc(&w, nc));
+    MFE_CHECK(W.alloc(&x, nc));
+    MFE_CHECK(W.alloc(&ev, nc));
+    MFE_CHECK(W.alloc(&res, nr));
+    MFE_CHECK(W.alloc(&part, pb));
+    MFE_CHECK(W.alloc(&sc, 1));
+    return MFE_OK;
   }
 };
 
+// Iterations per captured block: a block between two residual checks is replayed as
+// whole graphs of at most this many iterations, the rest of it launched eagerly.
+constexpr int kLsqrGraphIters = 25;
+
+}  // namespace
+
+// A plan's LSQR workspace and captured iteration block, kept between calls: the plan's
+// layouts, and so every pointer the graph holds, are fixed for the plan's lifetime, and a
+// call rewrites every vector it reads before reading it.
+struct LsqrCache {
+  int64_t nr = -1, nc = -1, pb = -1;
+  Work W;
+  LsqrBufs B;
+  GraphHolder G;
+};
+
+void free_lsqr_cache(LsqrCache* c) { delete c; }
+
+namespace {
+
 int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, double tol, int32_t max_iter,
-             int32_t check_every, double* x_out, mfe_lsqr_info* info, hipStream_t st) {
+             int32_t check_every, double* x_out, mfe_lsqr_info* info, hipStream_t st, LsqrCache* cache = nullptr) {
   const int64_t nr = ops.rows(), nc = ops.cols();
   const int64_t pb = std::max(ops.fwd_blocks(), ops.bwd_blocks()) + ceil_div(nr, kRed) + 1;
-  Work W;
-  double *bb, *dd, *ee, *u, *du, *v, *w, *x, *ev, *res, *part, *w_tmp;
-  LsqrScal* sc;
-  MFE_CHECK(W.alloc(&w_tmp, nc));
-  MFE_CHECK(W.alloc(&bb, nr));
-  MFE_CHECK(W.alloc(&dd, nr));
-  MFE_CHECK(W.alloc(&ee, nc));
-  MFE_CHECK(W.alloc(&u, nr));
-  MFE_CHECK(W.alloc(&du, nr));
-  MFE_CHECK(W.alloc(&v, nc));
-  MFE_CHECK(W.alloc(&w, nc));
-  MFE_CHECK(W.alloc(&x, nc));
-  MFE_CHECK(W.alloc(&ev, nc));
-  MFE_CHECK(W.alloc(&res, nr));
-  MFE_CHECK(W.alloc(&part, pb));
-  MFE_CHECK(W.alloc(&sc, 1));
+  // Vectors and the captured block: the plan's cache when given (allocated on its first
+  // use), else this call's own.
+  Work Wl;
+  GraphHolder Gl;
+  LsqrBufs B;
+  GraphHolder* Gp = &Gl;
+  if (cache) {
+    if (cache->nr != nr || cache->nc != nc || cache->pb != pb) {
+      Work fresh;
+      LsqrBufs nb;
+      MFE_CHECK(nb.alloc(fresh, nr, nc, pb));
+      cache->G.reset();
+      for (void* q : cache->W.bufs) (void)hipFree(q);
+      cache->W.bufs.swap(fresh.bufs);
+      cache->B = nb;
+      cache->nr = nr;
+      cache->nc = nc;
+      cache->pb = pb;
+    }
+    B = cache->B;
+    Gp = &cache->G;
+  } else {
+    MFE_CHECK(B.alloc(Wl, nr, nc, pb));
+  }
+  GraphHolder& G = *Gp;
+  double *bb = B.bb, *dd = B.dd, *ee = B.ee, *u = B.u, *du = B.du, *v = B.v, *w = B.w, *x = B.x, *ev = B.ev,
+         *res = B.res, *part = B.part, *w_tmp = B.w_tmp;
+  LsqrScal* sc = B.sc;
   for (double* z : {u, du, res}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nr, st));
   for (double* z : {v, w, x, ev}) MFE_HIP(hipMemsetAsync(z, 0, sizeof(double) * nc, st));
   ops.to_op(true, b, 0.0, 0, bb, st);
@@ -673,26 +733,28 @@ int run_lsqr(const Ops& ops, const double* b, const double* d, const double* e, 
     ops.bwd(ee, du, &sc->inv_beta, &sc->coef_q, v, v, ev, part, s);
     k_scal_step<<<1, kScal, 0, s>>>(part, ops.bwd_blocks(), sc, 2, 0);
   };
-  // The check_every iterations between two residual checks are captured once in a HIP
-  // graph and replayed (the launches are identical from one block to the next); a
-  // shorter last block runs eagerly.
-  GraphHolder G;
+  // The iterations between two residual checks are replayed as whole captured blocks of
+  // g iterations (the launches are identical from one block to the next), the rest
+  // eagerly; the block is captured once per call, or once per plan.
+  const int g = std::min<int>(check_every, kLsqrGraphIters);
   for (int it = 1; it <= max_iter;) {
     const int block_end =
         (int)std::min<int64_t>(max_iter, ((int64_t)(it - 1) / check_every + 1) * (int64_t)check_every);
     const int nblk = block_end - it + 1;
-    if (nblk == check_every && check_every > 1) {
-      if (!G.exec) {
+    int done = 0;
+    if (g > 1 && nblk >= g) {
+      if (!G.exec || G.iters != g) {
+        G.reset();
         MFE_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
         MFE_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < check_every; ++i) iteration(G.cap);
+        for (int i = 0; i < g; ++i) iteration(G.cap);
         MFE_HIP(hipStreamEndCapture(G.cap, &G.graph));
         MFE_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        G.iters = g;
       }
-      MFE_HIP(hipGraphLaunch(G.exec, st));
-    } else {
-      for (int i = 0; i < nblk; ++i) iteration(st);
+      for (; done + g <= nblk; done += g) MFE_HIP(hipGraphLaunch(G.exec, st));
     }
+    for (; done < nblk; ++done) iteration(st);
     MFE_HIP(hipGetLastError());
     it = block_end + 1;
     {
@@ -828,7 +890,8 @@ int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, do
               int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t st) {
   MFE_CHECK(ensure_mats(p, st));
   SellOps ops(p);
-  return run_lsqr(ops, b, d, e, tol, max_iter, check_every, x, info, st);
+  if (!p->lsqr_cache) p->lsqr_cache = new LsqrCache();
+  return run_lsqr(ops, b, d, e, tol, max_iter, check_every, x, info, st, p->lsqr_cache);
 }
 
 int plan_residual(mfe_plan* p, const double* d, const double* e, double alpha, double beta, double* rms,

@@ -155,6 +155,10 @@ struct PhaseArgs {
 
 struct mfe_plan_impl;
 
+// LSQR workspace and captured iteration block kept by a plan between calls (lsqr.hip).
+struct LsqrCache;
+void free_lsqr_cache(LsqrCache* c);
+
 }  // namespace mfe
 
 struct mfe_plan {
@@ -182,6 +186,8 @@ struct mfe_plan {
   int32_t tune_nt = -1;
   int32_t tune_sched = -1;
   int32_t tune_wg = 0;  // threads per workgroup of the one-launch step (0: kBlock)
+  // LSQR workspace and graph of its iteration block, allocated by the first mfe_plan_lsqr
+  mfe::LsqrCache* lsqr_cache = nullptr;
   // scratch of the warm-start calls (sketch, features, network outputs)
   void* ws = nullptr;
   size_t ws_bytes = 0;

@@ -392,6 +392,7 @@ void plan_free(mfe_plan* p) {
     (void)hipFree(p->part[i]);
   }
   (void)hipFree(p->ws);
+  mfe::free_lsqr_cache(p->lsqr_cache);
   plan_free_variants(p);
   (void)hipFree(p->segs);
   (void)hipFree(p->seg_prefix);

@@ -302,6 +302,33 @@ def test_lsqr_graph_blocks_equal_eager_iterations():
         assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
 
 
+def test_plan_lsqr_keeps_workspace_between_calls():
+    """A plan keeps LSQR's vectors and captured iteration block between calls.  Calls with
+    other right-hand sides, scalings and check intervals in between (check_every = 30:
+    one captured block of 25 iterations and 5 eager ones, then a shorter eager block)
+    leave a repeated call's x bit for bit equal to the first one's and to calls without a
+    plan, and the capped blocks equal fully eager iterations."""
+    from paper_1602_06621_amd import Plan, lsqr
+
+    c = scaled_sparse(900, 500, 7, 0.7, 41)
+    A = c.to_scipy()
+    b1, _ = rhs_noisy(A, 42, noise=1e-3)
+    b2, _ = rhs_noisy(A, 43, noise=1e-2)
+    rng = np.random.default_rng(44)
+    d, e = _t(np.exp(rng.normal(0, 0.3, 900))), _t(np.exp(rng.normal(0, 0.3, 500)))
+    with Plan([_csr(c)], max_probes=1) as plan:
+        x1, i1 = plan.lsqr(_t(b1), d, e, tol=0.0, max_iter=60, check_every=5)
+        x2, _ = plan.lsqr(_t(b2), None, None, tol=0.0, max_iter=37, check_every=30)
+        x3, _ = plan.lsqr(_t(b1), None, e, tol=1e-6, max_iter=500, check_every=7)
+        x4, i4 = plan.lsqr(_t(b1), d, e, tol=0.0, max_iter=60, check_every=5)
+    x5, _ = lsqr(_csr(c), _t(b1), d, e, tol=0.0, max_iter=60, check_every=5)
+    x6, _ = lsqr(_csr(c), _t(b2), None, None, tol=0.0, max_iter=37, check_every=1)
+    torch.cuda.synchronize()
+    _say("plan lsqr reuse", i1, i4, float(x3.abs().max()))
+    assert torch.equal(x1, x4) and torch.equal(x1, x5) and i1 == i4
+    assert torch.equal(x2, x6)
+
+
 def test_sparse_lsqr_converges_and_stops():
     """Stopping rule: relative residual or normal-equation test, checked every 10 steps."""
     from paper_1602_06621_amd import lsqr
