@@ -51,6 +51,22 @@ TRAFFIC_BYTES_PER_STEP = (543.2 + 40.3) * 1e6
 TRAFFIC_SOURCE = "profiles/k_phase_csr_1e6x5e5_k16.md (FETCH_SIZE x 1.861 + WRITE_SIZE x 0.931 per launch)"
 
 
+def stored_oracle_error(name, u_bar, v_bar, suffix=""):
+    """Largest |difference| of u_bar, v_bar (device tensors) from a stored FP64 oracle run
+    (tests/golden/<name>, written by tests/golden/make_long_runs.py from the oracle alone),
+    over the indices the file stores (every `stride`-th).  None when the file is absent."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    st = int(ref["stride"]) if "stride" in ref.files else 1
+    ub = u_bar.cpu().numpy()[::st]
+    vb = v_bar.cpu().numpy()[::st]
+    return float(max(np.abs(ub - ref["u_bar" + suffix]).max(), np.abs(vb - ref["v_bar" + suffix]).max()))
+
+
 def step_bytes(m, n, nnz, k):
     """Algorithmic HBM bytes of one step of the two-structure design: per stored entry and
     product 8 B (FP32 value + int32 index), the two offset arrays (4 B per row and per
@@ -204,14 +220,17 @@ def bench_c3(mfe):
     del A
     D = mfe.Dense(torch.tensor(bits.view(np.int16), device="cuda:0"))
     al, be = mfe.default_alpha_beta(m, n)
-    s, _ = timed(lambda: mfe.equilibrate(D, al, be, GAMMA, BOX_M, T, k, 2003), 2, 1)
+    s, out = timed(lambda: mfe.equilibrate(D, al, be, GAMMA, BOX_M, T, k, 2003), 2, 1)
     tim = mfe.last_timing()
     by, fl = bf16_algorithmic(m, n, k)
     step_s = tim["step_ms"] / 1e3
     return {"workload": "dense bf16 16384x8192, k=64 exact +-1 probes x bf16(e^v), FP32 accumulate, T=500",
             "ms_per_run": s * 1e3, "step_ms": tim["step_ms"], "pairs_per_s": T * k / s,
             "hbm_gbs": by / step_s / 1e9, "hbm_frac": by / step_s / 1e9 / HBM_PEAK_GBS,
-            "mfma_tflops": fl / step_s / 1e12, "mfma_frac": fl / step_s / 1e12 / BF16_PEAK_TFLOPS}
+            "mfma_tflops": fl / step_s / 1e12, "mfma_frac": fl / step_s / 1e12 / BF16_PEAK_TFLOPS,
+            # the run's u_bar, v_bar against the stored 500-step FP64 oracle run on bf16(A)
+            "err_vs_oracle": stored_oracle_error("c3_bf16.npz", out["u_bar"], out["v_bar"]),
+            "err_tolerance": 2e-2}
 
 
 def bench_c4(mfe):
@@ -793,7 +812,12 @@ def main():
     ceil = measure_ceilings(mfe, csr.m, csr.n, csr.nnz)
 
     extra = {"prep_ms": prep_ms, "gen_s": gen_s,
-             "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9}
+             "hbm_gbs_whole_run": bytes_launch * T_STEPS / (ms_per_step / 1e3) / 1e9,
+             # the last timed run's u_bar, v_bar after the 2000 steps against the stored FP64
+             # oracle run (every 13th row and column)
+             "err_vs_oracle": (stored_oracle_error("c1_prefix.npz", out["u_bar"], out["v_bar"], "_2000")
+                               if out is not None and T_STEPS == 2000 else None),
+             "err_tolerance": 1e-5}
     for name, fn in (("c0", bench_c0), ("c2", bench_c2), ("c3", bench_c3), ("c4", bench_c4)):
         if name in work:
             print(f"# measuring {name}", file=sys.stderr, flush=True)
