@@ -220,48 +220,67 @@ __device__ inline void philox_index(uint64_t seed, uint64_t it, uint64_t b, int6
   out = (int64_t)(w.x[0] % (uint64_t)count);
 }
 
-// Forward for `count` samples (rows of X, or X[idx[b]] when idx is given); optionally
-// keeps h1, h2 for the backward pass.  Parameters are staged in LDS.  (64-thread
-// workgroups, which spread a 4096-sample batch over 64 compute units instead of 16, made
-// it slower: 49 -> 60 us, the weight staging then dominates.)
+// Training forward and backward: kLanesPerSample threads per sample, each owning a
+// quarter of the hidden units; the sample's first hidden layer (forward) or output-layer
+// deltas (backward) are exchanged through LDS.  A 4096-sample batch spreads over 64
+// workgroups.  With one sample per thread (16 workgroups) the two kernels took 49.6 and
+// 39.1 us per batch.
+constexpr int kLanesPerSample = 4;
+constexpr int kPart = kH / kLanesPerSample;
+constexpr int kSamplesPerWg = 256 / kLanesPerSample;
+
+int64_t train_grid(int64_t count) { return ceil_div(count, (int64_t)kSamplesPerWg); }
+
+// Forward for `count` samples (rows of X, or X[idx[b]] when idx is given); keeps h1, h2
+// (nullable) for the backward pass.  Parameters are staged in LDS.  Each unit's sums run
+// in the same order as one sample per thread; the output adds the four threads' partial
+// sums of w3 h2 pairwise.
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ params, const float* __restrict__ X,
                                                  const int64_t* __restrict__ idx, int64_t count, float* __restrict__ y,
                                                  float* __restrict__ h1s, float* __restrict__ h2s) {
   __shared__ float P[kP];
+  __shared__ float H1[kSamplesPerWg][kH + 1];
   for (int i = threadIdx.x; i < kP; i += 256) P[i] = params[i];
-  __syncthreads();
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= count) return;
+  const int q = (int)threadIdx.x % kLanesPerSample, ls = (int)threadIdx.x / kLanesPerSample;
+  const int64_t b = (int64_t)blockIdx.x * kSamplesPerWg + ls;
+  const bool live = b < count;
+  const int64_t row = live ? (idx ? idx[b] : b) : 0;
+  float x[kF];
+#pragma unroll
+  for (int f = 0; f < kF; ++f) x[f] = live ? X[row * kF + f] : 0.f;
+  __syncthreads();  // parameters staged
   const float* W1 = P;
   const float* b1 = W1 + kF * kH;
   const float* W2 = b1 + kH;
   const float* b2 = W2 + kH * kH;
   const float* w3 = b2 + kH;
   const float b3 = w3[kH];
-  const int64_t row = idx ? idx[b] : b;
-  float x[kF];
+  const int j0 = q * kPart;
 #pragma unroll
-  for (int f = 0; f < kF; ++f) x[f] = X[row * kF + f];
-  float h1[kH];
-#pragma unroll
-  for (int j = 0; j < kH; ++j) {
+  for (int jj = 0; jj < kPart; ++jj) {
+    const int j = j0 + jj;
     float a = b1[j];
 #pragma unroll
     for (int f = 0; f < kF; ++f) a = fmaf(x[f], W1[f * kH + j], a);
-    h1[j] = tanhf(a);
+    const float h = tanhf(a);
+    H1[ls][j] = h;
+    if (live && h1s) h1s[b * kH + j] = h;
   }
-  float out = b3;
-  for (int j = 0; j < kH; ++j) {
+  __syncthreads();  // the sample's 64 first-layer units are in LDS
+  float out = 0.f;
+  for (int jj = 0; jj < kPart; ++jj) {
+    const int j = j0 + jj;
     float a = b2[j];
 #pragma unroll
-    for (int i = 0; i < kH; ++i) a = fmaf(h1[i], W2[i * kH + j], a);
+    for (int i = 0; i < kH; ++i) a = fmaf(H1[ls][i], W2[i * kH + j], a);
     const float h = tanhf(a);
-    if (h2s) h2s[b * kH + j] = h;
+    if (live && h2s) h2s[b * kH + j] = h;
     out = fmaf(h, w3[j], out);
   }
-  if (h1s)
-    for (int j = 0; j < kH; ++j) h1s[b * kH + j] = h1[j];
-  y[b] = out;
+  // the four partial sums (consecutive lanes of one wavefront), added pairwise
+  out += __shfl_xor(out, 1, 64);
+  out += __shfl_xor(out, 2, 64);
+  if (live && q == 0) y[b] = b3 + out;
 }
 
 // Inference on the matrix cores (v_mfma_f32_32x32x2_f32, FP32 products and sums): a
@@ -358,7 +377,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ par
 }
 
 // Per-sample backward: gy = 2 (y - t)/B, gh2 = gy w3 (1 - h2^2), gh1 = (gh2 W2') (1 - h1^2).
-// Also the per-sample squared error for the loss.
+// Also the per-sample squared error for the loss.  Same layout as k_mlp_fwd; every sum
+// runs in the same order as one sample per thread.
 __global__ __launch_bounds__(256) void k_mlp_bwd(const float* __restrict__ params, const float* __restrict__ y,
                                                  const float* __restrict__ t, const int64_t* __restrict__ idx,
                                                  int64_t count, const float* __restrict__ h1s,
@@ -366,33 +386,46 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float* __restrict__ param
                                                  float* __restrict__ gh1, float* __restrict__ gh2,
                                                  double* __restrict__ se) {
   __shared__ float P[kH * kH + 2 * kH];
+  __shared__ float G2[kSamplesPerWg][kH + 1];
   const float* W2g = params + kF * kH + kH;
   for (int i = threadIdx.x; i < kH * kH; i += 256) P[i] = W2g[i];
   const float* w3g = W2g + kH * kH + kH;
   for (int i = threadIdx.x; i < kH; i += 256) P[kH * kH + i] = w3g[i];
-  __syncthreads();
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= count) return;
+  const int q = (int)threadIdx.x % kLanesPerSample, ls = (int)threadIdx.x / kLanesPerSample;
+  const int64_t b = (int64_t)blockIdx.x * kSamplesPerWg + ls;
+  const bool live = b < count;
+  float g = 0.f;
+  if (live) {
+    const int64_t row = idx ? idx[b] : b;
+    const float r = y[b] - t[row];
+    g = 2.0f * r / (float)count;
+    if (q == 0) {
+      se[b] = (double)r * (double)r;
+      gy[b] = g;
+    }
+  }
+  __syncthreads();  // W2, w3 staged
   const float* W2 = P;
   const float* w3 = P + kH * kH;
-  const int64_t row = idx ? idx[b] : b;
-  const float r = y[b] - t[row];
-  se[b] = (double)r * (double)r;
-  const float g = 2.0f * r / (float)count;
-  gy[b] = g;
-  float g2[kH];
+  const int j0 = q * kPart;
 #pragma unroll
-  for (int j = 0; j < kH; ++j) {
-    const float h = h2s[b * kH + j];
-    g2[j] = g * w3[j] * (1.0f - h * h);
-    gh2[b * kH + j] = g2[j];
+  for (int jj = 0; jj < kPart; ++jj) {
+    const int j = j0 + jj;
+    const float h = live ? h2s[b * kH + j] : 0.f;
+    const float g2 = g * w3[j] * (1.0f - h * h);
+    G2[ls][j] = g2;
+    if (live) gh2[b * kH + j] = g2;
   }
-  for (int i = 0; i < kH; ++i) {
+  __syncthreads();  // the sample's 64 output-layer deltas are in LDS
+  for (int ii = 0; ii < kPart; ++ii) {
+    const int i = j0 + ii;
     float a = 0.f;
 #pragma unroll
-    for (int j = 0; j < kH; ++j) a = fmaf(g2[j], W2[i * kH + j], a);
-    const float h = h1s[b * kH + i];
-    gh1[b * kH + i] = a * (1.0f - h * h);
+    for (int j = 0; j < kH; ++j) a = fmaf(G2[ls][j], W2[i * kH + j], a);
+    if (live) {
+      const float h = h1s[b * kH + i];
+      gh1[b * kH + i] = a * (1.0f - h * h);
+    }
   }
 }
 
@@ -400,9 +433,8 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const float* __restrict__ param
 // [c S, min((c + 1) S, count)) for every parameter in FP64, in sample order, staging
 // kWgTile samples' activations and deltas at a time in LDS (coalesced loads; each
 // thread owns parameters tid, tid + 256, ...).  Stage two adds each parameter's chunk
-// partials in chunk order.  With one thread per parameter looping over the whole batch
-// (strided loads, 19 workgroups) an Adam step on 4096 samples took ~1.3 ms; with the two
-// stages (17 + 12 us) it takes ~0.13 ms.
+// partials in a fixed order.  With one thread per parameter looping over the whole batch
+// (strided loads, 19 workgroups) the gradient of a 4096-sample batch took ~1.2 ms.
 constexpr int kWgTile = 32;
 constexpr int kWgMaxChunks = 512;
 constexpr int kWgPer = (kP + 255) / 256;
@@ -476,14 +508,19 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad_part(const float* __restrict_
   }
 }
 
+// Four consecutive lanes per parameter: lane l adds chunks l, l + 4, ... in order, then
+// the four sums are added pairwise.
 __global__ __launch_bounds__(256) void k_mlp_wgrad_sum(const double* __restrict__ part, int chunks,
                                                        float* __restrict__ grad) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= kP) return;
+  const int p = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2), l = (int)(threadIdx.x & 3);
   double acc = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < chunks; ++c) acc += part[(int64_t)c * kP + p];
-  grad[p] = (float)acc;
+  if (p < kP) {
+#pragma unroll 4
+    for (int c = l; c < chunks; c += 4) acc += part[(int64_t)c * kP + p];
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (p < kP && l == 0) grad[p] = (float)acc;
 }
 
 // grad = the batch's weight gradient; part holds wgrad_chunks(count) x kP doubles.
@@ -492,7 +529,8 @@ void launch_wgrad(const float* X, const int64_t* idx, int64_t count, const float
   const int64_t C = wgrad_chunks(count);
   const int64_t S = ceil_div(count, C);
   k_mlp_wgrad_part<<<dim3((unsigned)C), dim3(256), 0, st>>>(X, idx, count, S, gy, h1, h2, g1, g2, part);
-  k_mlp_wgrad_sum<<<dim3((unsigned)ceil_div((int64_t)kP, (int64_t)256)), dim3(256), 0, st>>>(part, (int)C, grad);
+  k_mlp_wgrad_sum<<<dim3((unsigned)ceil_div((int64_t)kP * 4, (int64_t)256)), dim3(256), 0, st>>>(part, (int)C,
+                                                                                                 grad);
 }
 
 __global__ void k_sum(const double* __restrict__ v, int64_t n, double scale, double* out) {
@@ -867,11 +905,12 @@ int mlp_train(float* params, float* adam_m, float* adam_v, int32_t step0, const 
   double* part;
   MFE_CHECK(W.alloc(&part, wgrad_chunks(batch) * kP));
   const unsigned gb = (unsigned)ceil_div(batch, 256), gp = (unsigned)ceil_div(kP, 256);
+  const unsigned gt = (unsigned)train_grid(batch);
   for (int it = 0; it < iters; ++it) {
     const uint64_t step = (uint64_t)step0 + it + 1;
     k_batch_indices<<<gb, 256, 0, st>>>(seed, step, batch, total, idx);
-    k_mlp_fwd<<<gb, 256, 0, st>>>(params, X, idx, batch, y, h1, h2);
-    k_mlp_bwd<<<gb, 256, 0, st>>>(params, y, t, idx, batch, h1, h2, gy, g1, g2, se);
+    k_mlp_fwd<<<gt, 256, 0, st>>>(params, X, idx, batch, y, h1, h2);
+    k_mlp_bwd<<<gt, 256, 0, st>>>(params, y, t, idx, batch, h1, h2, gy, g1, g2, se);
     launch_wgrad(X, idx, batch, gy, h1, h2, g1, g2, part, grad, st);
     k_sum<<<1, 256, 0, st>>>(se, batch, 1.0 / (double)batch, loss + it);
     k_adam<<<gp, 256, 0, st>>>(params, grad, adam_m, adam_v, (int)step, lr);
@@ -898,9 +937,9 @@ int mlp_grad(const float* params, const float* X, const float* t, int64_t count,
   MFE_CHECK(W.alloc(&l, 1));
   double* part;
   MFE_CHECK(W.alloc(&part, wgrad_chunks(count) * kP));
-  const unsigned gb = (unsigned)ceil_div(count, 256);
-  k_mlp_fwd<<<gb, 256, 0, st>>>(params, X, nullptr, count, y, h1, h2);
-  k_mlp_bwd<<<gb, 256, 0, st>>>(params, y, t, nullptr, count, h1, h2, gy, g1, g2, se);
+  const unsigned gt = (unsigned)train_grid(count);
+  k_mlp_fwd<<<gt, 256, 0, st>>>(params, X, nullptr, count, y, h1, h2);
+  k_mlp_bwd<<<gt, 256, 0, st>>>(params, y, t, nullptr, count, h1, h2, gy, g1, g2, se);
   launch_wgrad(X, nullptr, count, gy, h1, h2, g1, g2, part, grad, st);
   k_sum<<<1, 256, 0, st>>>(se, count, 1.0 / (double)count, l);
   MFE_HIP(hipGetLastError());
