@@ -210,10 +210,14 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
   const int split = mode != 0 ? ld_stream<NT>(S.len_lo + r) : 0;
   const int q_beg = mode == 2 ? split : 0;
   const int q_end = mode == 1 ? split : len;
-  // The epilogue's operands are loaded before the gather loop so their latency overlaps it.
+  // The epilogue's operands are loaded before the gather loop so their latency overlaps
+  // it -- except in the Section 6 kernels, where loading them after the loop shortens
+  // their live range enough for the one-launch variant kernel to run eight waves per SIMD
+  // without spilling (per-index targets 137-139 -> 130-132 us per step on the 1e6 x 5e5
+  // matrix, 16 x 8 blocks 142 -> 137 us; results unchanged bit for bit).
   int32_t li = 0, mi = 0;
   double x_old = 0.0, xbar_old = 0.0, tgt_r = 0.0;
-  if (!partial_out) {
+  auto load_epilogue = [&]() {
     li = ld_stream<NT>(S.orig + r);
     x_old = ld_stream<NT>(S.x + r);
     if (!VAR || !S.zout) xbar_old = ld_stream<NT>(S.xbar + r);
@@ -221,7 +225,8 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
     if constexpr (VAR) {
       if (S.tgt) tgt_r = ld_stream<NT>(S.tgt + r);
     }
-  }
+  };
+  if (!partial_out && !VAR) load_epilogue();
   const long long* __restrict__ e = reinterpret_cast<const long long*>(S.ent + S.slice_off[s] + lane);
   const DT* __restrict__ gather = reinterpret_cast<const DT*>(S.gather);
   double acc[KP];
@@ -234,6 +239,7 @@ __device__ __forceinline__ void side_update(const SideDev& S, const MatDev* __re
       if (p < k) st_stream<NT>(S.part + (int64_t)p * S.nint + r, acc[p]);
     return;
   }
+  if (VAR) load_epilogue();
   if (li < 0) return;
   finish_update<KP, PACKED, VAR, NT>(S, mats, k, sc, r, li, mi, x_old, xbar_old, tgt_r, acc, flag);
 }
@@ -317,15 +323,24 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk,
 // with at most 16 probes: 8 (64 VGPRs, 12 bytes spilled), which keeps eight workgroups per
 // CU resident instead of five (85 VGPRs): 131.3 -> 126.1 us per step on the 1e6 x 5e5
 // headline (131 at six waves); the 2e5 x 1e5 warm-start matrix is unchanged (40.2 us).
-// The same bound on the single-direction and Section 6 kernels made them slower (the
-// symmetric product 75.8 -> 83.5 us, per-index targets 132.7 -> 140.2 us: 28-44 bytes
-// spilled), so they keep the compiler's choice, as do other probe counts and loads in
-// flight (more accumulators or loads): with 8 probes and 16 loads in flight a bound of
+// The same bound on the single-direction kernels made them slower (the symmetric product
+// 75.8 -> 83.5 us: 28-44 bytes spilled), so they keep the compiler's choice; the Section 6
+// one-launch kernel spilled as well (per-index targets 132.7 -> 140.2 us) until its
+// epilogue operands were loaded after the gather loop (var_step_waves).  Other probe
+// counts and loads in flight keep the compiler's choice too (more accumulators or loads):
+// with 8 probes and 16 loads in flight a bound of
 // five waves (96 VGPRs instead of 107, 52 bytes spilled) took the 512-matrix batched
 // step from 2.07 to 2.53 ms.
 template <int KP, int NB>
 constexpr int step_waves() {
   return (KP <= 16 && NB == 1) ? 8 : 1;
+}
+
+// The same bound for the one-launch Section 6 kernel up to 16 probes (64 VGPRs, no spill
+// with its epilogue operands loaded after the gather loop).
+template <int KP>
+constexpr int var_step_waves() {
+  return KP <= 16 ? 8 : 1;
 }
 
 // Largest workgroup of the one-launch step kernel (the launch size is a plan tuning, 256
@@ -377,7 +392,8 @@ __global__ __launch_bounds__((step_max_threads<KP, NB, PACKED>()), (step_waves<K
 
 // The same with the Section 6 variant update (per-index targets, block sides).
 template <int KP, bool PACKED>
-__global__ __launch_bounds__(kBlock) void k_phase_both_var(PhaseArgs a, SideDev C, int64_t col_blocks) {
+__global__ __launch_bounds__(kBlock, (var_step_waves<KP>())) void k_phase_both_var(PhaseArgs a, SideDev C,
+                                                                          int64_t col_blocks) {
   const int64_t b = blockIdx.x;
   if (b >= a.side_blocks + col_blocks) signgen_block(a.gen, b - a.side_blocks - col_blocks, (int64_t)blockDim.x);
   else if (a.side.nt) phase_both<KP, PACKED, kBatch, true, true>(a, C, b);
