@@ -324,7 +324,9 @@ __device__ __forceinline__ void signgen_block(const SignGenDev& g, int64_t gblk,
 // CU resident instead of five (85 VGPRs): 131.3 -> 126.1 us per step on the 1e6 x 5e5
 // headline (131 at six waves); the 2e5 x 1e5 warm-start matrix is unchanged (40.2 us).
 // The same bound on the single-direction kernels made them slower (the symmetric product
-// 75.8 -> 83.5 us: 28-44 bytes spilled), so they keep the compiler's choice; the Section 6
+// 75.8 -> 83.5 us: 28-44 bytes spilled; 77.6 us with their epilogue operands loaded after
+// the gather loop, 12 bytes spilled, and one launch per direction on the headline 133.5 ->
+// 138.5 us), so they keep the compiler's choice; the Section 6
 // one-launch kernel spilled as well (per-index targets 132.7 -> 140.2 us) until its
 // epilogue operands were loaded after the gather loop (var_step_waves).  Other probe
 // counts and loads in flight keep the compiler's choice too (more accumulators or loads):
