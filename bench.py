@@ -200,8 +200,17 @@ def bench_c2(mfe):
     tim = plan.last_timing()
     plan.close()
     by = sparse_algorithmic_bytes(M, N, nnz, k)
+    # the step's gather bound: nnz sorted-row gathers per direction from a table of the mean
+    # per-matrix size (one table, so every gather can hit L2: an optimistic floor)
+    def rows_of(x):
+        return min((5, 10, 20, 40), key=lambda L: abs(L - x))
+    lr, lc = rows_of(nnz / M), rows_of(nnz / N)
+    floor_ms = (mfe.probe_gather_sorted(8 * (N // len(G)), nnz, lr, reps=5)
+                + mfe.probe_gather_sorted(8 * (M // len(G)), nnz, lc, reps=5))
     return {"workload": "512 CSR f32, m~U[1k,64k], n~U[m/4,m], nnz/row~Poisson(12), sigma=2; k=8, T=1000, one graph",
             "sum_m": M, "sum_n": N, "nnz": nnz, "ms_per_run": s * 1e3, "step_ms": tim["step_ms"],
+            "gather_floor_ms": floor_ms, "gather_floor": f"sorted rows of {lr} / {lc}, mean table sizes",
+            "gather_frac": floor_ms / tim["step_ms"],
             "pairs_per_s": 512 * T * k / s, "algorithmic_gbs": by / (tim["step_ms"] / 1e3) / 1e9,
             "hbm_frac": by / (tim["step_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, "prep_ms": prep_ms, "gen_s": gen_s,
             "autotune": tune, "autotune_s": tune_s,
