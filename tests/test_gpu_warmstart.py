@@ -141,6 +141,38 @@ def test_one_call_warm_start_equals_composed_steps():
             assert torch.equal(v0, warmstart_apply(f["v_sketch"], dv, 10.0))
 
 
+def test_warm_start_full_size_evaluation_matrix():
+    """The one-call warm start on the 200,000 x 100,000 evaluation matrix of the warm-start
+    benchmark (U{8..16} entries per row, sigma 2, seed 9001; sketch seed 5, 4 probes):
+    sketch initialisation and features against the oracle as in the small test, and the
+    learned start clip(sketch + MLP(features), -M, M) against the oracle's network applied
+    to the library's FP32 features (the network runs in FP32 on the matrix cores: 1e-5 of
+    the largest correction)."""
+    from paper_1602_06621_amd import Plan
+    from paper_1602_06621_amd.warmstart import init_params
+
+    c = warmstart_matrix(200_000, 100_000, 2.0, 9001)
+    al, be = A1.default_alpha_beta(c.m, c.n)
+    params = init_params(6)
+    with Plan([_gpu(c)], max_probes=16) as plan:
+        f = plan.sketch_features(5, 4, 0.1, 10.0)
+        u0, v0 = plan.warm_start(params, 5, 4, 0.1, 10.0, learned=True)
+        fr, fc = f["feat_rows"].cpu().numpy(), f["feat_cols"].cpu().numpy()
+        us, vs = f["u_sketch"].cpu().numpy(), f["v_sketch"].cpu().numpy()
+        u0, v0 = u0.cpu().numpy(), v0.cpu().numpy()
+    ofr, ofc, ous, ovs = OW.features(c.to_scipy(), 5, 4, al, be, 0.1, 10.0)
+    assert np.allclose(us, ous, rtol=1e-12, atol=1e-12) and np.allclose(vs, ovs, rtol=1e-12, atol=1e-12)
+    assert np.allclose(fr, ofr, rtol=1e-5, atol=1e-6) and np.allclose(fc, ofc, rtol=1e-5, atol=1e-6)
+    theta = params.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for x0, feat, sk in ((u0, fr, us), (v0, fc, vs)):
+        d, _ = OM.forward(theta, feat.astype(np.float64), 64)
+        ref = np.clip(sk + d, -10.0, 10.0)
+        worst = max(worst, np.abs(x0 - ref).max() / max(1.0, np.abs(d).max()))
+    _say("full-size warm start: worst |u0 - oracle| / max(1, |correction|)", worst)
+    assert worst <= 1e-5
+
+
 def test_training_set_call_samples_strata_and_targets():
     """mfe_plan_training_set: every sample lies in its own stratum at the Philox offset the
     header states (recomputed here from the published Philox definition), its features are
