@@ -8,6 +8,7 @@
 // results are deterministic.  The scalar recurrence runs on the device; the host only
 // reads the scalars at the residual checks.
 #include <cmath>
+#include <new>
 #include <vector>
 
 #include "dense.h"
@@ -890,7 +891,10 @@ int plan_lsqr(mfe_plan* p, const double* b, const double* d, const double* e, do
               int32_t check_every, double* x, mfe_lsqr_info* info, hipStream_t st) {
   MFE_CHECK(ensure_mats(p, st));
   SellOps ops(p);
-  if (!p->lsqr_cache) p->lsqr_cache = new LsqrCache();
+  if (!p->lsqr_cache) {
+    p->lsqr_cache = new (std::nothrow) LsqrCache();
+    if (!p->lsqr_cache) return set_error(MFE_ENOMEM, "out of host memory for the LSQR workspace");
+  }
   return run_lsqr(ops, b, d, e, tol, max_iter, check_every, x, info, st, p->lsqr_cache);
 }
 
