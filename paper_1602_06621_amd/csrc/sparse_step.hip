@@ -443,13 +443,12 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 // variable, then every index of the block gets the new value and its descriptor for
 // the next step.  init != 0: the block variables start from x0 (or 0) instead.
 template <int KP, bool PACKED>
-__global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k, StepScalars sc,
-                                                    int64_t wbase, const double* __restrict__ x0, int init,
-                                                    int* flag) {
+__device__ __forceinline__ void block_step(const SideDev& S, const BlockDev& B, int k, const StepScalars& sc,
+                                           int64_t wbase, const double* __restrict__ x0, int init, int* flag,
+                                           int64_t gt) {
 #pragma clang fp contract(off)
   using C = Codec<KP, PACKED>;
   const int G = B.group;
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t b = gt / G;
   const int sub = (int)(gt % G);
   const bool valid = b < B.nb;
@@ -493,6 +492,27 @@ __global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k
     S.x[r] = xn;
     reinterpret_cast<typename C::T*>(S.out)[r] = C::encode(sx, extract_bits(S.next_signs + wbase, j * k, k));
   }
+}
+
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(256) void k_block_step(SideDev S, BlockDev B, int k, StepScalars sc,
+                                                    int64_t wbase, const double* __restrict__ x0, int init,
+                                                    int* flag) {
+  block_step<KP, PACKED>(S, B, k, sc, wbase, x0, init, flag, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Both sides' block updates of a step in one launch (they are independent within a step:
+// each reads its own side's estimates and writes its own side's state): the first row_wgs
+// workgroups take the row blocks, the rest the column blocks.
+template <int KP, bool PACKED>
+__global__ __launch_bounds__(256) void k_block_step_both(SideDev S0, BlockDev B0, StepScalars sc0, int64_t wbase0,
+                                                         SideDev S1, BlockDev B1, StepScalars sc1, int64_t wbase1,
+                                                         int k, int64_t row_wgs, int* flag) {
+  const int64_t w = blockIdx.x;
+  if (w < row_wgs)
+    block_step<KP, PACKED>(S0, B0, k, sc0, wbase0, nullptr, 0, flag, w * blockDim.x + threadIdx.x);
+  else
+    block_step<KP, PACKED>(S1, B1, k, sc1, wbase1, nullptr, 0, flag, (w - row_wgs) * blockDim.x + threadIdx.x);
 }
 
 // Targets of the blocks of one side: the sum over each block of the indices' squared
@@ -792,6 +812,16 @@ struct BlockLauncher {
 };
 
 template <int KP, bool PACKED>
+struct BlockBothLauncher {
+  static void run(const SideDev& S0, const BlockDev& B0, const StepScalars& sc0, int64_t wbase0, const SideDev& S1,
+                  const BlockDev& B1, const StepScalars& sc1, int64_t wbase1, int k, int* flag, hipStream_t st) {
+    const unsigned g0 = block_grid(B0.nb, B0.group), g1 = block_grid(B1.nb, B1.group);
+    k_block_step_both<KP, PACKED><<<dim3(g0 + g1), dim3(256), 0, st>>>(S0, B0, sc0, wbase0, S1, B1, sc1, wbase1, k,
+                                                                        (int64_t)g0, flag);
+  }
+};
+
+template <int KP, bool PACKED>
 struct InitLauncher {
   static void run(const SideDev& S, const MatDev* mats, const double* x0, int k, double M, int* flag,
                   hipStream_t st) {
@@ -993,6 +1023,11 @@ int plan_run(mfe_plan* p, const mfe_equil_params* prm, const double* alpha_b, co
       const PhaseArgs a = phase_args(t, true, 0), c = phase_args(t, false, 0);
       if (a.split <= 1 && c.split <= 1) {
         dispatch<BothLauncher>(k, packed, a, c.side, nb, (int)wg_threads, s);
+        if (blocked[0] && blocked[1]) {
+          dispatch<BlockBothLauncher>(k, packed, a.side, bd[0], a.sc, wbase[0], c.side, bd[1], c.sc, wbase[1], k,
+                                      p->flag, s);
+          return;
+        }
         for (int si = 0; si < 2; ++si)
           if (blocked[si]) {
             const PhaseArgs& x = si == 0 ? a : c;
